@@ -1,0 +1,187 @@
+"""CPU oracle for the triangle count -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never does, and the
+oracle imports nothing from it: the two share no code.  Both take their
+inputs from ``graphgen``.
+
+``tc_oracle.c`` (plain serial C, built with gcc) follows Bader, "Fast Triangle
+Counting" (arXiv 2309.09064):
+
+* :func:`build_csr`          simple undirected CSR from tuples (Introduction)
+* :func:`bfs_levels`         BFS from each unvisited vertex in id order (Alg. 4)
+* :func:`partition`          E0/E1 split, N0 rank-split rows (Alg. 4)
+* :func:`alg4`               T0 by forward-hashed (Alg. 2) + T1 hashed (Alg. 4)
+* :func:`count_emd`          direction-oriented sorted-merge edge iterator
+* :func:`alg3`               cover-edge count (Alg. 3)
+* :func:`vertex_triangles`   per-vertex triangle counts
+
+:mod:`oracle.mlp` holds the float64 reference of the scheduler network.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tc_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i32 = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_i64 = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_u64 = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True, opt: str = "-O2") -> str:
+    """Compile the oracle with gcc (``-O2``, as the paper compiled its C)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", opt, "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.orc_build_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, _i32, _i32, _i64, _i32, ctypes.c_int64]
+        lib.orc_build_csr.restype = ctypes.c_int64
+        lib.orc_bfs_levels.argtypes = [ctypes.c_int64, _i64, _i32, _i32]
+        lib.orc_bfs_levels.restype = ctypes.c_int64
+        lib.orc_partition.argtypes = [ctypes.c_int64, _i64, _i32, _i32, _i64, _i32, _i32, _i64, _i32]
+        lib.orc_partition.restype = None
+        lib.orc_alg4.argtypes = [ctypes.c_int64, _i64, _i32, _i32, ctypes.POINTER(ctypes.c_uint64),
+                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_alg4.restype = ctypes.c_int
+        lib.orc_count_emd.argtypes = [ctypes.c_int64, _i64, _i32]
+        lib.orc_count_emd.restype = ctypes.c_uint64
+        lib.orc_alg3.argtypes = [ctypes.c_int64, _i64, _i32, _i32]
+        lib.orc_alg3.restype = ctypes.c_uint64
+        lib.orc_vertex_triangles.argtypes = [ctypes.c_int64, _i64, _i32, _u64]
+        lib.orc_vertex_triangles.restype = None
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class CSR:
+    """Host CSR: ``row_ptr`` int64[n+1], ``col`` int32[nnz], rows sorted."""
+    n: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    @property
+    def m(self) -> int:
+        """Undirected edge count."""
+        return self.nnz // 2
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.row_ptr)
+
+
+def as_csr(n, row_ptr, col) -> CSR:
+    return CSR(int(n), np.ascontiguousarray(row_ptr, dtype=np.int64),
+               np.ascontiguousarray(col, dtype=np.int32))
+
+
+def build_csr(n: int, src: np.ndarray, dst: np.ndarray) -> CSR:
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    m = len(src)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    col = np.empty(max(2 * m, 1), dtype=np.int32)
+    nnz = _load().orc_build_csr(n, m, src, dst, rp, col, len(col))
+    if nnz == -1:
+        raise ValueError("vertex id out of range")
+    if nnz < 0:
+        raise RuntimeError(f"orc_build_csr failed ({nnz})")
+    return CSR(n, rp, col[:nnz].copy())
+
+
+def bfs_levels(g: CSR):
+    """Levels (int32[n]) and the number of components."""
+    lev = np.empty(max(g.n, 1), dtype=np.int32)
+    roots = _load().orc_bfs_levels(g.n, g.row_ptr, g.col if g.nnz else np.zeros(1, np.int32), lev)
+    if roots < 0:
+        raise RuntimeError("orc_bfs_levels failed")
+    return lev[:g.n], int(roots)
+
+
+@dataclass
+class Partition:
+    rp0: np.ndarray   # int64[n+1]
+    c0: np.ndarray    # int32[2|E0|]: per row, rank-upper part then rank-lower part
+    up0: np.ndarray   # int32[n]: size of the rank-upper part of each row
+    rp1: np.ndarray   # int64[n+1]
+    c1: np.ndarray    # int32[2|E1|]
+
+
+def _col_or_dummy(g: CSR):
+    return g.col if g.nnz else np.zeros(1, np.int32)
+
+
+def partition(g: CSR, level: np.ndarray) -> Partition:
+    lev = np.ascontiguousarray(level, dtype=np.int32)
+    rp0 = np.zeros(g.n + 1, np.int64)
+    rp1 = np.zeros(g.n + 1, np.int64)
+    c0 = np.empty(max(g.nnz, 1), np.int32)
+    c1 = np.empty(max(g.nnz, 1), np.int32)
+    up0 = np.zeros(max(g.n, 1), np.int32)
+    _load().orc_partition(g.n, g.row_ptr, _col_or_dummy(g), lev if g.n else np.zeros(1, np.int32),
+                          rp0, c0, up0, rp1, c1)
+    return Partition(rp0, c0[:rp0[-1]].copy(), up0[:g.n].copy(), rp1, c1[:rp1[-1]].copy())
+
+
+@dataclass
+class Alg4Result:
+    T: int
+    T0: int
+    T1: int
+    E0: int           # undirected horizontal edges
+    k: float          # percentage of edges that are horizontal
+
+
+def alg4(g: CSR, level: np.ndarray | None = None) -> Alg4Result:
+    """Algorithm 4; computes serial BFS levels when ``level`` is None."""
+    if level is None:
+        level, _ = bfs_levels(g)
+    lev = np.ascontiguousarray(level, dtype=np.int32)
+    t0 = ctypes.c_uint64()
+    t1 = ctypes.c_uint64()
+    e0 = ctypes.c_int64()
+    rc = _load().orc_alg4(g.n, g.row_ptr, _col_or_dummy(g), lev if g.n else np.zeros(1, np.int32),
+                          ctypes.byref(t0), ctypes.byref(t1), ctypes.byref(e0))
+    if rc != 0:
+        raise RuntimeError("orc_alg4 failed")
+    m = g.m
+    return Alg4Result(t0.value + t1.value, t0.value, t1.value, e0.value,
+                      100.0 * e0.value / m if m else 0.0)
+
+
+def count_emd(g: CSR) -> int:
+    return int(_load().orc_count_emd(g.n, g.row_ptr, _col_or_dummy(g)))
+
+
+def alg3(g: CSR, level: np.ndarray | None = None) -> int:
+    if level is None:
+        level, _ = bfs_levels(g)
+    lev = np.ascontiguousarray(level, dtype=np.int32)
+    return int(_load().orc_alg3(g.n, g.row_ptr, _col_or_dummy(g), lev if g.n else np.zeros(1, np.int32)))
+
+
+def vertex_triangles(g: CSR) -> np.ndarray:
+    tv = np.zeros(max(g.n, 1), np.uint64)
+    _load().orc_vertex_triangles(g.n, g.row_ptr, _col_or_dummy(g), tv)
+    return tv[:g.n]

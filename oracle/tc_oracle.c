@@ -1,0 +1,313 @@
+/*
+ * CPU ORACLE for the cover-edge + forward + hashing triangle count.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code with
+ * the GPU library: no headers, kernels, helpers or tables.
+ *
+ * Plain, serial, obviously-correct C.  Every routine names the passage of
+ * Bader, "Fast Triangle Counting" (arXiv 2309.09064) that it follows.  Row
+ * pointers are int64 here; the Python wrapper converts.
+ *
+ * Definitions (paper, Introduction and Section II):
+ *   G = (V, E) simple undirected, CSR with sorted rows, both directions stored.
+ *   A triangle is a set {a, b, c} of distinct vertices with ab, bc, ca in E.
+ *   L(v): BFS level, each component searched from its smallest unvisited id
+ *   (Algorithm 4, first loop), L(root) = 0.
+ *   E0 = {uv : L(u) = L(v)} (horizontal), E1 = E \ E0 (Algorithm 4, partition).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ CSR */
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Simple undirected graph in CSR from raw tuples (paper, Introduction: the
+ * input is CSR; experimental rules: sorted rows read-only).  Self-loops are
+ * dropped, each tuple is stored in both directions, duplicates are removed,
+ * rows are sorted ascending.  Returns nnz, -1 if an id is outside [0, n),
+ * -2 if nnz > cap, -3 on allocation failure.
+ */
+int64_t orc_build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                      int64_t *row_ptr, int32_t *col, int64_t cap)
+{
+    uint64_t *key = (uint64_t *)malloc((size_t)(2 * m + 1) * sizeof(uint64_t));
+    if (!key) return -3;
+    int64_t k = 0;
+    for (int64_t e = 0; e < m; ++e) {
+        int64_t u = src[e], v = dst[e];
+        if (u < 0 || u >= n || v < 0 || v >= n) { free(key); return -1; }
+        if (u == v) continue;
+        key[k++] = ((uint64_t)u << 32) | (uint64_t)v;
+        key[k++] = ((uint64_t)v << 32) | (uint64_t)u;
+    }
+    qsort(key, (size_t)k, sizeof(uint64_t), cmp_u64);
+    for (int64_t v = 0; v <= n; ++v) row_ptr[v] = 0;
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < k; ++i) {
+        if (i > 0 && key[i] == key[i - 1]) continue;
+        if (nnz >= cap) { free(key); return -2; }
+        col[nnz++] = (int32_t)(key[i] & 0xffffffffu);
+        row_ptr[(key[i] >> 32) + 1]++;
+    }
+    for (int64_t v = 0; v < n; ++v) row_ptr[v + 1] += row_ptr[v];
+    free(key);
+    return nnz;
+}
+
+/* ------------------------------------------------------------------ BFS */
+
+/*
+ * Algorithm 4, first loop (same as Algorithm 3): for v = 0..n-1 in id order,
+ * if v is unvisited, BFS(G, v).  L(v) is the hop distance from the root of
+ * v's search; the root gets level 0.  FIFO queue, textbook BFS.
+ * Returns the number of components (roots), or -3 on allocation failure.
+ */
+int64_t orc_bfs_levels(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t *level)
+{
+    int32_t *queue = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!queue) return -3;
+    for (int64_t v = 0; v < n; ++v) level[v] = -1;
+    int64_t roots = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        if (level[r] >= 0) continue;
+        ++roots;
+        int64_t head = 0, tail = 0;
+        level[r] = 0;
+        queue[tail++] = (int32_t)r;
+        while (head < tail) {
+            int32_t u = queue[head++];
+            for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+                int32_t w = col[j];
+                if (level[w] < 0) {
+                    level[w] = level[u] + 1;
+                    queue[tail++] = w;
+                }
+            }
+        }
+    }
+    free(queue);
+    return roots;
+}
+
+/* --------------------------------------------------------- partition (E0/E1) */
+
+/*
+ * Algorithm 4, partition loop: E0 = horizontal edges (equal levels), E1 = the
+ * rest.  Output CSRs keep each row in input (ascending) order:
+ *   N1(x)  = neighbours y with L(y) != L(x)                       (rp1, c1)
+ *   N0(x)  = neighbours y with L(y) == L(x), stored as the part with
+ *            rank(y) > rank(x) first, then the part with rank(y) < rank(x);
+ *            each part ascending by id.                            (rp0, c0)
+ *   up0[x] = |{y in N0(x) : rank(y) > rank(x)}|
+ * rank(x) = (deg(x), x) compared lexicographically, deg = full degree in G.
+ * The rank orientation is the forward algorithm's vertex order (paper,
+ * Related work: forward with degree ordering); the paper leaves the tie-break
+ * open, ids break ties here.
+ */
+static int rank_above(const int64_t *rp, int64_t y, int64_t x)
+{
+    int64_t dy = rp[y + 1] - rp[y], dx = rp[x + 1] - rp[x];
+    return dy > dx || (dy == dx && y > x);
+}
+
+void orc_partition(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *level,
+                   int64_t *rp0, int32_t *c0, int32_t *up0, int64_t *rp1, int32_t *c1)
+{
+    rp0[0] = 0;
+    rp1[0] = 0;
+    for (int64_t x = 0; x < n; ++x) {
+        int64_t p0 = rp0[x], p1 = rp1[x];
+        int32_t up = 0;
+        for (int64_t j = row_ptr[x]; j < row_ptr[x + 1]; ++j) {      /* upper part of N0 */
+            int32_t y = col[j];
+            if (level[y] == level[x] && rank_above(row_ptr, y, x)) { c0[p0++] = y; ++up; }
+        }
+        for (int64_t j = row_ptr[x]; j < row_ptr[x + 1]; ++j) {      /* lower part of N0 */
+            int32_t y = col[j];
+            if (level[y] == level[x] && !rank_above(row_ptr, y, x)) c0[p0++] = y;
+        }
+        for (int64_t j = row_ptr[x]; j < row_ptr[x + 1]; ++j) {      /* N1 */
+            int32_t y = col[j];
+            if (level[y] != level[x]) c1[p1++] = y;
+        }
+        up0[x] = up;
+        rp0[x + 1] = p0;
+        rp1[x + 1] = p1;
+    }
+}
+
+/* -------------------------------------------------------------- Algorithm 2 */
+
+/*
+ * Forward-hashed triangle count (Algorithm 2) on the graph given by
+ * (rp, adj).  Edges are enumerated row by row, u ascending, and each
+ * undirected edge is taken once, from its smaller endpoint (u < v).  A(v)
+ * grows as in the algorithm; `hash` is a Boolean array indexed by vertex id.
+ */
+static uint64_t forward_hashed(int64_t n, const int64_t *rp, const int32_t *adj)
+{
+    int64_t *a_off = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int64_t *a_len = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int32_t *a_set = (int32_t *)malloc((size_t)(rp[n] > 0 ? rp[n] : 1) * sizeof(int32_t));
+    unsigned char *hash = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!a_off || !a_len || !a_set || !hash) { free(a_off); free(a_len); free(a_set); free(hash); return UINT64_MAX; }
+    for (int64_t v = 0; v <= n; ++v) a_off[v] = rp[v];   /* A(v) holds at most deg(v) ids */
+    uint64_t T = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
+            int64_t v = adj[j];
+            if (!(u < v)) continue;
+            for (int64_t i = 0; i < a_len[u]; ++i) hash[a_set[a_off[u] + i]] = 1;
+            for (int64_t i = 0; i < a_len[v]; ++i)
+                if (hash[a_set[a_off[v] + i]]) ++T;
+            for (int64_t i = 0; i < a_len[u]; ++i) hash[a_set[a_off[u] + i]] = 0;
+            a_set[a_off[v] + a_len[v]++] = (int32_t)u;
+        }
+    }
+    free(a_off); free(a_len); free(a_set); free(hash);
+    return T;
+}
+
+/* -------------------------------------------------------------- Algorithm 4 */
+
+/*
+ * Fast triangle counting (Algorithm 4) given levels L:
+ *   partition E into G0 (horizontal) and G1;
+ *   T0 = forward-hashed count of G0 (Algorithm 2);
+ *   T1 = for each u: mark N_G1(u) in Hash; for each v in N_G0(u) with u < v,
+ *        count w in N_G1(v) that are marked; unmark.
+ * Outputs T0, T1 and |E0| (undirected).  Returns 0, or -3 on allocation
+ * failure.  Correct for any levels with |L(u) - L(v)| <= 1 on every edge.
+ */
+int orc_alg4(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *level,
+             uint64_t *t0_out, uint64_t *t1_out, int64_t *e0_out)
+{
+    const int64_t nnz = row_ptr[n];
+    int64_t *rp0 = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int64_t *rp1 = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int32_t *g0 = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    int32_t *g1 = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    unsigned char *hash = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!rp0 || !rp1 || !g0 || !g1 || !hash) {
+        free(rp0); free(rp1); free(g0); free(g1); free(hash);
+        return -3;
+    }
+    /* partition: each stored (directed) CSR entry goes to G0 or G1 */
+    rp0[0] = rp1[0] = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        int64_t p0 = rp0[u], p1 = rp1[u];
+        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+            int32_t v = col[j];
+            if (level[u] == level[v]) g0[p0++] = v; else g1[p1++] = v;
+        }
+        rp0[u + 1] = p0;
+        rp1[u + 1] = p1;
+    }
+    uint64_t T0 = forward_hashed(n, rp0, g0);
+    uint64_t T1 = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        for (int64_t j = rp1[u]; j < rp1[u + 1]; ++j) hash[g1[j]] = 1;
+        for (int64_t j = rp0[u]; j < rp0[u + 1]; ++j) {
+            int64_t v = g0[j];
+            if (!(u < v)) continue;
+            for (int64_t i = rp1[v]; i < rp1[v + 1]; ++i)
+                if (hash[g1[i]]) ++T1;
+        }
+        for (int64_t j = rp1[u]; j < rp1[u + 1]; ++j) hash[g1[j]] = 0;
+    }
+    *t0_out = T0;
+    *t1_out = T1;
+    *e0_out = rp0[n] / 2;
+    free(rp0); free(rp1); free(g0); free(g1); free(hash);
+    return (T0 == UINT64_MAX) ? -3 : 0;
+}
+
+/* ----------------------------------------------------- plain-definition count */
+
+/*
+ * Direction-oriented edge iterator with a sorted merge ("EMD" in the paper's
+ * list of algorithms): for every u and every neighbour v > u, count common
+ * neighbours w > v by a two-pointer merge of the sorted rows.  Counts each
+ * triangle u < v < w exactly once: the plain definition of T.
+ */
+uint64_t orc_count_emd(int64_t n, const int64_t *row_ptr, const int32_t *col)
+{
+    uint64_t T = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+            int64_t v = col[j];
+            if (v <= u) continue;
+            int64_t a = row_ptr[u], ae = row_ptr[u + 1], b = row_ptr[v], be = row_ptr[v + 1];
+            while (a < ae && b < be) {
+                if (col[a] < col[b]) ++a;
+                else if (col[a] > col[b]) ++b;
+                else { if (col[a] > v) ++T; ++a; ++b; }
+            }
+        }
+    }
+    return T;
+}
+
+/* -------------------------------------------------------------- Algorithm 3 */
+
+/*
+ * Cover-edge triangle count (Algorithm 3) given levels: for each horizontal
+ * edge (u, v) with u < v, each common neighbour w counts if L(w) != L(u), or
+ * if L(w) == L(u) and v < w.  Intersection by sorted merge.
+ */
+uint64_t orc_alg3(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *level)
+{
+    uint64_t T = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+            int64_t v = col[j];
+            if (!(level[u] == level[v] && u < v)) continue;
+            int64_t a = row_ptr[u], ae = row_ptr[u + 1], b = row_ptr[v], be = row_ptr[v + 1];
+            while (a < ae && b < be) {
+                if (col[a] < col[b]) ++a;
+                else if (col[a] > col[b]) ++b;
+                else {
+                    int64_t w = col[a];
+                    if (level[w] != level[u] || v < w) ++T;
+                    ++a; ++b;
+                }
+            }
+        }
+    }
+    return T;
+}
+
+/* ------------------------------------------------ per-vertex triangle counts */
+
+/*
+ * t(v) = number of triangles containing v (the clustering-coefficient input
+ * the paper's introduction motivates).  Plain definition by sorted merge:
+ * each triangle u < v < w adds 1 to t(u), t(v) and t(w).
+ */
+void orc_vertex_triangles(int64_t n, const int64_t *row_ptr, const int32_t *col, uint64_t *tv)
+{
+    for (int64_t v = 0; v < n; ++v) tv[v] = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+            int64_t v = col[j];
+            if (v <= u) continue;
+            int64_t a = row_ptr[u], ae = row_ptr[u + 1], b = row_ptr[v], be = row_ptr[v + 1];
+            while (a < ae && b < be) {
+                if (col[a] < col[b]) ++a;
+                else if (col[a] > col[b]) ++b;
+                else {
+                    if (col[a] > v) { tv[u]++; tv[v]++; tv[col[a]]++; }
+                    ++a; ++b;
+                }
+            }
+        }
+    }
+}

@@ -1,0 +1,307 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics
+(closed forms, brute force, trace(A^3)/6, networkx, printed karate row,
+invariants of the method).  No GPU."""
+from __future__ import annotations
+
+import os
+
+import networkx as nx
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse import csgraph
+
+import graphgen
+import oracle
+from _graphs import (book, brute_force, choose, complete, complete_bipartite, complete_tripartite,
+                     csr_from_edges, cycle, dense, disjoint_union, friendship, gnp, grid, petersen,
+                     random_tree, relabel, wheel)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def all_counts(g, level=None):
+    r = oracle.alg4(g, level)
+    return r, oracle.count_emd(g), oracle.alg3(g, level)
+
+
+def assert_T(g, expected):
+    r, emd, a3 = all_counts(g)
+    assert r.T == expected
+    assert emd == expected
+    assert a3 == expected
+
+
+# ------------------------------------------------------------ printed values
+
+def read_golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+def karate():
+    G = nx.karate_club_graph()
+    return csr_from_edges(G.number_of_nodes(), G.edges())
+
+
+def test_karate_printed_row():
+    """Table I/II, row karate: n=34, m=78, 45 triangles, k=35.9%."""
+    gold = read_golden("karate.txt")
+    g = karate()
+    assert g.n == gold["n"] and g.m == gold["m"]
+    r, emd, a3 = all_counts(g)
+    assert r.T == emd == a3 == gold["triangles"]
+    assert round(r.k, 1) == gold["k_percent"]
+    assert r.E0 == 28 and r.T0 == 8 and r.T1 == 37
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("n", range(1, 13))
+def test_complete_graph(n):
+    g = complete(n)
+    assert_T(g, choose(n, 3))
+    r = oracle.alg4(g)
+    # root 0 at level 0, every other vertex at level 1: G0 = K_{n-1}
+    assert r.T0 == choose(n - 1, 3)
+    assert r.T1 == choose(n - 1, 2)
+    assert r.E0 == choose(n - 1, 2)
+
+
+@pytest.mark.parametrize("n", range(5, 16))
+def test_wheel(n):
+    g = wheel(n)
+    assert_T(g, n - 1)
+    r = oracle.alg4(g)
+    assert r.T0 == 0 and r.T1 == n - 1 and r.E0 == n - 1
+
+
+def test_wheel_w4_is_k4():
+    assert_T(wheel(4), 4)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_trees_have_no_triangles(seed):
+    g = random_tree(50 + 17 * seed, seed)
+    assert_T(g, 0)
+    assert oracle.alg4(g).E0 == 0
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 3), (5, 5), (7, 2)])
+def test_complete_bipartite(a, b):
+    g = complete_bipartite(a, b)
+    assert_T(g, 0)
+    assert oracle.alg4(g).E0 == 0
+
+
+@pytest.mark.parametrize("a,b,c", [(1, 1, 1), (2, 3, 4), (5, 1, 3), (4, 4, 4)])
+def test_complete_tripartite(a, b, c):
+    assert_T(complete_tripartite(a, b, c), a * b * c)
+
+
+@pytest.mark.parametrize("n", [4, 6, 10, 3, 5, 9])
+def test_cycles(n):
+    assert_T(cycle(n), 1 if n == 3 else 0)
+    assert (oracle.alg4(cycle(n)).E0 == 0) == (n % 2 == 0)
+
+
+def test_grid_and_petersen():
+    assert_T(grid(7, 9), 0)
+    assert oracle.alg4(grid(7, 9)).E0 == 0
+    p = petersen()
+    assert_T(p, 0)
+    assert oracle.alg4(p).E0 > 0          # odd cycles: not bipartite
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 11])
+def test_friendship_and_book(k):
+    assert_T(friendship(k), k)
+    assert_T(book(k), k)
+
+
+def test_disjoint_union_is_additive():
+    parts = [complete(6), wheel(9), petersen(), friendship(4), gnp(30, 0.3, 3)]
+    g = disjoint_union(*parts)
+    assert_T(g, sum(oracle.count_emd(p) for p in parts))
+
+
+def test_empty_and_isolated():
+    g = csr_from_edges(5, [])
+    assert_T(g, 0)
+    lev, roots = oracle.bfs_levels(g)
+    assert roots == 5 and (lev == 0).all()
+    g0 = csr_from_edges(0, [])
+    assert oracle.count_emd(g0) == 0 and oracle.alg4(g0).T == 0
+
+
+# ------------------------------------------------------------ independent counts
+
+@pytest.mark.parametrize("seed", range(8))
+def test_brute_force_small(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 36))
+    g = gnp(n, float(rng.uniform(0.05, 0.9)), seed)
+    assert_T(g, brute_force(g))
+
+
+@pytest.mark.parametrize("n,p", [(120, 0.2), (300, 0.05), (400, 0.5), (250, 0.9)])
+def test_trace_a_cubed(n, p):
+    g = gnp(n, p, n)
+    A = dense(g)
+    assert_T(g, int(np.trace(A @ A @ A)) // 6)
+
+
+@pytest.mark.parametrize("scale", [8, 10])
+def test_networkx_triangles(scale):
+    n, s, d = graphgen.kronecker(scale, seed=scale)
+    g = oracle.build_csr(n, s, d)
+    G = nx.Graph()
+    G.add_nodes_from(range(n))
+    for u in range(n):
+        G.add_edges_from((u, int(v)) for v in g.col[g.row_ptr[u]:g.row_ptr[u + 1]])
+    tri = nx.triangles(G)
+    assert_T(g, sum(tri.values()) // 3)
+    tv = oracle.vertex_triangles(g)
+    assert all(int(tv[v]) == tri[v] for v in range(n))
+
+
+# ------------------------------------------------------------ levels
+
+def scipy_levels(g):
+    """BFS distance from the smallest id of each component (scipy)."""
+    A = sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+    ncomp, lab = csgraph.connected_components(A, directed=False)
+    lev = np.full(g.n, -1, np.int64)
+    for c in range(ncomp):
+        members = np.flatnonzero(lab == c)
+        root = members.min()
+        dist = csgraph.shortest_path(A, unweighted=True, indices=root, directed=False)
+        lev[members] = dist[members].astype(np.int64)
+    return lev, ncomp
+
+
+@pytest.mark.parametrize("gen", ["kron9", "er", "karate", "union"])
+def test_levels_match_shortest_paths(gen):
+    if gen == "kron9":
+        n, s, d = graphgen.kronecker(9, seed=3)
+        g = oracle.build_csr(n, s, d)
+    elif gen == "er":
+        n, s, d = graphgen.erdos_renyi(700, 0.003, 9)
+        g = oracle.build_csr(n, s, d)
+    elif gen == "karate":
+        g = karate()
+    else:
+        g = disjoint_union(random_tree(20, 1), complete(5), csr_from_edges(3, []), cycle(9))
+    lev, roots = oracle.bfs_levels(g)
+    ref, ncomp = scipy_levels(g)
+    assert roots == ncomp
+    assert np.array_equal(lev.astype(np.int64), ref)
+
+
+def test_levels_are_one_lipschitz():
+    n, s, d = graphgen.kronecker(11, seed=5)
+    g = oracle.build_csr(n, s, d)
+    lev, _ = oracle.bfs_levels(g)
+    u = np.repeat(np.arange(g.n), g.degrees())
+    assert np.abs(lev[u] - lev[g.col]).max() <= 1
+
+
+# ------------------------------------------------------------ invariants of the method
+
+@pytest.fixture(scope="module")
+def kron12():
+    n, s, d = graphgen.kronecker(12, seed=12)
+    return oracle.build_csr(n, s, d)
+
+
+def test_three_counters_agree_kronecker(kron12):
+    r, emd, a3 = all_counts(kron12)
+    assert r.T == emd == a3
+    assert r.T0 + r.T1 == r.T
+
+
+def test_all_horizontal_levels_give_forward_hashed(kron12):
+    """L = 0 everywhere is 1-Lipschitz: all edges horizontal, T1 = 0, T0 = T."""
+    z = np.zeros(kron12.n, np.int32)
+    r = oracle.alg4(kron12, z)
+    assert r.T1 == 0 and r.T0 == oracle.count_emd(kron12)
+    assert r.E0 == kron12.m
+    assert oracle.alg3(kron12, z) == r.T
+
+
+def multi_source_levels(g, roots):
+    """BFS distance to the nearest of several roots (levels still 1-Lipschitz)."""
+    A = sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+    dist = csgraph.shortest_path(A, unweighted=True, indices=roots, directed=False).min(axis=0)
+    lev = np.where(np.isinf(dist), 0, dist).astype(np.int32)
+    return lev
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_count_invariant_under_root_choice(kron12, seed):
+    rng = np.random.default_rng(seed)
+    roots = rng.choice(kron12.n, size=1 + 5 * seed, replace=False)
+    lev = multi_source_levels(kron12, roots)
+    r = oracle.alg4(kron12, lev)
+    assert r.T == oracle.count_emd(kron12)
+    assert oracle.alg3(kron12, lev) == r.T
+
+
+def test_count_invariant_under_relabelling():
+    g = gnp(90, 0.15, 4)
+    perm = np.random.default_rng(1).permutation(g.n)
+    h = relabel(g, perm)
+    assert oracle.alg4(h).T == oracle.alg4(g).T == brute_force(g)
+
+
+def test_vertex_triangle_sum(kron12):
+    assert int(oracle.vertex_triangles(kron12).sum()) == 3 * oracle.count_emd(kron12)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_horizontal_edges_iff_not_bipartite(seed):
+    rng = np.random.default_rng(seed)
+    g = gnp(int(rng.integers(5, 40)), float(rng.uniform(0.02, 0.2)), seed)
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    for u in range(g.n):
+        G.add_edges_from((u, int(v)) for v in g.col[g.row_ptr[u]:g.row_ptr[u + 1]])
+    assert (oracle.alg4(g).E0 == 0) == nx.is_bipartite(G)
+
+
+# ------------------------------------------------------------ CSR builder and partition
+
+@pytest.mark.parametrize("scale", [6, 10, 13])
+def test_build_csr_matches_numpy(scale):
+    n, s, d = graphgen.kronecker(scale, seed=scale + 1)
+    g = oracle.build_csr(n, s, d)
+    ref = csr_from_edges(n, zip(s.tolist(), d.tolist()))
+    assert np.array_equal(g.row_ptr, ref.row_ptr)
+    assert np.array_equal(g.col, ref.col)
+
+
+def test_build_csr_rejects_bad_ids():
+    with pytest.raises(ValueError):
+        oracle.build_csr(4, np.array([0, 4], np.int32), np.array([1, 2], np.int32))
+
+
+def test_partition_definition(kron12):
+    lev, _ = oracle.bfs_levels(kron12)
+    p = oracle.partition(kron12, lev)
+    g = kron12
+    deg = g.degrees()
+    for x in range(0, g.n, 7):
+        nb = g.col[g.row_ptr[x]:g.row_ptr[x + 1]]
+        hor = nb[lev[nb] == lev[x]]
+        above = (deg[hor] > deg[x]) | ((deg[hor] == deg[x]) & (hor > x))
+        row0 = p.c0[p.rp0[x]:p.rp0[x + 1]]
+        assert np.array_equal(row0, np.concatenate([hor[above], hor[~above]]))
+        assert p.up0[x] == above.sum()
+        assert np.array_equal(p.c1[p.rp1[x]:p.rp1[x + 1]], nb[lev[nb] != lev[x]])
+    assert p.rp0[-1] == 2 * oracle.alg4(g, lev).E0
