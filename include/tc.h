@@ -1,0 +1,213 @@
+/*
+ * tc.h -- C ABI of the MI355X (gfx950) triangle-counting library.
+ *
+ * The library computes the cover-edge + forward + hashing triangle count of
+ * Bader, "Fast Triangle Counting" (arXiv 2309.09064, Algorithm 4):
+ *   1. BFS levels L(v), each component searched from its smallest vertex id
+ *      (Algorithm 4, first loop);
+ *   2. the partition of E into horizontal edges E0 (L(u) = L(v)) and the
+ *      level-spanning rest E1 (Algorithm 4, partition loop);
+ *   3. T0 = triangles inside G0 = (V, E0), counted forward-style over the
+ *      rank-oriented lists N0+ (Algorithm 2);
+ *   4. T1 = for each horizontal edge {u, v}, |N1(u) & N1(v)| (Algorithm 4,
+ *      hashed loop), each intersection hashing the larger list and streaming
+ *      the smaller one (Section II, cost min(d(u), d(v)));
+ *   T = T0 + T1.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Graph: simple undirected graph in CSR, both directions stored, rows
+ *    sorted ascending, no self-loops or duplicates.  row_ptr is int32[n+1]
+ *    with row_ptr[0] = 0 and row_ptr[n] = nnz; col_idx is int32[nnz].
+ *    nnz < 2^31.  The input is read-only (Section III, experimental rules).
+ *  - Pointers named d_* are DEVICE pointers (HIP device memory of the
+ *    current device); pointers named h_* or of struct type are HOST pointers.
+ *    The caller owns every buffer.
+ *  - Scratch memory comes only from the caller's workspace (ws, ws_bytes);
+ *    query its size with the matching *_ws function.  Entry points allocate
+ *    no device memory, so every auxiliary structure is released when the
+ *    caller frees the workspace.  ws must be 256-byte aligned.
+ *  - stream: a hipStream_t passed as void*; NULL means the default stream.
+ *    Work is enqueued on that stream.  Entry points that return a host value
+ *    (nnz, a count) synchronise that stream before returning.
+ *  - Errors: functions returning int return TC_OK (0) or a negative tc_err
+ *    code.  tc_count returns TC_COUNT_ERROR (UINT64_MAX) on failure; this is
+ *    unambiguous because a graph with nnz < 2^31 has fewer than 2^47
+ *    triangles.  tc_last_error() returns the calling thread's last code and
+ *    tc_strerror() its text.  Arguments are validated on the host before any
+ *    device work; with TC_VALIDATE the CSR itself is checked on the device.
+ */
+#ifndef TC_H
+#define TC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+enum tc_err {
+    TC_OK = 0,
+    TC_ERR_ARG = -1,        /* NULL pointer, negative size, bad option      */
+    TC_ERR_RANGE = -2,      /* a vertex id outside [0, n)                    */
+    TC_ERR_OVERFLOW = -3,   /* nnz or a size does not fit int32 CSR          */
+    TC_ERR_CAPACITY = -4,   /* output buffer too small                       */
+    TC_ERR_WORKSPACE = -5,  /* workspace missing, too small or misaligned    */
+    TC_ERR_HIP = -6,        /* a HIP runtime call failed                     */
+    TC_ERR_NO_DEVICE = -7,  /* no gfx950 device visible                      */
+    TC_ERR_INVALID_CSR = -8 /* TC_VALIDATE found a malformed CSR / levels    */
+};
+
+#define TC_COUNT_ERROR UINT64_MAX
+
+/* ------------------------------------------------------------ options */
+
+/* Intersection strategies a bucket of work can be given (all exact). */
+enum tc_strategy {
+    TC_STRAT_AUTO = -1,       /* use the schedule (heuristic or network)     */
+    TC_STRAT_WAVE_HASH = 0,   /* owner list in a wavefront-private LDS hash   */
+    TC_STRAT_WG_HASH = 1,     /* owner list in a workgroup-shared LDS hash    */
+    TC_STRAT_BSEARCH = 2,     /* binary search in the owner's global list     */
+    TC_STRAT_MERGE = 3,       /* two-pointer merge of the two sorted lists    */
+    TC_NUM_STRATEGIES = 4
+};
+
+enum tc_schedule {
+    TC_SCHED_HEURISTIC = 0,   /* list-size thresholds                        */
+    TC_SCHED_MLP = 1          /* the loaded cost network (tc_sched_load)      */
+};
+
+enum tc_flags {
+    TC_VALIDATE = 1,          /* check CSR (sorted, symmetric-free checks,
+                                 ranges) and levels on the device            */
+    TC_TIMING = 2             /* fill the phase times of tc_stats            */
+};
+
+typedef struct tc_options {
+    int32_t schedule;         /* tc_schedule                                 */
+    int32_t force_strategy;   /* tc_strategy; >= 0 forces it on every bucket
+                                 (infeasible hash choices fall back to
+                                 TC_STRAT_BSEARCH)                           */
+    int32_t flags;            /* tc_flags bits                               */
+    int32_t wave_slots;       /* LDS hash slots per wavefront (power of 2,
+                                 64..4096); 0 = default 2048                 */
+    int32_t wg_slots;         /* LDS hash slots per workgroup (power of 2,
+                                 1024..32768); 0 = default 16384             */
+    int32_t chunk_work;       /* target probe elements per work item;
+                                 0 = default 16384                           */
+    int32_t grid_blocks;      /* persistent grid size; 0 = 2 per CU          */
+    int32_t wave_max_owner;   /* heuristic: largest owner list for the
+                                 wavefront hash; 0 = wave_slots / 2          */
+} tc_options;
+
+/* Per-call statistics (host struct, all optional). */
+typedef struct tc_stats {
+    uint64_t T0;              /* triangles inside G0                          */
+    uint64_t T1;              /* triangles with exactly one horizontal edge   */
+    int64_t e0;               /* undirected horizontal edges |E0|             */
+    int64_t units;            /* (owner, kind) work units                     */
+    int64_t items;            /* work items after chunking                    */
+    int64_t probes;           /* probe elements streamed (sum of the smaller
+                                 list over all live intersections)           */
+    int64_t hashed;           /* owner-list elements hashed or searched       */
+    int32_t levels;           /* number of BFS levels (max level + 1)         */
+    int32_t bfs_rounds;       /* BFS level steps executed                     */
+    float ms_bfs;             /* phase times (TC_TIMING), milliseconds        */
+    float ms_partition;
+    float ms_bucket;
+    float ms_isect;
+    int32_t strategy_items[TC_NUM_STRATEGIES]; /* items run per strategy     */
+} tc_stats;
+
+/* ------------------------------------------------------------ error query */
+
+int tc_last_error(void);
+const char *tc_strerror(int code);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int tc_version(void);
+
+/* ------------------------------------------------------------ CSR build */
+
+/*
+ * Workspace bytes for tc_build_csr with n vertices and m_tuples tuples.
+ */
+int tc_build_csr_ws(int32_t n, int64_t m_tuples, size_t *h_ws_bytes);
+
+/*
+ * Simple undirected CSR from raw edge tuples (the paper's input format,
+ * Introduction): drops self-loops, stores each tuple in both directions,
+ * removes duplicates and sorts every row.
+ *   d_src, d_dst  int32[m_tuples] device, ids in [0, n)
+ *   d_row_ptr     int32[n+1] device, output
+ *   d_col_idx     int32[col_cap] device, output (first nnz entries)
+ *   h_nnz         host, receives nnz
+ * Errors: TC_ERR_RANGE (an id outside [0, n)), TC_ERR_OVERFLOW (2 * m_tuples
+ * >= 2^31), TC_ERR_CAPACITY (nnz > col_cap; *h_nnz still receives nnz).
+ * Synchronises the stream.
+ */
+int tc_build_csr(int32_t n, int64_t m_tuples, const int32_t *d_src, const int32_t *d_dst,
+                 int32_t *d_row_ptr, int32_t *d_col_idx, int64_t col_cap, int64_t *h_nnz,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ BFS levels */
+
+int tc_bfs_levels_ws(int32_t n, int64_t nnz, size_t *h_ws_bytes);
+
+/*
+ * BFS levels with the paper's serial semantics (Algorithm 4, first loop):
+ * every component is searched from its smallest vertex id, which gets level
+ * 0; L(v) is the hop distance from that root.  The result is unique.
+ *   d_levels   int32[n] device, output
+ *   h_levels_count  host, optional (NULL ok): max level + 1
+ * Computed as connected components by minimum-id linking, then a
+ * multi-source direction-optimising BFS from all roots.  Synchronises.
+ */
+int tc_bfs_levels(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                  int32_t *d_levels, int32_t *h_levels_count, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* ------------------------------------------------------------ count */
+
+int tc_count_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_bytes);
+
+/*
+ * Triangle count T = T0 + T1 (Algorithm 4).
+ *   d_levels   int32[n] device or NULL.  NULL: computed as by tc_bfs_levels
+ *              (charged to this call).  Non-NULL: any levels with
+ *              |L(u) - L(v)| <= 1 on every edge give the same T (the
+ *              cover-edge argument behind Algorithm 3); the paper notes the
+ *              method pays off when BFS results already exist.
+ *   opt        host, NULL = defaults (heuristic schedule)
+ *   stats      host, NULL ok
+ * Returns T, or TC_COUNT_ERROR (see tc_last_error).  Synchronises.
+ */
+uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                  const int32_t *d_levels, const tc_options *opt, tc_stats *stats, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/*
+ * The two CSRs of the partition (Algorithm 4, partition loop), for tests and
+ * for callers that reuse them.  Outputs (device, caller-owned):
+ *   d_rp0  int32[n+1], d_c0 int32[nnz]: N0(x) per row = the neighbours of
+ *          equal level with rank above x, ascending, then those with rank
+ *          below x, ascending; rank(y) = (deg(y), y) lexicographic.
+ *   d_up0  int32[n]: size of the rank-above part of each N0 row.
+ *   d_rp1  int32[n+1], d_c1 int32[nnz]: N1(x) = neighbours of other level,
+ *          ascending.
+ *   h_e0   host: |E0| (undirected).
+ * Synchronises.
+ */
+int tc_partition_ws(int32_t n, int64_t nnz, size_t *h_ws_bytes);
+int tc_partition(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                 const int32_t *d_levels, int32_t *d_rp0, int32_t *d_c0, int32_t *d_up0,
+                 int32_t *d_rp1, int32_t *d_c1, int64_t *h_e0, void *ws, size_t ws_bytes,
+                 void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H */

@@ -1,0 +1,198 @@
+"""MI355X triangle counting (cover-edge + forward + hashing, Bader 2023).
+
+A thin torch-facing layer over the C ABI in ``include/tc.h``: it allocates
+device tensors (outputs and workspaces) with PyTorch, passes raw pointers and
+the current HIP stream, and converts status codes into exceptions.  Every
+step of the computation runs in ``libtc.so``'s HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _capi
+from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_STRATEGIES, TC_SCHED_HEURISTIC, TC_SCHED_MLP,
+                    TC_STRAT_AUTO, TC_STRAT_BSEARCH, TC_STRAT_MERGE, TC_STRAT_WAVE_HASH, TC_STRAT_WG_HASH,
+                    TC_TIMING, TC_VALIDATE)
+
+__all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count", "workspace",
+           "STRATEGY_NAMES", "TC_STRAT_AUTO", "TC_STRAT_WAVE_HASH", "TC_STRAT_WG_HASH", "TC_STRAT_BSEARCH",
+           "TC_STRAT_MERGE", "TC_SCHED_HEURISTIC", "TC_SCHED_MLP", "TC_VALIDATE", "TC_TIMING"]
+
+
+class TCError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _capi.load().tc_strerror(code).decode()
+        super().__init__(f"{where}: {msg} ({code})")
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise TCError(rc, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_i32_cuda(t, name):
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous int32 CUDA tensor")
+
+
+def workspace(nbytes: int, device=None):
+    """A 256-byte aligned device workspace (a uint8 tensor view)."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    raw = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=dev)
+    off = (-raw.data_ptr()) % 256
+    return raw[off:off + int(nbytes)] if nbytes else raw[off:off + 1]
+
+
+@dataclass
+class Options:
+    schedule: int = TC_SCHED_HEURISTIC
+    force_strategy: int = TC_STRAT_AUTO
+    validate: bool = False
+    timing: bool = False
+    wave_slots: int = 0
+    wg_slots: int = 0
+    chunk_work: int = 0
+    grid_blocks: int = 0
+    wave_max_owner: int = 0
+
+    def to_c(self):
+        o = _capi.tc_options()
+        o.schedule = self.schedule
+        o.force_strategy = self.force_strategy
+        o.flags = (TC_VALIDATE if self.validate else 0) | (TC_TIMING if self.timing else 0)
+        o.wave_slots = self.wave_slots
+        o.wg_slots = self.wg_slots
+        o.chunk_work = self.chunk_work
+        o.grid_blocks = self.grid_blocks
+        o.wave_max_owner = self.wave_max_owner
+        return o
+
+
+@dataclass
+class CountResult:
+    T: int
+    T0: int
+    T1: int
+    e0: int
+    units: int
+    items: int
+    probes: int
+    hashed: int
+    levels: int
+    bfs_rounds: int
+    ms: dict = field(default_factory=dict)
+    strategy_items: dict = field(default_factory=dict)
+
+
+def build_csr(n: int, src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """Simple undirected CSR (row_ptr, col_idx) from device tuples."""
+    _require_i32_cuda(src, "src")
+    _require_i32_cuda(dst, "dst")
+    lib = _capi.load()
+    m = src.numel()
+    if dst.numel() != m:
+        raise ValueError("src and dst differ in length")
+    need = ctypes.c_size_t()
+    _check(lib.tc_build_csr_ws(n, m, ctypes.byref(need)), "tc_build_csr_ws")
+    ws = workspace(need.value, src.device)
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=src.device)
+    col = torch.empty(max(2 * m, 1), dtype=torch.int32, device=src.device)
+    nnz = ctypes.c_int64()
+    _check(lib.tc_build_csr(n, m, _ptr(src), _ptr(dst), _ptr(row_ptr), _ptr(col), col.numel(),
+                            ctypes.byref(nnz), _ptr(ws), need.value, _stream(stream)), "tc_build_csr")
+    return row_ptr, col[:nnz.value]
+
+
+def bfs_levels(row_ptr: torch.Tensor, col: torch.Tensor, stream=None):
+    """Levels (int32 CUDA tensor) and the number of levels."""
+    _require_i32_cuda(row_ptr, "row_ptr")
+    _require_i32_cuda(col, "col")
+    lib = _capi.load()
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    need = ctypes.c_size_t()
+    _check(lib.tc_bfs_levels_ws(n, nnz, ctypes.byref(need)), "tc_bfs_levels_ws")
+    ws = workspace(need.value, row_ptr.device)
+    lev = torch.empty(max(n, 1), dtype=torch.int32, device=row_ptr.device)
+    nlev = ctypes.c_int32()
+    _check(lib.tc_bfs_levels(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(lev), ctypes.byref(nlev), _ptr(ws),
+                             need.value, _stream(stream)), "tc_bfs_levels")
+    return lev[:n], nlev.value
+
+
+def partition(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor, stream=None):
+    """The E0/E1 partition CSRs as a dict of device tensors."""
+    for t, nm in ((row_ptr, "row_ptr"), (col, "col"), (levels, "levels")):
+        _require_i32_cuda(t, nm)
+    lib = _capi.load()
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    need = ctypes.c_size_t()
+    _check(lib.tc_partition_ws(n, nnz, ctypes.byref(need)), "tc_partition_ws")
+    ws = workspace(need.value, row_ptr.device)
+    dev = row_ptr.device
+    out = {
+        "rp0": torch.empty(n + 1, dtype=torch.int32, device=dev),
+        "c0": torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+        "up0": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+        "rp1": torch.empty(n + 1, dtype=torch.int32, device=dev),
+        "c1": torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+    }
+    e0 = ctypes.c_int64()
+    _check(lib.tc_partition(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(levels), _ptr(out["rp0"]), _ptr(out["c0"]),
+                            _ptr(out["up0"]), _ptr(out["rp1"]), _ptr(out["c1"]), ctypes.byref(e0), _ptr(ws),
+                            need.value, _stream(stream)), "tc_partition")
+    out["e0"] = e0.value
+    out["up0"] = out["up0"][:n]
+    return out
+
+
+class Counter:
+    """Reusable counting context: one workspace for repeated calls."""
+
+    def __init__(self, n: int, nnz: int, options: Options | None = None, device=None):
+        self.n, self.nnz = n, nnz
+        self.options = options or Options()
+        self._opt = self.options.to_c()
+        lib = _capi.load()
+        need = ctypes.c_size_t()
+        _check(lib.tc_count_ws(n, nnz, ctypes.byref(self._opt), ctypes.byref(need)), "tc_count_ws")
+        self.ws_bytes = need.value
+        self.ws = workspace(need.value, device)
+
+    def __call__(self, row_ptr, col, levels=None, stream=None) -> CountResult:
+        lib = _capi.load()
+        st = _capi.tc_stats()
+        T = lib.tc_count(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(levels), ctypes.byref(self._opt),
+                         ctypes.byref(st), _ptr(self.ws), self.ws_bytes, _stream(stream))
+        if T == TC_COUNT_ERROR:
+            raise TCError(lib.tc_last_error(), "tc_count")
+        return CountResult(
+            T=int(T), T0=int(st.T0), T1=int(st.T1), e0=int(st.e0), units=int(st.units), items=int(st.items),
+            probes=int(st.probes), hashed=int(st.hashed), levels=int(st.levels), bfs_rounds=int(st.bfs_rounds),
+            ms={"bfs": st.ms_bfs, "partition": st.ms_partition, "bucket": st.ms_bucket, "isect": st.ms_isect},
+            strategy_items={STRATEGY_NAMES[k]: int(st.strategy_items[k]) for k in range(TC_NUM_STRATEGIES)})
+
+
+def count(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor | None = None,
+          options: Options | None = None, stream=None) -> CountResult:
+    """Triangle count T = T0 + T1 with statistics."""
+    _require_i32_cuda(row_ptr, "row_ptr")
+    _require_i32_cuda(col, "col")
+    if levels is not None:
+        _require_i32_cuda(levels, "levels")
+    c = Counter(row_ptr.numel() - 1, col.numel(), options, row_ptr.device)
+    return c(row_ptr, col, levels, stream)

@@ -1,0 +1,415 @@
+// C ABI of libtc: argument checks on the host before any device work,
+// workspace carving, optional device-side input validation, error codes.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "tc_internal.hpp"
+
+namespace tc {
+
+namespace {
+thread_local int g_last_error = TC_OK;
+constexpr int kMaxDevices = 64;
+DeviceInfo g_dev[kMaxDevices];
+}  // namespace
+
+void set_error(int code) { g_last_error = code; }
+int last_error() { return g_last_error; }
+
+void note_hip_error(hipError_t e, const char *what, const char *file, int line) {
+    if (getenv("TC_LOG")) fprintf(stderr, "libtc: %s failed: %s (%s:%d)\n", what, hipGetErrorString(e), file, line);
+}
+
+int device_info(DeviceInfo *out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TC_ERR_NO_DEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return TC_ERR_NO_DEVICE;
+    DeviceInfo &d = g_dev[dev];
+    if (!d.ok) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return TC_ERR_NO_DEVICE;
+        if (strncmp(p.gcnArchName, "gfx950", 6) != 0) return TC_ERR_NO_DEVICE;
+        d.cus = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+        d.ok = 1;
+    }
+    *out = d;
+    return TC_OK;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- validation
+
+// bit 0: row_ptr not monotone / wrong ends; bit 1: column out of range;
+// bit 2: row not strictly ascending (duplicate or unsorted); bit 3: self-loop;
+// bit 4: missing reverse entry; bit 5: levels differ by more than one.
+__global__ void k_validate(int32_t n, int64_t nnz, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           const int32_t *__restrict__ lev, int32_t *__restrict__ bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+        int32_t b = rp[x], e = rp[x + 1];
+        if (e < b || b < 0 || (int64_t)e > nnz || (x == 0 && b != 0) || (x == n - 1 && (int64_t)e != nnz)) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        for (int32_t j = b; j < e; ++j) {
+            int32_t y = col[j];
+            if (y < 0 || y >= n) { atomicOr(bad, 2); continue; }
+            if (j > b && col[j - 1] >= y) atomicOr(bad, 4);
+            if (y == x) atomicOr(bad, 8);
+            int32_t lo = rp[y], hi = rp[y + 1];
+            bool found = false;
+            if (lo >= 0 && hi <= nnz && lo <= hi) {
+                while (lo < hi) {
+                    int32_t mid = (lo + hi) >> 1;
+                    if (col[mid] < (int32_t)x) lo = mid + 1; else hi = mid;
+                }
+                found = lo < rp[y + 1] && col[lo] == (int32_t)x;
+            }
+            if (!found) atomicOr(bad, 16);
+            if (lev) {
+                int32_t d = lev[x] - lev[y];
+                if (d > 1 || d < -1) atomicOr(bad, 32);
+            }
+        }
+    }
+}
+
+int validate_device(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, const int32_t *lev,
+                    int32_t *scratch, hipStream_t s) {
+    TC_HIP_TRY(hipMemsetAsync(scratch, 0, sizeof(int32_t), s));
+    if (n > 0) {
+        int64_t g = ((int64_t)n + 255) / 256;
+        if (g > 16384) g = 16384;
+        hipLaunchKernelGGL(k_validate, dim3((unsigned)g), dim3(256), 0, s, n, nnz, rp, col, lev, scratch);
+        TC_HIP_TRY(hipGetLastError());
+    }
+    int32_t bad = 0;
+    TC_HIP_TRY(hipMemcpyAsync(&bad, scratch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TC_HIP_TRY(hipStreamSynchronize(s));
+    if (n == 0 && nnz != 0) bad |= 1;
+    return bad ? TC_ERR_INVALID_CSR : TC_OK;
+}
+
+// ---------------------------------------------------------------- options
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int make_cfg(const tc_options *opt, CountCfg *cfg, int *flags) {
+    CountCfg c;
+    *flags = 0;
+    if (opt) {
+        if (opt->schedule != TC_SCHED_HEURISTIC && opt->schedule != TC_SCHED_MLP) return TC_ERR_ARG;
+        if (opt->force_strategy < TC_STRAT_AUTO || opt->force_strategy >= TC_NUM_STRATEGIES) return TC_ERR_ARG;
+        if (opt->wave_slots && (!is_pow2(opt->wave_slots) || opt->wave_slots < 64 || opt->wave_slots > 4096))
+            return TC_ERR_ARG;
+        if (opt->wg_slots && (!is_pow2(opt->wg_slots) || opt->wg_slots < 1024 || opt->wg_slots > 32768))
+            return TC_ERR_ARG;
+        if (opt->chunk_work < 0 || opt->grid_blocks < 0 || opt->wave_max_owner < 0) return TC_ERR_ARG;
+        c.schedule = opt->schedule;
+        c.force = opt->force_strategy;
+        if (opt->wave_slots) c.wave_slots = opt->wave_slots;
+        if (opt->wg_slots) c.wg_slots = opt->wg_slots;
+        if (opt->chunk_work) c.chunk_work = opt->chunk_work;
+        c.grid_blocks = opt->grid_blocks;
+        c.wave_max_owner = opt->wave_max_owner;
+        *flags = opt->flags;
+    }
+    // the eight wavefront tables of a block share the workgroup's LDS
+    if (c.wave_slots * 8 > 32768) return TC_ERR_ARG;
+    c.timing = (*flags & TC_TIMING) != 0;
+    *cfg = c;
+    return TC_OK;
+}
+
+int check_graph_args(int32_t n, int64_t nnz, const void *rp, const void *col) {
+    if (n < 0 || nnz < 0) return TC_ERR_ARG;
+    if (nnz >= (int64_t(1) << 31)) return TC_ERR_OVERFLOW;
+    if (n > 0 && !rp) return TC_ERR_ARG;
+    if (nnz > 0 && !col) return TC_ERR_ARG;
+    if (n == 0 && nnz > 0) return TC_ERR_ARG;
+    return TC_OK;
+}
+
+int check_ws(void *ws, size_t ws_bytes, size_t need) {
+    if (need > ws_bytes) return TC_ERR_WORKSPACE;
+    if (need > 0 && !ws) return TC_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return TC_ERR_WORKSPACE;
+    return TC_OK;
+}
+
+int fail(int code) {
+    set_error(code);
+    return code;
+}
+
+// ---------------------------------------------------------------- tc_count layout
+
+struct CountPlan {
+    int32_t *levels;
+    PartBufs pb;
+    void *scratch;
+    size_t scratch_bytes;
+    int32_t *flag;
+};
+
+CountPlan carve_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels) {
+    CountPlan P;
+    const int64_t nn = n > 0 ? n : 1;
+    const int64_t nz = nnz > 0 ? nnz : 1;
+    P.levels = own_levels ? c.take<int32_t>(nn) : nullptr;
+    P.pb.rp0 = c.take<int32_t>(nn + 1);
+    P.pb.c0 = c.take<int32_t>(nz);
+    P.pb.up0 = c.take<int32_t>(nn);
+    P.pb.rp1 = c.take<int32_t>(nn + 1);
+    P.pb.c1 = c.take<int32_t>(nz);
+    P.pb.d0 = c.take<int32_t>(nn);
+    P.pb.rpu = c.take<int32_t>(nn + 1);
+    P.pb.e0x2 = c.take<int64_t>(1);
+    P.flag = c.take<int32_t>(64);
+    size_t sb = bfs_ws_bytes(n, nnz);
+    size_t t = partition_ws_bytes(n, nnz);
+    if (t > sb) sb = t;
+    t = count_ws_bytes(n, nnz);
+    if (t > sb) sb = t;
+    P.scratch = c.take<char>(sb);
+    P.scratch_bytes = sb;
+    return P;
+}
+
+}  // namespace
+}  // namespace tc
+
+using namespace tc;
+
+extern "C" {
+
+int tc_last_error(void) { return tc::last_error(); }
+
+const char *tc_strerror(int code) {
+    switch (code) {
+    case TC_OK: return "ok";
+    case TC_ERR_ARG: return "invalid argument";
+    case TC_ERR_RANGE: return "vertex id out of range";
+    case TC_ERR_OVERFLOW: return "size does not fit int32 CSR";
+    case TC_ERR_CAPACITY: return "output buffer too small";
+    case TC_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case TC_ERR_HIP: return "HIP runtime error";
+    case TC_ERR_NO_DEVICE: return "no gfx950 device";
+    case TC_ERR_INVALID_CSR: return "malformed CSR or levels";
+    default: return "unknown error";
+    }
+}
+
+int tc_version(void) { return 10000; }
+
+int tc_build_csr_ws(int32_t n, int64_t m_tuples, size_t *h_ws_bytes) {
+    if (!h_ws_bytes || n < 0 || m_tuples < 0) return fail(TC_ERR_ARG);
+    if (2 * m_tuples >= (int64_t(1) << 31)) return fail(TC_ERR_OVERFLOW);
+    *h_ws_bytes = build_csr_ws_bytes(n, m_tuples);
+    return fail(TC_OK);
+}
+
+int tc_build_csr(int32_t n, int64_t m_tuples, const int32_t *d_src, const int32_t *d_dst, int32_t *d_row_ptr,
+                 int32_t *d_col_idx, int64_t col_cap, int64_t *h_nnz, void *ws, size_t ws_bytes, void *stream) {
+    if (n < 0 || m_tuples < 0 || col_cap < 0 || !d_row_ptr || !h_nnz) return fail(TC_ERR_ARG);
+    if (m_tuples > 0 && (!d_src || !d_dst)) return fail(TC_ERR_ARG);
+    if (col_cap > 0 && !d_col_idx) return fail(TC_ERR_ARG);
+    if (2 * m_tuples >= (int64_t(1) << 31)) return fail(TC_ERR_OVERFLOW);
+    int rc = check_ws(ws, ws_bytes, build_csr_ws_bytes(n, m_tuples));
+    if (rc != TC_OK) return fail(rc);
+    DeviceInfo di;
+    rc = device_info(&di);
+    if (rc != TC_OK) return fail(rc);
+    rc = build_csr_run(n, m_tuples, d_src, d_dst, d_row_ptr, d_col_idx, col_cap, h_nnz, ws, ws_bytes,
+                       static_cast<hipStream_t>(stream));
+    return fail(rc);
+}
+
+int tc_bfs_levels_ws(int32_t n, int64_t nnz, size_t *h_ws_bytes) {
+    if (!h_ws_bytes) return fail(TC_ERR_ARG);
+    int rc = check_graph_args(n, nnz, (const void *)1, (const void *)1);
+    if (rc != TC_OK) return fail(rc);
+    *h_ws_bytes = bfs_ws_bytes(n, nnz);
+    return fail(TC_OK);
+}
+
+int tc_bfs_levels(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t *d_levels,
+                  int32_t *h_levels_count, void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
+    if (rc != TC_OK) return fail(rc);
+    if (n > 0 && !d_levels) return fail(TC_ERR_ARG);
+    rc = check_ws(ws, ws_bytes, bfs_ws_bytes(n, nnz));
+    if (rc != TC_OK) return fail(rc);
+    DeviceInfo di;
+    rc = device_info(&di);
+    if (rc != TC_OK) return fail(rc);
+    BfsOut bo;
+    rc = bfs_run(n, nnz, d_row_ptr, d_col_idx, d_levels, &bo, ws, ws_bytes, static_cast<hipStream_t>(stream));
+    if (rc == TC_OK) {
+        hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) rc = TC_ERR_HIP;
+    }
+    if (rc == TC_OK && h_levels_count) *h_levels_count = bo.levels;
+    return fail(rc);
+}
+
+int tc_partition_ws(int32_t n, int64_t nnz, size_t *h_ws_bytes) {
+    if (!h_ws_bytes) return fail(TC_ERR_ARG);
+    int rc = check_graph_args(n, nnz, (const void *)1, (const void *)1);
+    if (rc != TC_OK) return fail(rc);
+    Carver c(nullptr, 0);
+    const int64_t nn = n > 0 ? n : 1;
+    c.take<int32_t>(nn);          // d0
+    c.take<int32_t>(nn + 1);      // rpu
+    c.take<int64_t>(1);           // 2|E0|
+    c.take<char>(partition_ws_bytes(n, nnz));
+    *h_ws_bytes = c.used();
+    return fail(TC_OK);
+}
+
+int tc_partition(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
+                 int32_t *d_rp0, int32_t *d_c0, int32_t *d_up0, int32_t *d_rp1, int32_t *d_c1, int64_t *h_e0,
+                 void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
+    if (rc != TC_OK) return fail(rc);
+    if (!d_rp0 || !d_rp1 || !h_e0 || (n > 0 && (!d_levels || !d_up0)) || (nnz > 0 && (!d_c0 || !d_c1)))
+        return fail(TC_ERR_ARG);
+    size_t need = 0;
+    tc_partition_ws(n, nnz, &need);
+    rc = check_ws(ws, ws_bytes, need);
+    if (rc != TC_OK) return fail(rc);
+    DeviceInfo di;
+    rc = device_info(&di);
+    if (rc != TC_OK) return fail(rc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n == 0) {   // empty graph: both row-pointer arrays are {0}
+        if (hipMemsetAsync(d_rp0, 0, sizeof(int32_t), s) != hipSuccess ||
+            hipMemsetAsync(d_rp1, 0, sizeof(int32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return fail(TC_ERR_HIP);
+        *h_e0 = 0;
+        return fail(TC_OK);
+    }
+    Carver c(ws, ws_bytes);
+    const int64_t nn = n > 0 ? n : 1;
+    PartBufs pb;
+    pb.rp0 = d_rp0;
+    pb.c0 = d_c0;
+    pb.up0 = d_up0;
+    pb.rp1 = d_rp1;
+    pb.c1 = d_c1;
+    pb.d0 = c.take<int32_t>(nn);
+    pb.rpu = c.take<int32_t>(nn + 1);
+    pb.e0x2 = c.take<int64_t>(1);
+    void *scratch = c.take<char>(partition_ws_bytes(n, nnz));
+    rc = partition_run(n, nnz, d_row_ptr, d_col_idx, d_levels, pb, scratch, partition_ws_bytes(n, nnz), s);
+    if (rc != TC_OK) return fail(rc);
+    int64_t e0x2 = 0;
+    if (hipMemcpyAsync(&e0x2, pb.e0x2, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(TC_ERR_HIP);
+    *h_e0 = e0x2 / 2;
+    return fail(TC_OK);
+}
+
+int tc_count_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_bytes) {
+    if (!h_ws_bytes) return fail(TC_ERR_ARG);
+    int rc = check_graph_args(n, nnz, (const void *)1, (const void *)1);
+    if (rc != TC_OK) return fail(rc);
+    CountCfg cfg;
+    int flags;
+    rc = make_cfg(opt, &cfg, &flags);
+    if (rc != TC_OK) return fail(rc);
+    Carver c(nullptr, 0);
+    carve_plan(c, n, nnz, true);
+    *h_ws_bytes = c.used();
+    return fail(TC_OK);
+}
+
+uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
+                  const tc_options *opt, tc_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
+    if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
+    CountCfg cfg;
+    int flags;
+    rc = make_cfg(opt, &cfg, &flags);
+    if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
+    size_t need = 0;
+    {
+        Carver c(nullptr, 0);
+        carve_plan(c, n, nnz, true);
+        need = c.used();
+    }
+    rc = check_ws(ws, ws_bytes, need);
+    if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
+    DeviceInfo di;
+    rc = device_info(&di);
+    if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n == 0) {   // no vertices, no triangles
+        if (stats) memset(stats, 0, sizeof(*stats));
+        fail(TC_OK);
+        return 0;
+    }
+    Carver c(ws, ws_bytes);
+    CountPlan P = carve_plan(c, n, nnz, true);
+    if (flags & TC_VALIDATE) {
+        rc = validate_device(n, nnz, d_row_ptr, d_col_idx, d_levels, P.flag, s);
+        if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
+    }
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    const bool timing = (flags & TC_TIMING) != 0;
+    auto fail_ev = [&](int code) {
+        for (auto &e : ev) if (e) (void)hipEventDestroy(e);
+        fail(code);
+        return TC_COUNT_ERROR;
+    };
+    if (timing) {
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail_ev(TC_ERR_HIP);
+        if (hipEventRecord(ev[0], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
+    }
+    BfsOut bo;
+    const int32_t *lev = d_levels;
+    if (!lev) {
+        rc = bfs_run(n, nnz, d_row_ptr, d_col_idx, P.levels, &bo, P.scratch, P.scratch_bytes, s);
+        if (rc != TC_OK) return fail_ev(rc);
+        lev = P.levels;
+    }
+    if (timing && hipEventRecord(ev[1], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
+    rc = partition_run(n, nnz, d_row_ptr, d_col_idx, lev, P.pb, P.scratch, P.scratch_bytes, s);
+    if (rc != TC_OK) return fail_ev(rc);
+    if (timing && hipEventRecord(ev[2], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
+    CountOut co;
+    rc = count_run(n, nnz, P.pb, cfg, &co, P.scratch, P.scratch_bytes, s);
+    if (rc != TC_OK) return fail_ev(rc);
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->T0 = co.T0;
+        stats->T1 = co.T1;
+        int64_t e0x2 = 0;
+        if (hipMemcpyAsync(&e0x2, P.pb.e0x2, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail_ev(TC_ERR_HIP);
+        stats->e0 = e0x2 / 2;
+        stats->units = co.units;
+        stats->items = co.items;
+        stats->probes = co.probes;
+        stats->hashed = co.hashed;
+        stats->levels = bo.levels;
+        stats->bfs_rounds = bo.rounds;
+        for (int k = 0; k < TC_NUM_STRATEGIES; ++k) stats->strategy_items[k] = co.strategy_items[k];
+        if (timing) {
+            (void)hipEventElapsedTime(&stats->ms_bfs, ev[0], ev[1]);
+            (void)hipEventElapsedTime(&stats->ms_partition, ev[1], ev[2]);
+            stats->ms_bucket = co.ms_bucket;
+            stats->ms_isect = co.ms_isect;
+        }
+    }
+    for (auto &e : ev) if (e) (void)hipEventDestroy(e);
+    fail(TC_OK);
+    return co.T0 + co.T1;
+}
+
+}  // extern "C"

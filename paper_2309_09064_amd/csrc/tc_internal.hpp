@@ -1,0 +1,164 @@
+// Internal declarations shared by the HIP translation units of libtc.
+// Everything here is gfx950-only: 64-wide wavefronts, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/tc.h"
+
+namespace tc {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ errors
+
+void set_error(int code);
+int last_error();
+
+#define TC_HIP_TRY(expr)                                   \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) {                            \
+            ::tc::note_hip_error(e_, #expr, __FILE__, __LINE__); \
+            return TC_ERR_HIP;                             \
+        }                                                  \
+    } while (0)
+
+#define TC_TRY(expr)                  \
+    do {                              \
+        int rc_ = (expr);             \
+        if (rc_ != TC_OK) return rc_; \
+    } while (0)
+
+void note_hip_error(hipError_t e, const char *what, const char *file, int line);
+
+// ------------------------------------------------------------------ workspace
+
+// Carves 256-byte aligned pieces out of the caller's workspace.  With a NULL
+// base it only measures (used by the *_ws size queries), so the size query
+// and the real carving run the same code.
+struct Carver {
+    char *base;
+    size_t cap;
+    size_t off = 0;
+    Carver(void *b, size_t c) : base(static_cast<char *>(b)), cap(c) {}
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t used() const { return (off + 255) & ~size_t(255); }
+    bool fits() const { return used() <= cap; }
+};
+
+// ------------------------------------------------------------------ device info
+
+struct DeviceInfo {
+    int cus = 256;
+    int ok = 0;
+};
+int device_info(DeviceInfo *out);
+
+// ------------------------------------------------------------------ device helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T t = __shfl_up(v, d, kWave);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+
+// Orders LDS traffic between lanes of one wavefront (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Last r in [lo, hi] with rp[r] <= e (the CSR row that holds entry e).
+template <class P>
+__device__ __forceinline__ int64_t row_of(const P *rp, int64_t lo, int64_t hi, int64_t e) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)rp[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ scan
+
+// Exclusive prefix sum of n values (int32 or int64 input) into int32 or int64
+// output of n+1 entries (out[n] = total).  Three-level reduce-then-scan.
+size_t scan_ws_bytes(int64_t n);
+int scan_exclusive_i32_to_i32(const int32_t *in, int32_t *out, int64_t n, void *ws, hipStream_t s);
+int scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, void *ws, hipStream_t s);
+int scan_exclusive_i64_to_i64(const int64_t *in, int64_t *out, int64_t n, void *ws, hipStream_t s);
+
+// ------------------------------------------------------------------ phases
+
+// CSR build
+size_t build_csr_ws_bytes(int32_t n, int64_t m);
+int build_csr_run(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t *row_ptr,
+                  int32_t *col, int64_t col_cap, int64_t *h_nnz, void *ws, size_t ws_bytes,
+                  hipStream_t s);
+
+// BFS levels
+struct BfsOut {
+    int32_t levels = 0;
+    int32_t rounds = 0;
+};
+size_t bfs_ws_bytes(int32_t n, int64_t nnz);
+int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32_t *lev, BfsOut *out,
+            void *ws, size_t ws_bytes, hipStream_t s);
+
+// Partition into N0 (rank-split rows) and N1
+struct PartBufs {
+    int32_t *rp0, *c0, *up0, *rp1, *c1;   // outputs (rp* are n+1)
+    int32_t *d0;                          // n: |N0(x)|
+    int32_t *rpu;                         // n+1: prefix of up0
+    int64_t *e0x2;                        // device scalar: 2|E0|
+};
+size_t partition_ws_bytes(int32_t n, int64_t nnz);
+int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, const int32_t *lev,
+                  const PartBufs &pb, void *ws, size_t ws_bytes, hipStream_t s);
+
+// Counting phase (bucketize + intersect)
+struct CountOut {
+    uint64_t T0 = 0, T1 = 0;
+    int64_t units = 0, items = 0, probes = 0, hashed = 0;
+    int32_t strategy_items[TC_NUM_STRATEGIES] = {0, 0, 0, 0};
+    float ms_bucket = 0.f, ms_isect = 0.f;
+};
+struct CountCfg {
+    int schedule = TC_SCHED_HEURISTIC;
+    int force = TC_STRAT_AUTO;
+    int wave_slots = 2048;
+    int wg_slots = 16384;
+    int chunk_work = 16384;
+    int grid_blocks = 0;
+    int wave_max_owner = 0;
+    const int32_t *table = nullptr;   // device per-bucket strategies (schedule)
+    bool timing = false;
+};
+size_t count_ws_bytes(int32_t n, int64_t nnz);
+int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, CountOut *out,
+              void *ws, size_t ws_bytes, hipStream_t s);
+
+}  // namespace tc

@@ -1,0 +1,230 @@
+// Partition of the edge set (Algorithm 4, partition loop) into horizontal
+// edges E0 (equal levels) and the rest E1, compacted into two CSRs whose rows
+// keep the input order:
+//   N0(x) = [ neighbours y with L(y)=L(x) and rank(y) > rank(x) | the rest of
+//             the equal-level neighbours ],   rank(y) = (deg(y), y);
+//   N1(x) = neighbours y with L(y) != L(x).
+// The rank-above part N0+(x) is the forward algorithm's oriented list
+// (Algorithm 2 with degree ordering).
+//
+// Two coalesced passes over the CSR entries.  Pass 1 marks each entry
+// (horizontal, rank-above) into a byte, counts per row with atomics and per
+// 2048-entry block.  Pass 2 turns block offsets plus an in-block scan into the
+// number of horizontal / rank-above entries before every entry, which fixes
+// its destination without any per-row cursor:
+//   N1 entry at e     -> c1[e - H(e)]
+//   N0+ entry at e    -> c0[rp0[x] + U(e) - rpu[x]]
+//   other N0 entry    -> c0[H(e) - U(e) + rpu[x+1]]
+// where H(e), U(e) count horizontal and rank-above entries before e and rpu is
+// the prefix sum of |N0+|.
+#include "tc_internal.hpp"
+
+namespace tc {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRun = 8;
+constexpr int kBlockEntries = kThreads * kRun;
+constexpr int kWaves = kThreads / kWave;
+
+// rank(y) > rank(x) with rank = (degree, id), dx = deg(x)
+__device__ __forceinline__ bool rank_above(const int32_t *rp, int32_t y, int32_t x, int32_t dx) {
+    int32_t dy = rp[y + 1] - rp[y];
+    return dy > dx || (dy == dx && y > x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ col,
+                                                         const int32_t *__restrict__ lev,
+                                                         uint8_t *__restrict__ flags, int32_t *__restrict__ d0,
+                                                         int32_t *__restrict__ up0, int32_t *__restrict__ bh,
+                                                         int32_t *__restrict__ bu) {
+    __shared__ int32_t sh[kWaves], su[kWaves];
+    const int64_t e0 = (int64_t)blockIdx.x * kBlockEntries + (int64_t)threadIdx.x * kRun;
+    int32_t th = 0, tu = 0;
+    if (e0 < nnz) {
+        const int64_t e1 = e0 + kRun < nnz ? e0 + kRun : nnz;
+        int64_t x = row_of(rp, 0, n - 1, e0);
+        int64_t xe = rp[x + 1];
+        int32_t lx = lev[x], dx = (int32_t)(xe - rp[x]);
+        int32_t ch = 0, cu = 0;
+        uint8_t f[kRun];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) f[k] = 0;
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const int64_t e = e0 + k;
+            if (e < e1) {
+                while (e >= xe) {
+                    if (ch) atomicAdd(&d0[x], ch);
+                    if (cu) atomicAdd(&up0[x], cu);
+                    ch = cu = 0;
+                    ++x;
+                    xe = rp[x + 1];
+                    lx = lev[x];
+                    dx = (int32_t)(xe - rp[x]);
+                }
+                const int32_t y = col[e];
+                const bool hor = lev[y] == lx;
+                const bool up = hor && rank_above(rp, y, (int32_t)x, dx);
+                f[k] = (uint8_t)(hor | (up << 1));
+                ch += hor;
+                cu += up;
+            }
+        }
+        if (ch) atomicAdd(&d0[x], ch);
+        if (cu) atomicAdd(&up0[x], cu);
+        uint64_t word = 0;
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            word |= (uint64_t)f[k] << (8 * k);
+            th += f[k] & 1;
+            tu += f[k] >> 1;
+        }
+        if (e1 - e0 == kRun) {
+            *reinterpret_cast<uint64_t *>(flags + e0) = word;   // e0 is a multiple of 8
+        } else {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k)
+                if (e0 + k < e1) flags[e0 + k] = f[k];
+        }
+    }
+    th = wave_sum(th);
+    tu = wave_sum(tu);
+    if (lane_id() == 0) { sh[threadIdx.x / kWave] = th; su[threadIdx.x / kWave] = tu; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t a = 0, b = 0;
+        for (int i = 0; i < kWaves; ++i) { a += sh[i]; b += su[i]; }
+        bh[blockIdx.x] = a;
+        bu[blockIdx.x] = b;
+    }
+}
+
+__global__ void k_part_rp1(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ rp0,
+                           int32_t *__restrict__ rp1) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += (int64_t)gridDim.x * blockDim.x)
+        rp1[x] = rp[x] - rp0[x];
+}
+
+__global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ col,
+                                                            const uint8_t *__restrict__ flags,
+                                                            const int32_t *__restrict__ bh_off,
+                                                            const int32_t *__restrict__ bu_off,
+                                                            const int32_t *__restrict__ rp0,
+                                                            const int32_t *__restrict__ rpu,
+                                                            int32_t *__restrict__ c0, int32_t *__restrict__ c1) {
+    __shared__ int64_t wsum[kWaves];
+    const int64_t e0 = (int64_t)blockIdx.x * kBlockEntries + (int64_t)threadIdx.x * kRun;
+    const int64_t e1 = e0 < nnz ? (e0 + kRun < nnz ? e0 + kRun : nnz) : e0;
+    uint8_t f[kRun];
+    int64_t packed = 0;   // horizontal count << 32 | rank-above count
+    uint64_t word = 0;
+    if (e1 - e0 == kRun) {
+        word = *reinterpret_cast<const uint64_t *>(flags + e0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kRun; ++k)
+            if (e0 + k < e1) word |= (uint64_t)flags[e0 + k] << (8 * k);
+    }
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) {
+        f[k] = (uint8_t)(word >> (8 * k));
+        packed += ((int64_t)(f[k] & 1) << 32) | (int64_t)(f[k] >> 1);
+    }
+    // block exclusive scan of the packed counts
+    int64_t inc = wave_incl_scan(packed);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int64_t before = inc - packed;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    if (e0 >= e1) return;
+    int64_t H = (int64_t)bh_off[blockIdx.x] + (before >> 32);
+    int64_t U = (int64_t)bu_off[blockIdx.x] + (before & 0xffffffffll);
+    int64_t x = row_of(rp, 0, n - 1, e0);
+    int64_t xe = rp[x + 1];
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) {
+        const int64_t e = e0 + k;
+        if (e < e1) {
+            while (e >= xe) { ++x; xe = rp[x + 1]; }
+            const uint8_t fe = f[k];
+            const int32_t y = col[e];
+            if (fe & 1) {
+                if (fe & 2) c0[(int64_t)rp0[x] + U - rpu[x]] = y;
+                else c0[H - U + rpu[x + 1]] = y;
+            } else {
+                c1[e - H] = y;
+            }
+            H += fe & 1;
+            U += fe >> 1;
+        }
+    }
+}
+
+struct PartLayout {
+    uint8_t *flags;
+    int32_t *bh, *bu;
+    void *scan;
+};
+
+PartLayout carve_part(Carver &c, int32_t n, int64_t nnz) {
+    PartLayout L;
+    const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
+    L.flags = c.take<uint8_t>(nnz > 0 ? nnz : 1);
+    L.bh = c.take<int32_t>(nblk + 1);
+    L.bu = c.take<int32_t>(nblk + 1);
+    int64_t big = (int64_t)n + 1 > nblk ? (int64_t)n + 1 : nblk;
+    L.scan = c.take<char>(scan_ws_bytes(big));
+    return L;
+}
+
+unsigned grid_for(int64_t work, int threads) {
+    int64_t g = (work + threads - 1) / threads;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+size_t partition_ws_bytes(int32_t n, int64_t nnz) {
+    Carver c(nullptr, 0);
+    carve_part(c, n, nnz);
+    return c.used();
+}
+
+int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, const int32_t *lev,
+                  const PartBufs &pb, void *ws, size_t ws_bytes, hipStream_t s) {
+    Carver c(ws, ws_bytes);
+    PartLayout L = carve_part(c, n, nnz);
+    if (!c.fits()) return TC_ERR_WORKSPACE;
+    TC_HIP_TRY(hipMemsetAsync(pb.d0, 0, sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
+    TC_HIP_TRY(hipMemsetAsync(pb.up0, 0, sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
+    const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_part_mark, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, lev, L.flags,
+                           pb.d0, pb.up0, L.bh, L.bu);
+        TC_HIP_TRY(hipGetLastError());
+    }
+    TC_TRY(scan_exclusive_i32_to_i32(pb.d0, pb.rp0, n, L.scan, s));
+    TC_TRY(scan_exclusive_i32_to_i32(pb.up0, pb.rpu, n, L.scan, s));
+    hipLaunchKernelGGL(k_part_rp1, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, n, rp, pb.rp0, pb.rp1);
+    TC_HIP_TRY(hipGetLastError());
+    if (nnz > 0) {
+        TC_TRY(scan_exclusive_i32_to_i32(L.bh, L.bh, nblk, L.scan, s));
+        TC_TRY(scan_exclusive_i32_to_i32(L.bu, L.bu, nblk, L.scan, s));
+        hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, L.flags,
+                           L.bh, L.bu, pb.rp0, pb.rpu, pb.c0, pb.c1);
+        TC_HIP_TRY(hipGetLastError());
+    }
+    if (pb.e0x2) {
+        TC_HIP_TRY(hipMemsetAsync(pb.e0x2, 0, sizeof(int64_t), s));
+        TC_HIP_TRY(hipMemcpyAsync(pb.e0x2, pb.rp0 + n, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    return TC_OK;
+}
+
+}  // namespace tc

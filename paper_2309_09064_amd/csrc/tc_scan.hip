@@ -1,0 +1,116 @@
+// Device-wide exclusive prefix sums (reduce-then-scan, three levels at most).
+// A tile is 256 threads x 8 consecutive values; sums are kept in int64.
+#include "tc_internal.hpp"
+
+namespace tc {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPer = 8;
+constexpr int kTile = kThreads * kPer;
+constexpr int kWaves = kThreads / kWave;
+
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *total) {
+    __shared__ int64_t wsum[kWaves];
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    int64_t inc = wave_incl_scan(v);
+    if (lane_id() == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        int64_t s = wsum[i];
+        before += (i < w) ? s : 0;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+template <class Tin>
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const Tin *__restrict__ in, int64_t n,
+                                                           int64_t *__restrict__ sums) {
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kPer;
+    int64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        int64_t idx = base + i;
+        if (idx < n) acc += (int64_t)in[idx];
+    }
+    int64_t tot;
+    (void)block_excl_scan(acc, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+template <class Tin, class Tout>
+__global__ __launch_bounds__(kThreads) void k_scan_apply(const Tin *in, int64_t n, const int64_t *offs,
+                                                          Tout *out) {
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kPer;
+    int64_t v[kPer];
+    int64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        int64_t idx = base + i;
+        v[i] = (idx < n) ? (int64_t)in[idx] : 0;
+        acc += v[i];
+    }
+    int64_t tot;
+    int64_t run = block_excl_scan(acc, &tot);
+    const int64_t off = offs ? offs[blockIdx.x] : 0;
+    run += off;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        int64_t idx = base + i;
+        if (idx < n) out[idx] = (Tout)run;
+        run += v[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = (Tout)(off + tot);
+}
+
+int64_t nblocks(int64_t n) { return (n + kTile - 1) / kTile; }
+
+template <class Tin, class Tout>
+int scan_impl(const Tin *in, Tout *out, int64_t n, int64_t *ws, hipStream_t s) {
+    if (n <= kTile) {
+        hipLaunchKernelGGL((k_scan_apply<Tin, Tout>), dim3(1), dim3(kThreads), 0, s, in, n,
+                           (const int64_t *)nullptr, out);
+        TC_HIP_TRY(hipGetLastError());
+        return TC_OK;
+    }
+    const int64_t nb = nblocks(n);
+    int64_t *sums = ws;                 // nb + 1 entries
+    int64_t *rest = ws + ((nb + 1 + 31) & ~int64_t(31));
+    hipLaunchKernelGGL((k_scan_reduce<Tin>), dim3((unsigned)nb), dim3(kThreads), 0, s, in, n, sums);
+    TC_HIP_TRY(hipGetLastError());
+    TC_TRY((scan_impl<int64_t, int64_t>(sums, sums, nb, rest, s)));
+    hipLaunchKernelGGL((k_scan_apply<Tin, Tout>), dim3((unsigned)nb), dim3(kThreads), 0, s, in, n,
+                       (const int64_t *)sums, out);
+    TC_HIP_TRY(hipGetLastError());
+    return TC_OK;
+}
+
+}  // namespace
+
+size_t scan_ws_bytes(int64_t n) {
+    size_t total = 0;
+    while (n > kTile) {
+        int64_t nb = nblocks(n);
+        total += (size_t)((nb + 1 + 31) & ~int64_t(31)) * sizeof(int64_t);
+        n = nb;
+    }
+    return total + 256;
+}
+
+int scan_exclusive_i32_to_i32(const int32_t *in, int32_t *out, int64_t n, void *ws, hipStream_t s) {
+    return scan_impl<int32_t, int32_t>(in, out, n, static_cast<int64_t *>(ws), s);
+}
+int scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, void *ws, hipStream_t s) {
+    return scan_impl<int32_t, int64_t>(in, out, n, static_cast<int64_t *>(ws), s);
+}
+int scan_exclusive_i64_to_i64(const int64_t *in, int64_t *out, int64_t n, void *ws, hipStream_t s) {
+    return scan_impl<int64_t, int64_t>(in, out, n, static_cast<int64_t *>(ws), s);
+}
+
+}  // namespace tc
