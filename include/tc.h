@@ -92,12 +92,13 @@ typedef struct tc_options {
                                  TC_STRAT_BSEARCH)                           */
     int32_t flags;            /* tc_flags bits                               */
     int32_t wave_slots;       /* LDS hash slots per wavefront (power of 2,
-                                 64..4096); 0 = default 2048                 */
+                                 64..2048); 0 = default 2048                 */
     int32_t wg_slots;         /* LDS hash slots per workgroup (power of 2,
-                                 1024..32768); 0 = default 16384             */
+                                 1024..32768); 0 = default 32768             */
     int32_t chunk_work;       /* target probe elements per work item;
                                  0 = default 16384                           */
-    int32_t grid_blocks;      /* persistent grid size; 0 = 2 per CU          */
+    int32_t grid_blocks;      /* persistent grid size; 0 = as many 1024-thread
+                                 blocks as fit in LDS, at most 2 per CU      */
     int32_t wave_max_owner;   /* heuristic: largest owner list for the
                                  wavefront hash; 0 = wave_slots / 2          */
 } tc_options;

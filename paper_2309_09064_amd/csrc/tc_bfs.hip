@@ -12,7 +12,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kRun = 8;           // CSR entries per thread in edge passes
-constexpr int kSamples = 1024;
+constexpr int kSamples = 256;
 
 __device__ __forceinline__ void link(int32_t *comp, int32_t u, int32_t v) {
     int32_t p1 = comp[u], p2 = comp[v];
@@ -48,50 +48,33 @@ __global__ void k_cc_compress(int32_t n, int32_t *comp) {
     }
 }
 
-// Most frequent label among kSamples hashed vertices (one block).
+// Most frequent label among kSamples hashed vertices (one block): every
+// thread counts the samples equal to its own, ties go to the smaller label.
 __global__ __launch_bounds__(kSamples) void k_cc_sample_mode(int32_t n, const int32_t *comp, int32_t *giant) {
-    __shared__ int32_t s[kSamples];
-    __shared__ int32_t best_len[kSamples / kWave];
-    __shared__ int32_t best_val[kSamples / kWave];
+    __shared__ int32_t smp[kSamples];
+    __shared__ int64_t best[kSamples / kWave];
     const int t = threadIdx.x;
     uint32_t h = (uint32_t)t * 2654435761u + 0x9E3779B9u;
     h ^= h >> 15;
     h *= 2246822519u;
     h ^= h >> 13;
-    s[t] = comp[(int64_t)h % n];
+    smp[t] = comp[(int64_t)h % n];
     __syncthreads();
-    for (int k = 2; k <= kSamples; k <<= 1) {         // bitonic sort
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            int p = t ^ j;
-            if (p > t) {
-                int32_t a = s[t], b = s[p];
-                bool up = (t & k) == 0;
-                if ((a > b) == up) { s[t] = b; s[p] = a; }
-            }
-            __syncthreads();
-        }
-    }
-    // run length ending at t, if t ends a run
-    int len = 0;
-    if (t == kSamples - 1 || s[t] != s[t + 1]) {
-        int i = t;
-        while (i >= 0 && s[i] == s[t]) --i;
-        len = t - i;
-    }
-    int32_t val = s[t];
+    const int32_t mine = smp[t];
+    int32_t c = 0;
+    for (int i = 0; i < kSamples; ++i) c += smp[i] == mine;
+    // larger count wins, then smaller label: pack as (count, -label)
+    int64_t key = ((int64_t)c << 32) | (uint32_t)(0x7fffffff - mine);
     for (int d = kWave / 2; d > 0; d >>= 1) {
-        int ol = __shfl_xor(len, d, kWave);
-        int32_t ov = __shfl_xor(val, d, kWave);
-        if (ol > len || (ol == len && ov < val)) { len = ol; val = ov; }
+        int64_t o = __shfl_xor(key, d, kWave);
+        key = o > key ? o : key;
     }
-    if (lane_id() == 0) { best_len[t / kWave] = len; best_val[t / kWave] = val; }
+    if (lane_id() == 0) best[t / kWave] = key;
     __syncthreads();
     if (t == 0) {
-        int bl = -1;
-        int32_t bv = 0;
-        for (int i = 0; i < kSamples / kWave; ++i)
-            if (best_len[i] > bl || (best_len[i] == bl && best_val[i] < bv)) { bl = best_len[i]; bv = best_val[i]; }
-        *giant = bv;
+        int64_t b = best[0];
+        for (int i = 1; i < kSamples / kWave; ++i) b = best[i] > b ? best[i] : b;
+        *giant = 0x7fffffff - (int32_t)(b & 0xffffffff);
     }
 }
 
@@ -100,42 +83,43 @@ __global__ __launch_bounds__(kSamples) void k_cc_sample_mode(int32_t n, const in
 __global__ __launch_bounds__(kThreads) void k_cc_link_rest(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ col, const int32_t *giant,
                                                             int32_t *comp) {
+    __shared__ int64_t rows[2];
     const int32_t g = *giant;
-    const int64_t nruns = (nnz + kRun - 1) / kRun;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e0 = r * kRun;
-        const int64_t e1 = e0 + kRun < nnz ? e0 + kRun : nnz;
-        int64_t x = row_of(rp, 0, n - 1, e0);
-        int64_t xe = rp[x + 1];
-        bool skip = comp[x] == g;
-        for (int64_t e = e0; e < e1; ++e) {
-            while (e >= xe) { ++x; xe = rp[x + 1]; skip = comp[x] == g; }
-            if (!skip && e - rp[x] >= 2) link(comp, (int32_t)x, col[e]);
+    constexpr int64_t kTile = (int64_t)kThreads * kRun;
+    for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < nnz; t0 += (int64_t)gridDim.x * kTile) {
+        tile_rows(rp, n, t0, t0 + kTile < nnz ? t0 + kTile : nnz, rows);
+        const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
+        if (e0 < nnz) {
+            const int64_t e1 = e0 + kRun < nnz ? e0 + kRun : nnz;
+            int64_t x = row_of(rp, rows[0], rows[1], e0);
+            int64_t xe = rp[x + 1];
+            bool skip = comp[x] == g;
+            for (int64_t e = e0; e < e1; ++e) {
+                while (e >= xe) { ++x; xe = rp[x + 1]; skip = comp[x] == g; }
+                if (!skip && e - rp[x] >= 2) link(comp, (int32_t)x, col[e]);
+            }
         }
+        __syncthreads();   // `rows` is rewritten for the next tile
     }
 }
 
-// Level 0: roots (label == own id).  Roots with edges seed the frontier.
-__global__ void k_bfs_init(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ comp,
-                           int32_t *__restrict__ lev, int32_t *__restrict__ front, int32_t *__restrict__ fcount) {
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = base + threadIdx.x;
-        bool seed = false;
-        if (v < n) {
-            bool root = comp[v] == (int32_t)v;
-            lev[v] = root ? 0 : -1;
-            seed = root && rp[v + 1] > rp[v];
-        }
-        uint64_t bal = __ballot(seed);
-        int32_t wbase = 0;
-        if (lane_id() == 0 && bal) wbase = atomicAdd(fcount, __popcll(bal));
-        wbase = __shfl(wbase, 0, kWave);
-        if (seed) {
-            int l = lane_id();
-            uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));
-            front[wbase + __popcll(bal & lt)] = (int32_t)v;
-        }
-    }
+// Level 0: the roots (label == own id); every other vertex starts unvisited.
+__global__ void k_bfs_init(int32_t n, const int32_t *__restrict__ comp, int32_t *__restrict__ lev) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        lev[v] = comp[v] == (int32_t)v ? 0 : -1;
+}
+
+// Frontier of `level`: flag[v] = 1 for vertices on that level with an edge.
+__global__ void k_level_flags(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ lev,
+                              int32_t level, int32_t *__restrict__ flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        flag[v] = lev[v] == level && rp[v + 1] > rp[v];
+}
+
+__global__ void k_compact(int32_t n, const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
+                          int32_t *__restrict__ front) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        if (flag[v]) front[pos[v]] = (int32_t)v;
 }
 
 __global__ void k_front_deg(int32_t f, const int32_t *__restrict__ front, const int32_t *__restrict__ rp,
@@ -147,45 +131,73 @@ __global__ void k_front_deg(int32_t f, const int32_t *__restrict__ front, const 
 }
 
 // Top-down expansion over the concatenated adjacency of the frontier: each
-// thread takes kRun consecutive (frontier vertex, neighbour) pairs.
+// thread takes kRun consecutive (frontier vertex, neighbour) pairs and sets
+// unvisited neighbours to the next level.  Every writer stores the same
+// value, so plain stores suffice.
 __global__ __launch_bounds__(kThreads) void k_bfs_expand(int32_t f, const int32_t *__restrict__ front,
                                                           const int64_t *__restrict__ fpre,
                                                           const int32_t *__restrict__ rp,
                                                           const int32_t *__restrict__ col, int32_t next_level,
-                                                          int32_t *lev, int32_t *__restrict__ next,
-                                                          int32_t *__restrict__ ncount) {
+                                                          int32_t *lev) {
+    __shared__ int64_t rows[2];
     const int64_t E = fpre[f];
-    const int64_t nruns = (E + kRun - 1) / kRun;
-    const int l = lane_id();
-    const uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t rb = (int64_t)blockIdx.x * blockDim.x; rb < nruns; rb += stride) {
-        const int64_t r = rb + threadIdx.x;
-        const bool active = r < nruns;
-        int64_t e0 = r * kRun;
-        int64_t i = 0, iend = 0, base = 0;
-        if (active) {
-            i = row_of(fpre, 0, f - 1, e0);
-            iend = fpre[i + 1];
-            base = (int64_t)rp[front[i]] - fpre[i];
-        }
-        for (int k = 0; k < kRun; ++k) {
-            const int64_t e = e0 + k;
-            bool found = false;
-            int32_t w = 0;
-            if (active && e < E) {
+    constexpr int64_t kTile = (int64_t)kThreads * kRun;
+    for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < E; t0 += (int64_t)gridDim.x * kTile) {
+        tile_rows(fpre, f, t0, t0 + kTile < E ? t0 + kTile : E, rows);
+        const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
+        if (e0 < E) {
+            const int64_t e1 = e0 + kRun < E ? e0 + kRun : E;
+            int64_t i = row_of(fpre, rows[0], rows[1], e0);
+            int64_t iend = fpre[i + 1];
+            int64_t base = (int64_t)rp[front[i]] - fpre[i];
+            for (int64_t e = e0; e < e1; ++e) {
                 while (e >= iend) { ++i; iend = fpre[i + 1]; base = (int64_t)rp[front[i]] - fpre[i]; }
-                w = col[base + e];
-                if (lev[w] < 0 && atomicCAS(&lev[w], -1, next_level) == -1) found = true;
-            }
-            uint64_t bal = __ballot(found);
-            if (bal) {
-                int32_t wbase = 0;
-                if (l == 0) wbase = atomicAdd(ncount, __popcll(bal));
-                wbase = __shfl(wbase, 0, kWave);
-                if (found) next[wbase + __popcll(bal & lt)] = w;
+                const int32_t w = col[base + e];
+                if (lev[w] < 0) lev[w] = next_level;
             }
         }
+        __syncthreads();   // `rows` is rewritten for the next tile
+    }
+}
+
+// Bottom-up step: every unvisited vertex looks for a neighbour on the current
+// level and stops at the first one.  Rows longer than kBigRow are scanned by
+// the whole wavefront, 64 neighbours per step.  A vertex set here holds
+// next_level != level, so concurrent readers looking for `level` are unaffected.
+constexpr int32_t kBigRow = 64;
+
+__global__ __launch_bounds__(kThreads) void k_bfs_bottom_up(int32_t n, const int32_t *__restrict__ rp,
+                                                             const int32_t *__restrict__ col, int32_t level,
+                                                             int32_t *lev) {
+    const int l = lane_id();
+    for (int64_t vb = (int64_t)blockIdx.x * blockDim.x; vb < n; vb += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = vb + threadIdx.x;
+        bool todo = false;
+        int32_t b = 0, e = 0;
+        if (v < n && lev[v] < 0) {
+            b = rp[v];
+            e = rp[v + 1];
+            todo = e > b;
+        }
+        const bool big = todo && e - b > kBigRow;
+        bool found = false;
+        if (todo && !big) {
+            for (int32_t j = b; j < e; ++j)
+                if (lev[col[j]] == level) { found = true; break; }
+        }
+        uint64_t bm = __ballot(big);
+        while (bm) {
+            const int src = __ffsll((unsigned long long)bm) - 1;
+            bm &= bm - 1;
+            const int32_t sb = __shfl(b, src, kWave), se = __shfl(e, src, kWave);
+            bool hit = false;
+            for (int32_t j = sb; j < se && !hit; j += kWave) {
+                const bool h = j + l < se && lev[col[j + l]] == level;
+                hit = __ballot(h) != 0;
+            }
+            if (l == src) found = hit;
+        }
+        if (found) lev[v] = level + 1;
     }
 }
 
@@ -197,7 +209,7 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65536) {
 }
 
 struct BfsLayout {
-    int32_t *comp, *fa, *fb, *fdeg, *cnt, *giant;
+    int32_t *comp, *front, *flag, *pos, *fdeg, *giant;
     int64_t *fpre;
     void *scan;
 };
@@ -206,11 +218,11 @@ BfsLayout carve_bfs(Carver &c, int32_t n) {
     BfsLayout L;
     const int64_t nn = n > 0 ? n : 1;
     L.comp = c.take<int32_t>(nn);
-    L.fa = c.take<int32_t>(nn);
-    L.fb = c.take<int32_t>(nn);
+    L.front = c.take<int32_t>(nn);
+    L.flag = c.take<int32_t>(nn);
+    L.pos = c.take<int32_t>(nn + 1);
     L.fdeg = c.take<int32_t>(nn);
     L.fpre = c.take<int64_t>(nn + 1);
-    L.cnt = c.take<int32_t>(64);
     L.giant = c.take<int32_t>(64);
     L.scan = c.take<char>(scan_ws_bytes(nn));
     return L;
@@ -248,27 +260,36 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
     hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(kThreads), 0, s, n, L.comp);
     TC_HIP_TRY(hipGetLastError());
 
-    TC_HIP_TRY(hipMemsetAsync(L.cnt, 0, 2 * sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_bfs_init, dim3(gv), dim3(kThreads), 0, s, n, rp, L.comp, lev, L.fa, L.cnt);
+    hipLaunchKernelGGL(k_bfs_init, dim3(gv), dim3(kThreads), 0, s, n, L.comp, lev);
     TC_HIP_TRY(hipGetLastError());
-    int32_t *cur = L.fa, *nxt = L.fb;
-    int ci = 0;
+    Mailbox mb;
+    TC_TRY(mailbox(&mb));
     int32_t level = 0, rounds = 0;
+    const unsigned gb = grid_for(n, kThreads, (int64_t)di.cus * 8);
     for (;;) {
-        int32_t f = 0;
-        TC_HIP_TRY(hipMemcpyAsync(&f, L.cnt + ci, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        // frontier of `level` (vertices with an edge), compacted in id order
+        hipLaunchKernelGGL(k_level_flags, dim3(gv), dim3(kThreads), 0, s, n, rp, lev, level, L.flag);
+        TC_HIP_TRY(hipGetLastError());
+        TC_TRY(scan_exclusive_i32_to_i32(L.flag, L.pos, n, L.scan, s));
+        TC_TRY(mail_i32(L.pos + n, mb.dev, s));
         TC_HIP_TRY(hipStreamSynchronize(s));
+        const int32_t f = (int32_t)mb.host[0];
         if (f == 0) break;
         ++rounds;
-        TC_HIP_TRY(hipMemsetAsync(L.cnt + (ci ^ 1), 0, sizeof(int32_t), s));
-        hipLaunchKernelGGL(k_front_deg, dim3(grid_for(f, kThreads)), dim3(kThreads), 0, s, f, cur, rp, L.fdeg);
-        TC_HIP_TRY(hipGetLastError());
-        TC_TRY(scan_exclusive_i32_to_i64(L.fdeg, L.fpre, f, L.scan, s));
-        hipLaunchKernelGGL(k_bfs_expand, dim3((unsigned)di.cus * 8), dim3(kThreads), 0, s, f, cur, L.fpre, rp,
-                           col, level + 1, lev, nxt, L.cnt + (ci ^ 1));
-        TC_HIP_TRY(hipGetLastError());
-        int32_t *t = cur; cur = nxt; nxt = t;
-        ci ^= 1;
+        if ((int64_t)f * 16 > (int64_t)n) {
+            // large frontier: bottom-up, every unvisited vertex checks its row
+            hipLaunchKernelGGL(k_bfs_bottom_up, dim3(gb), dim3(kThreads), 0, s, n, rp, col, level, lev);
+            TC_HIP_TRY(hipGetLastError());
+        } else {
+            hipLaunchKernelGGL(k_compact, dim3(gv), dim3(kThreads), 0, s, n, L.flag, L.pos, L.front);
+            hipLaunchKernelGGL(k_front_deg, dim3(grid_for(f, kThreads)), dim3(kThreads), 0, s, f, L.front, rp,
+                               L.fdeg);
+            TC_HIP_TRY(hipGetLastError());
+            TC_TRY(scan_exclusive_i32_to_i64(L.fdeg, L.fpre, f, L.scan, s));
+            hipLaunchKernelGGL(k_bfs_expand, dim3((unsigned)di.cus * 8), dim3(kThreads), 0, s, f, L.front, L.fpre,
+                               rp, col, level + 1, lev);
+            TC_HIP_TRY(hipGetLastError());
+        }
         ++level;
     }
     // `level` is the number of expansions; the last one found nothing unless

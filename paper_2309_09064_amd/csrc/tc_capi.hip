@@ -38,6 +38,42 @@ int device_info(DeviceInfo *out) {
 }
 
 namespace {
+thread_local Mailbox t_mail;
+
+__global__ void k_mail_u64(const uint64_t *src, uint64_t *dst, int count) {
+    if ((int)threadIdx.x < count) dst[threadIdx.x] = src[threadIdx.x];
+}
+__global__ void k_mail_i32(const int32_t *src, uint64_t *dst) {
+    if (threadIdx.x == 0) dst[0] = (uint64_t)(int64_t)src[0];
+}
+}  // namespace
+
+int mailbox(Mailbox *out) {
+    if (!t_mail.host) {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, 4096, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return TC_ERR_HIP;
+        void *d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) return TC_ERR_HIP;
+        t_mail.host = static_cast<uint64_t *>(h);
+        t_mail.dev = static_cast<uint64_t *>(d);
+    }
+    *out = t_mail;
+    return TC_OK;
+}
+
+int mail_u64(const uint64_t *src, uint64_t *dst, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_mail_u64, dim3(1), dim3(64), 0, s, src, dst, count);
+    TC_HIP_TRY(hipGetLastError());
+    return TC_OK;
+}
+
+int mail_i32(const int32_t *src, uint64_t *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_mail_i32, dim3(1), dim3(64), 0, s, src, dst);
+    TC_HIP_TRY(hipGetLastError());
+    return TC_OK;
+}
+
+namespace {
 
 // ---------------------------------------------------------------- validation
 
@@ -102,7 +138,7 @@ int make_cfg(const tc_options *opt, CountCfg *cfg, int *flags) {
     if (opt) {
         if (opt->schedule != TC_SCHED_HEURISTIC && opt->schedule != TC_SCHED_MLP) return TC_ERR_ARG;
         if (opt->force_strategy < TC_STRAT_AUTO || opt->force_strategy >= TC_NUM_STRATEGIES) return TC_ERR_ARG;
-        if (opt->wave_slots && (!is_pow2(opt->wave_slots) || opt->wave_slots < 64 || opt->wave_slots > 4096))
+        if (opt->wave_slots && (!is_pow2(opt->wave_slots) || opt->wave_slots < 64 || opt->wave_slots > 2048))
             return TC_ERR_ARG;
         if (opt->wg_slots && (!is_pow2(opt->wg_slots) || opt->wg_slots < 1024 || opt->wg_slots > 32768))
             return TC_ERR_ARG;
@@ -114,10 +150,11 @@ int make_cfg(const tc_options *opt, CountCfg *cfg, int *flags) {
         if (opt->chunk_work) c.chunk_work = opt->chunk_work;
         c.grid_blocks = opt->grid_blocks;
         c.wave_max_owner = opt->wave_max_owner;
+        if (opt->flags & ~(TC_VALIDATE | TC_TIMING)) return TC_ERR_ARG;
         *flags = opt->flags;
     }
-    // the eight wavefront tables of a block share the workgroup's LDS
-    if (c.wave_slots * 8 > 32768) return TC_ERR_ARG;
+    // the sixteen wavefront tables of a block share the workgroup's LDS
+    if (c.wave_slots * 16 > 32768) return TC_ERR_ARG;
     c.timing = (*flags & TC_TIMING) != 0;
     *cfg = c;
     return TC_OK;
@@ -159,11 +196,14 @@ CountPlan carve_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels) {
     const int64_t nn = n > 0 ? n : 1;
     const int64_t nz = nnz > 0 ? nnz : 1;
     P.levels = own_levels ? c.take<int32_t>(nn) : nullptr;
+    // the list arrays get kListPad ints of padding on both sides: the
+    // intersection kernel reads whole 8-element runs that may straddle a
+    // list's ends (never used, always inside the allocation)
     P.pb.rp0 = c.take<int32_t>(nn + 1);
-    P.pb.c0 = c.take<int32_t>(nz);
+    P.pb.c0 = c.take<int32_t>(nz + 2 * kListPad) + (c.base ? kListPad : 0);
     P.pb.up0 = c.take<int32_t>(nn);
     P.pb.rp1 = c.take<int32_t>(nn + 1);
-    P.pb.c1 = c.take<int32_t>(nz);
+    P.pb.c1 = c.take<int32_t>(nz + 2 * kListPad) + (c.base ? kListPad : 0);
     P.pb.d0 = c.take<int32_t>(nn);
     P.pb.rpu = c.take<int32_t>(nn + 1);
     P.pb.e0x2 = c.take<int64_t>(1);
@@ -388,11 +428,7 @@ uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_
         memset(stats, 0, sizeof(*stats));
         stats->T0 = co.T0;
         stats->T1 = co.T1;
-        int64_t e0x2 = 0;
-        if (hipMemcpyAsync(&e0x2, P.pb.e0x2, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return fail_ev(TC_ERR_HIP);
-        stats->e0 = e0x2 / 2;
+        stats->e0 = co.e0x2 / 2;
         stats->units = co.units;
         stats->items = co.items;
         stats->probes = co.probes;

@@ -17,6 +17,9 @@
 // wavefront items (each wavefront has a private LDS table, or searches the
 // owner list in global memory).  Every strategy computes the same exact
 // integer, so the schedule never changes a count.
+#include <stdio.h>
+#include <stdlib.h>
+
 #include "tc_internal.hpp"
 
 namespace tc {
@@ -24,10 +27,13 @@ namespace {
 
 constexpr int kRun = 8;                 // CSR entries per thread in row passes
 constexpr int kThreads = 256;
-constexpr int kIsectThreads = 512;      // 8 wavefronts per persistent block
+constexpr int kIsectThreads = 1024;     // 16 wavefronts per persistent block
 constexpr int kIsectWaves = kIsectThreads / kWave;
 constexpr int kBuckets = 2 * 32 * 32;
-constexpr int kMinPartnersPerItem = 8;
+constexpr int kOwnRowsMax = 512;           // rows a tile may span and still count in LDS
+constexpr int kMinPartnersPerItem = 8;     // wavefront items
+constexpr int kMinPartnersPerWgItem = 4096; // workgroup items
+constexpr int kWgItemWaves = 4 * kIsectWaves; // a workgroup item holds this many wavefront items of work
 constexpr int32_t kEmpty = -1;
 
 struct Item {
@@ -91,60 +97,113 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
                                                    const int32_t *__restrict__ c0, const int32_t *__restrict__ up0,
                                                    const int32_t *__restrict__ rp1, int32_t *__restrict__ cnt,
                                                    unsigned long long *__restrict__ work) {
+    __shared__ int64_t rows[2];
+    __shared__ int32_t acc_n[2][kOwnRowsMax];
+    __shared__ unsigned long long acc_w[2][kOwnRowsMax];
     const int64_t e0x2 = *e0x2p;
-    const int64_t nruns = (e0x2 + kRun - 1) / kRun;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e0 = r * kRun;
-        const int64_t e1 = e0 + kRun < e0x2 ? e0 + kRun : e0x2;
-        int64_t x = row_of(rp0, 0, n - 1, e0);
-        int64_t xe = rp0[x + 1];
-        int32_t s0x = up0[x], s1x = rp1[x + 1] - rp1[x];
-        int32_t n0 = 0, n1 = 0;
-        unsigned long long w0 = 0, w1 = 0;
-        auto flush = [&]() {
-            if (n0) { atomicAdd(&cnt[2 * x], n0); atomicAdd(&work[2 * x], w0); }
-            if (n1) { atomicAdd(&cnt[2 * x + 1], n1); atomicAdd(&work[2 * x + 1], w1); }
-            n0 = n1 = 0;
-            w0 = w1 = 0;
-        };
-        for (int64_t e = e0; e < e1; ++e) {
-            while (e >= xe) {
-                flush();
-                ++x;
-                xe = rp0[x + 1];
-                s0x = up0[x];
-                s1x = rp1[x + 1] - rp1[x];
+    constexpr int64_t kTile = (int64_t)kThreads * kRun;
+    for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < e0x2; t0 += (int64_t)gridDim.x * kTile) {
+        tile_rows(rp0, n, t0, t0 + kTile < e0x2 ? t0 + kTile : e0x2, rows);
+        const int64_t r_lo = rows[0], r_hi = rows[1];
+        const int64_t nr = r_hi - r_lo + 1;
+        const bool local = nr <= kOwnRowsMax;   // count in LDS, flush once per row
+        if (local)
+            for (int64_t i = threadIdx.x; i < nr; i += kThreads) {
+                acc_n[0][i] = acc_n[1][i] = 0;
+                acc_w[0][i] = acc_w[1][i] = 0;
             }
-            const int32_t y = c0[e];
-            const int32_t s0y = up0[y], s1y = rp1[y + 1] - rp1[y];
-            if (owns(s0x, s0y, (int32_t)x, y)) { ++n0; w0 += (unsigned)s0y; }
-            if (owns(s1x, s1y, (int32_t)x, y)) { ++n1; w1 += (unsigned)s1y; }
+        __syncthreads();
+        const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
+        if (e0 < e0x2) {
+            const int64_t e1 = e0 + kRun < e0x2 ? e0 + kRun : e0x2;
+            int64_t x = row_of(rp0, r_lo, r_hi, e0);
+            int64_t xe = rp0[x + 1];
+            int32_t s0x = up0[x], s1x = rp1[x + 1] - rp1[x];
+            int32_t n0 = 0, n1 = 0;
+            unsigned long long w0 = 0, w1 = 0;
+            auto flush = [&]() {
+                if (local) {
+                    const int64_t i = x - r_lo;
+                    if (n0) { atomicAdd(&acc_n[0][i], n0); atomicAdd(&acc_w[0][i], w0); }
+                    if (n1) { atomicAdd(&acc_n[1][i], n1); atomicAdd(&acc_w[1][i], w1); }
+                } else {
+                    if (n0) { atomicAdd(&cnt[2 * x], n0); atomicAdd(&work[2 * x], w0); }
+                    if (n1) { atomicAdd(&cnt[2 * x + 1], n1); atomicAdd(&work[2 * x + 1], w1); }
+                }
+                n0 = n1 = 0;
+                w0 = w1 = 0;
+            };
+            for (int64_t e = e0; e < e1; ++e) {
+                while (e >= xe) {
+                    flush();
+                    ++x;
+                    xe = rp0[x + 1];
+                    s0x = up0[x];
+                    s1x = rp1[x + 1] - rp1[x];
+                }
+                const int32_t y = c0[e];
+                const int32_t s0y = up0[y], s1y = rp1[y + 1] - rp1[y];
+                if (owns(s0x, s0y, (int32_t)x, y)) { ++n0; w0 += (unsigned)s0y; }
+                if (owns(s1x, s1y, (int32_t)x, y)) { ++n1; w1 += (unsigned)s1y; }
+            }
+            flush();
         }
-        flush();
+        __syncthreads();
+        if (local) {
+            for (int64_t i = threadIdx.x; i < nr; i += kThreads) {
+                const int64_t r = r_lo + i;
+                const bool edge = r == r_lo || r == r_hi;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int32_t c = acc_n[k][i];
+                    if (edge) {
+                        if (c) { atomicAdd(&cnt[2 * r + k], c); atomicAdd(&work[2 * r + k], acc_w[k][i]); }
+                    } else {
+                        cnt[2 * r + k] = c;
+                        work[2 * r + k] = acc_w[k][i];
+                    }
+                }
+            }
+        }
+        __syncthreads();   // LDS is reused by the next tile
     }
 }
 
-// Items per unit; count pass (fill == 0) histograms items per bucket, fill
-// pass writes them.  Stats: [0] units, [1] probes, [2] hashed, [3..6] items
-// per strategy.
+// Items per unit.  The count pass (kFill = 0) histograms items per bucket;
+// the fill pass writes them.  A block handles 4096 units: LDS atomics order
+// the block's items inside each bucket, then one global atomic per (block,
+// bucket) reserves the block's range.  Stats: [0] units, [1] probes,
+// [2] hashed, [3..6] items per strategy.
+constexpr int kItemThreads = 1024;
+constexpr int kUnitsPerThread = 4;
+
 template <int kFill>
-__global__ __launch_bounds__(kThreads) void k_items(int32_t n, const int32_t *__restrict__ rp0,
-                                                     const int32_t *__restrict__ up0,
-                                                     const int32_t *__restrict__ rp1, const int32_t *__restrict__ cnt,
-                                                     const unsigned long long *__restrict__ work, SchedCfg sc,
-                                                     int32_t *__restrict__ bucket_items,
-                                                     const int32_t *__restrict__ bucket_off,
-                                                     int32_t *__restrict__ bucket_cur, Item *__restrict__ items,
-                                                     unsigned long long *__restrict__ stats) {
-    __shared__ int32_t hist[kFill ? 1 : kBuckets];
-    if (!kFill) {
-        for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) hist[i] = 0;
-        __syncthreads();
-    }
-    unsigned long long units = 0, probes = 0, hashed = 0, ps0 = 0, ps1 = 0, ps2 = 0, ps3 = 0;
+__global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t *__restrict__ rp0,
+                                                         const int32_t *__restrict__ up0,
+                                                         const int32_t *__restrict__ rp1,
+                                                         const int32_t *__restrict__ cnt,
+                                                         const unsigned long long *__restrict__ work, SchedCfg sc,
+                                                         int32_t *__restrict__ bucket_items,
+                                                         const int32_t *__restrict__ bucket_off,
+                                                         int32_t *__restrict__ bucket_cur, Item *__restrict__ items,
+                                                         unsigned long long *__restrict__ stats) {
+    __shared__ int32_t hist[kBuckets];
+    __shared__ int32_t bbase[kFill ? kBuckets : 1];
+    for (int i = threadIdx.x; i < kBuckets; i += kItemThreads) hist[i] = 0;
+    __syncthreads();
     const int64_t total = 2 * (int64_t)n;
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total; u += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = cnt[u];
+    const int64_t u0 = ((int64_t)blockIdx.x * kItemThreads + threadIdx.x) * kUnitsPerThread;
+    int bk[kUnitsPerThread], loc[kUnitsPerThread], st[kUnitsPerThread];
+    int32_t nchs[kUnitsPerThread];
+    unsigned long long units = 0, probes = 0, hashed = 0, ps0 = 0, ps1 = 0, ps2 = 0, ps3 = 0;
+#pragma unroll
+    for (int k = 0; k < kUnitsPerThread; ++k) {
+        const int64_t u = u0 + k;
+        bk[k] = -1;
+        nchs[k] = 0;
+        loc[k] = 0;
+        st[k] = 0;
+        const int32_t c = u < total ? cnt[u] : 0;
         if (c == 0) continue;
         const int32_t x = (int32_t)(u >> 1);
         const int kind = (int)(u & 1);
@@ -152,98 +211,209 @@ __global__ __launch_bounds__(kThreads) void k_items(int32_t n, const int32_t *__
         const int32_t sx = kind == 0 ? up0[x] : rp1[x + 1] - rp1[x];
         const int b = bucket_of(kind, sx, (int64_t)w, c);
         const int s = strategy_for(sc, b);
-        const int64_t target = (int64_t)sc.chunk_work * (s == TC_STRAT_WG_HASH ? kIsectWaves : 1);
+        const int64_t target = (int64_t)sc.chunk_work * (s == TC_STRAT_WG_HASH ? kWgItemWaves : 1);
         const int32_t jb = rp0[x], je = rp0[x + 1];
+        const int32_t minp = s == TC_STRAT_WG_HASH ? kMinPartnersPerWgItem : kMinPartnersPerItem;
         int64_t nch = ((int64_t)w + target - 1) / target;
-        const int64_t cap = (je - jb + kMinPartnersPerItem - 1) / kMinPartnersPerItem;
+        const int64_t cap = (je - jb + minp - 1) / minp;
         if (nch > cap) nch = cap;
         if (nch < 1) nch = 1;
+        bk[k] = b;
+        st[k] = s;
+        nchs[k] = (int32_t)nch;
+        loc[k] = atomicAdd(&hist[b], (int32_t)nch);
         if (!kFill) {
-            atomicAdd(&hist[b], (int32_t)nch);
+            const unsigned long long nc = (unsigned long long)nch;
             ++units;
             probes += w;
-            hashed += (unsigned long long)sx * (unsigned long long)nch;
-            const unsigned long long nc = (unsigned long long)nch;
+            hashed += (unsigned long long)sx * nc;
             ps0 += s == 0 ? nc : 0;
             ps1 += s == 1 ? nc : 0;
             ps2 += s == 2 ? nc : 0;
             ps3 += s == 3 ? nc : 0;
-        } else {
-            const int32_t pos = bucket_off[b] + atomicAdd(&bucket_cur[b], (int32_t)nch);
-            const int64_t len = je - jb;
-            for (int64_t k = 0; k < nch; ++k) {
-                Item it;
-                it.owner = x;
-                it.code = kind | (s << 1);
-                it.jb = jb + (int32_t)(len * k / nch);
-                it.je = jb + (int32_t)(len * (k + 1) / nch);
-                items[pos + k] = it;
-            }
         }
     }
+    __syncthreads();
     if (!kFill) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
+        for (int i = threadIdx.x; i < kBuckets; i += kItemThreads)
             if (hist[i]) atomicAdd(&bucket_items[i], hist[i]);
-        units = wave_sum(units);
-        probes = wave_sum(probes);
-        hashed = wave_sum(hashed);
-        ps0 = wave_sum(ps0);
-        ps1 = wave_sum(ps1);
-        ps2 = wave_sum(ps2);
-        ps3 = wave_sum(ps3);
-        if (lane_id() == 0) {
-            atomicAdd(&stats[0], units);
-            atomicAdd(&stats[1], probes);
-            atomicAdd(&stats[2], hashed);
-            atomicAdd(&stats[3], ps0);
-            atomicAdd(&stats[4], ps1);
-            atomicAdd(&stats[5], ps2);
-            atomicAdd(&stats[6], ps3);
+        __shared__ unsigned long long red[kItemThreads / kWave][7];
+        const unsigned long long v[7] = {wave_sum(units), wave_sum(probes), wave_sum(hashed), wave_sum(ps0),
+                                         wave_sum(ps1), wave_sum(ps2), wave_sum(ps3)};
+        if (lane_id() == 0)
+            for (int k = 0; k < 7; ++k) red[threadIdx.x / kWave][k] = v[k];
+        __syncthreads();
+        if (threadIdx.x < 7) {
+            unsigned long long a = 0;
+            for (int i = 0; i < kItemThreads / kWave; ++i) a += red[i][threadIdx.x];
+            if (a) atomicAdd(&stats[threadIdx.x], a);
+        }
+        return;
+    }
+    for (int i = threadIdx.x; i < kBuckets; i += kItemThreads)
+        bbase[i] = hist[i] ? bucket_off[i] + atomicAdd(&bucket_cur[i], hist[i]) : 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kUnitsPerThread; ++k) {
+        if (bk[k] < 0) continue;
+        const int64_t u = u0 + k;
+        const int32_t x = (int32_t)(u >> 1);
+        const int32_t jb = rp0[x], je = rp0[x + 1];
+        const int64_t len = je - jb;
+        const int32_t pos = bbase[bk[k]] + loc[k];
+        const int32_t code = (int32_t)(u & 1) | (st[k] << 1);
+        for (int32_t c = 0; c < nchs[k]; ++c) {
+            Item it;
+            it.owner = x;
+            it.code = code;
+            it.jb = jb + (int32_t)(len * c / nchs[k]);
+            it.je = jb + (int32_t)(len * (c + 1) / nchs[k]);
+            items[pos + c] = it;
         }
     }
 }
 
-// Queue layout (one thread): workgroup-table buckets first, then the rest;
-// inside each queue larger owners first.  q[2] = workgroup items, q[3] = all.
-__global__ void k_bucket_order(const int32_t *__restrict__ bucket_items, SchedCfg sc,
-                               int32_t *__restrict__ bucket_off, int32_t *__restrict__ q) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int32_t off = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int ob = 31; ob >= 0; --ob)
-            for (int pb = 31; pb >= 0; --pb)
-                for (int kind = 0; kind < 2; ++kind) {
-                    const int b = (kind * 32 + ob) * 32 + pb;
-                    const bool wg = strategy_for(sc, b) == TC_STRAT_WG_HASH;
-                    if (wg != (pass == 0)) continue;
-                    bucket_off[b] = off;
-                    off += bucket_items[b];
-                }
-        if (pass == 0) q[2] = off;
-    }
-    q[3] = off;
+// Queue layout: workgroup-table buckets first, then the rest; inside each
+// queue larger owners first.  One block: place every bucket's item count at
+// its queue position, exclusive-scan the 4096 positions, read offsets back.
+// q[2] = workgroup items, q[3] = all items.
+__device__ __forceinline__ int queue_pos(const SchedCfg &sc, int b) {
+    const int ob = (b >> 5) & 31, pb = b & 31, kind = b >> 10;
+    const bool wg = strategy_for(sc, b) == TC_STRAT_WG_HASH;
+    return (wg ? 0 : kBuckets) + ((31 - ob) * 32 + (31 - pb)) * 2 + kind;
+}
+
+__global__ __launch_bounds__(1024) void k_bucket_order(const int32_t *__restrict__ bucket_items, SchedCfg sc,
+                                                        int32_t *__restrict__ bucket_off, int32_t *__restrict__ q) {
+    __shared__ int32_t A[2 * kBuckets];
+    __shared__ int32_t wtot[16];
+    const int t = threadIdx.x;
+    for (int i = t; i < 2 * kBuckets; i += 1024) A[i] = 0;
+    __syncthreads();
+    for (int b = t; b < kBuckets; b += 1024) A[queue_pos(sc, b)] = bucket_items[b];
+    __syncthreads();
+    int32_t v[4];
+    int32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { v[j] = A[4 * t + j]; sum += v[j]; }
+    const int32_t inc = wave_incl_scan(sum);
+    if (lane_id() == kWave - 1) wtot[t / kWave] = inc;
+    __syncthreads();
+    int32_t run = inc - sum;
+    for (int i = 0; i < t / kWave; ++i) run += wtot[i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { A[4 * t + j] = run; run += v[j]; }
+    if (t == 1023) q[3] = run;
+    __syncthreads();
+    for (int b = t; b < kBuckets; b += 1024) bucket_off[b] = A[queue_pos(sc, b)];
+    if (t == 0) q[2] = A[kBuckets];
 }
 
 // ---------------------------------------------------------------- probes
 
-__device__ __forceinline__ uint32_t hash_slot(int32_t v, int shift) {
-    return ((uint32_t)v * 0x9E3779B1u) >> shift;
+// LDS hash table of 4-slot buckets (open addressing over buckets).  A key's
+// home bucket is a multiplicative hash of the id; slots of a bucket fill in
+// order, so a lookup that meets a bucket whose last slot is empty can stop.
+// Tables are sized so at most half the slots are used.
+struct HashTab {
+    int32_t *tab;
+    uint32_t bmask;   // buckets - 1
+    int shift;        // 32 - log2(buckets)
+};
+
+__device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots) {
+    HashTab t;
+    t.tab = tab;
+    t.bmask = (1u << (lg_slots - 2)) - 1;
+    t.shift = 32 - (lg_slots - 2);
+    return t;
 }
 
-__device__ __forceinline__ void hash_insert(int32_t *tab, uint32_t mask, int shift, int32_t v) {
-    uint32_t h = hash_slot(v, shift);
-    while (atomicCAS(&tab[h], kEmpty, v) != kEmpty) h = (h + 1) & mask;
+__device__ __forceinline__ uint32_t home_bucket(const HashTab &t, int32_t v) {
+    return ((uint32_t)v * 0x9E3779B1u) >> t.shift;
 }
 
-__device__ __forceinline__ uint32_t hash_has(const int32_t *tab, uint32_t mask, int shift, int32_t v) {
-    uint32_t h = hash_slot(v, shift);
+__device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
+    uint32_t b = home_bucket(t, v);
     for (;;) {
-        int32_t t = tab[h];
-        if (t == v) return 1u;
-        if (t == kEmpty) return 0u;
-        h = (h + 1) & mask;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (atomicCAS(&t.tab[4 * b + j], kEmpty, v) == kEmpty) return;
+        b = (b + 1) & t.bmask;
     }
+}
+
+// Membership of up to kPer keys (negative = absent slot), the lookups of all
+// keys interleaved so their LDS reads overlap.
+template <int kPer>
+__device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (&v)[kPer]) {
+    uint32_t b[kPer];
+    bool live[kPer];
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        live[u] = v[u] >= 0;
+        b[u] = home_bucket(t, v[u]);
+        any |= live[u];
+    }
+    uint32_t hits = 0;
+    while (any) {
+        int4 q[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (live[u]) q[u] = *reinterpret_cast<const int4 *>(&t.tab[4 * b[u]]);
+        any = false;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            if (!live[u]) continue;
+            const int32_t x = v[u];
+            if (q[u].x == x || q[u].y == x || q[u].z == x || q[u].w == x) {
+                ++hits;
+                live[u] = false;
+            } else if (q[u].w == kEmpty) {
+                live[u] = false;
+            } else {
+                b[u] = (b[u] + 1) & t.bmask;
+                any = true;
+            }
+        }
+    }
+    return hits;
+}
+
+// Lookups of the kPer keys of a window in two interleaved groups of four
+// (eight keys in flight would need twice the registers).
+template <class Group>
+__device__ __forceinline__ uint32_t in_fours(const int32_t (&v)[8], Group grp) {
+    const int32_t a[4] = {v[0], v[1], v[2], v[3]};
+    const int32_t b[4] = {v[4], v[5], v[6], v[7]};
+    return grp(a) + grp(b);
+}
+
+// Membership of up to kPer keys in a sorted global list by branch-free binary
+// search, the searches interleaved.
+template <int kPer>
+__device__ __forceinline__ uint32_t search_count(const int32_t *a, int32_t len, const int32_t (&v)[kPer]) {
+    int32_t base[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) base[u] = 0;
+    int32_t n = len;
+    while (n > 1) {
+        const int32_t half = n >> 1;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) base[u] = a[base[u] + half] < v[u] ? base[u] + half : base[u];
+        n -= half;
+    }
+    // base is now the last index whose element is below the key (or 0);
+    // the lower bound is one further when that element is below the key
+    uint32_t hits = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        if (v[u] < 0 || len <= 0) continue;
+        const int32_t lb = base[u] + (a[base[u]] < v[u] ? 1 : 0);
+        hits += (lb < len && a[lb] == v[u]) ? 1u : 0u;
+    }
+    return hits;
 }
 
 __device__ __forceinline__ uint32_t bsearch_has(const int32_t *a, int32_t len, int32_t v) {
@@ -296,51 +466,98 @@ struct Graph {
     const int32_t *rp0, *c0, *up0, *rp1, *c1;
 };
 
-// Streams every owned partner list of c0 positions [jb, je) of owner x
-// through `probe`; positions are split over `nw` cooperating wavefronts,
-// this wavefront being number `w`.
-template <class Probe>
-__device__ __forceinline__ uint32_t stream_partners(const Graph &g, int kind, int32_t x, int32_t sx, int32_t jb,
-                                                    int32_t je, int w, int nw, Probe probe) {
-    const int l = lane_id();
-    uint32_t hits = 0;
-    for (int32_t base = jb + w * kWave; base < je; base += nw * kWave) {
-        const int32_t p = base + l;
-        int32_t y = 0, sy = 0, yb = 0;
-        bool mine = false;
-        if (p < je) {
-            y = g.c0[p];
-            if (kind == 0) { sy = g.up0[y]; yb = g.rp0[y]; }
-            else { yb = g.rp1[y]; sy = g.rp1[y + 1] - yb; }
-            mine = owns(sx, sy, x, y);
-        }
-        uint64_t m = __ballot(mine);
-        const int32_t *lists = kind == 0 ? g.c0 : g.c1;
-        while (m) {
-            const int src = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            const int32_t len = __shfl(sy, src, kWave);
-            const int32_t *b = lists + __shfl(yb, src, kWave);
-            hits += probe(b, len);
-        }
+// Elements per lane per window step, and the per-wavefront LDS scratch used
+// to flatten a batch of partner lists: 64 * kPer marker bytes (window offset
+// o lives at byte (o % 64) * kPer + o / 64, so a lane reads its kPer window
+// slots with one load) and 64 partner records {start in the batch, list
+// offset}.
+constexpr int kPer = 8;
+constexpr int kScratchInts = 16 * kPer + 128;
+
+// Partner information for the c0 position p of owner x: is the edge owned
+// for this kind, and where is the partner's list.
+__device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p, int32_t je,
+                                           int32_t &sy, int32_t &yb) {
+    sy = 0;
+    yb = 0;
+    if (p >= je) return false;
+    const int32_t y = g.c0[p];
+    if (kind == 0) {
+        sy = g.up0[y];
+        yb = g.rp0[y];
+    } else {
+        yb = g.rp1[y];
+        sy = g.rp1[y + 1] - yb;
     }
+    return owns(sx, sy, x, y);
+}
+
+// Streams the owned partner lists among the 64 c0 positions starting at p0
+// through `count` (a functor over kPer keys).  The lists are concatenated
+// into one virtual array that the wavefront consumes 64 * kPer elements per
+// step (kPer loads in flight per lane); the list an element belongs to is
+// found from a ballot of the marked list starts in the window and a
+// popcount, O(1) per element.
+template <class Count>
+__device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p0,
+                                                 int32_t je, int32_t *scr, Count count) {
+    static_assert(kPer == 8, "a lane reads its window markers as one 64-bit word");
+    const int l = lane_id();
+    int32_t sy, yb;
+    const bool mine = partner_at(g, kind, x, sx, p0 + l, je, sy, yb);
+    const uint64_t m = __ballot(mine);
+    if (m == 0) return 0u;
+    uint8_t *marker = reinterpret_cast<uint8_t *>(scr);
+    int2 *pinfo = reinterpret_cast<int2 *>(scr + 16 * kPer);
+    const int32_t len = mine ? sy : 0;
+    const int32_t incl = wave_incl_scan(len);
+    const int32_t start = incl - len;
+    const int32_t total = __shfl(incl, kWave - 1, kWave);
+    if (mine) pinfo[__popcll(m & ((1ull << l) - 1))] = make_int2(start, yb);
+    const int32_t *lists = kind == 0 ? g.c0 : g.c1;
+    const uint64_t le = (l == kWave - 1) ? ~0ull : ((2ull << l) - 1);
+    uint32_t hits = 0;
+    int32_t before = 0;   // lists that start before the current window
+    for (int32_t base = 0; base < total; base += kPer * kWave) {
+        const int32_t o = start - base;
+        const bool mark = mine && o >= 0 && o < kPer * kWave;
+        const int mslot = (o & 63) * kPer + (o >> 6);
+        if (mark) marker[mslot] = 1;
+        wave_lds_sync();
+        const uint64_t mk = *reinterpret_cast<const uint64_t *>(marker + l * kPer);
+        wave_lds_sync();
+        if (mark) marker[mslot] = 0;
+        int32_t v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const uint64_t mw = __ballot((mk >> (8 * u)) & 0xffu);
+            const int32_t k = before + __popcll(mw & le) - 1;
+            before += __popcll(mw);
+            const int32_t f = base + u * kWave + l;
+            v[u] = -1;
+            if (f < total) {
+                const int2 pi = pinfo[k];
+                v[u] = lists[pi.y + f - pi.x];
+            }
+        }
+        hits += count(v);
+    }
+    wave_lds_sync();   // pinfo is rewritten by the next batch
     return hits;
 }
 
-// Probe a list with all lanes, four elements in flight per lane.
-template <class Has>
-__device__ __forceinline__ uint32_t probe_list(const int32_t *b, int32_t len, Has has) {
-    const int l = lane_id();
+// Merge strategy: partners one at a time, each merged against the owner list.
+__device__ __forceinline__ uint32_t merge_chunk(const Graph &g, int kind, int32_t x, int32_t sx, const int32_t *a,
+                                                int32_t p0, int32_t je) {
+    int32_t sy, yb;
+    const bool mine = partner_at(g, kind, x, sx, p0 + lane_id(), je, sy, yb);
+    uint64_t m = __ballot(mine);
+    const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     uint32_t hits = 0;
-    for (int32_t i = l; i < len; i += 4 * kWave) {
-        int32_t v0 = b[i];
-        int32_t v1 = i + kWave < len ? b[i + kWave] : -1;
-        int32_t v2 = i + 2 * kWave < len ? b[i + 2 * kWave] : -1;
-        int32_t v3 = i + 3 * kWave < len ? b[i + 3 * kWave] : -1;
-        hits += has(v0);
-        if (v1 >= 0) hits += has(v1);
-        if (v2 >= 0) hits += has(v2);
-        if (v3 >= 0) hits += has(v3);
+    while (m) {
+        const int src = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        hits += merge_count(a, sx, lists + __shfl(yb, src, kWave), __shfl(sy, src, kWave));
     }
     return hits;
 }
@@ -353,15 +570,18 @@ __device__ __forceinline__ int table_log2(int32_t sx, int max_log2) {
 
 __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__restrict__ items,
                                                           int32_t *__restrict__ q, int wg_log2, int wave_log2,
-                                                          unsigned long long *__restrict__ tri) {
+                                                          int table_ints, unsigned long long *__restrict__ tri) {
     extern __shared__ int32_t lds[];
+    __shared__ int32_t s_item, s_chunk;
     const int32_t n_wg = q[2], n_all = q[3];
-    __shared__ int32_t s_item;
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
-    uint64_t acc[2] = {0, 0};
+    int32_t *scr = lds + table_ints + w * kScratchInts;
+    reinterpret_cast<uint64_t *>(scr)[l] = 0ull;   // markers start clear
+    uint64_t acc0 = 0, acc1 = 0;
 
-    // ---- workgroup items: one shared table per block
+    // ---- workgroup items, claimed by blocks from a counter (they are few):
+    // one shared table, wavefronts claim 64-position chunks through LDS
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(&q[0], 1);
         __syncthreads();
@@ -373,59 +593,67 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
         const int32_t sx = list_size(kind, g.up0, g.rp1, x);
         const int lg = table_log2(sx, wg_log2);
-        const uint32_t mask = (1u << lg) - 1;
-        const int shift = 32 - lg;
-        for (int i = threadIdx.x; i <= (int)mask; i += kIsectThreads) lds[i] = kEmpty;
+        const HashTab ht = make_tab(lds, lg);
+        if (threadIdx.x == 0) s_chunk = 0;
+        for (int i = threadIdx.x; i < (1 << lg); i += kIsectThreads) lds[i] = kEmpty;
         __syncthreads();
-        for (int i = threadIdx.x; i < sx; i += kIsectThreads) hash_insert(lds, mask, shift, a[i]);
+        for (int i = threadIdx.x; i < sx; i += kIsectThreads) hash_insert(ht, a[i]);
         __syncthreads();
-        acc[kind] += stream_partners(g, kind, x, sx, item.jb, item.je, w, kIsectWaves,
-                                     [&](const int32_t *b, int32_t len) {
-                                         return probe_list(b, len, [&](int32_t v) {
-                                             return hash_has(lds, mask, shift, v);
-                                         });
-                                     });
-        __syncthreads();   // table reuse and s_item rewrite
+        uint32_t h = 0;
+        for (;;) {
+            int32_t c = 0;
+            if (l == 0) c = atomicAdd(&s_chunk, 1);
+            const int32_t p0 = item.jb + __shfl(c, 0, kWave) * kWave;
+            if (p0 >= item.je) break;
+            h += stream_chunk(g, kind, x, sx, p0, item.je, scr,
+                              [&](const int32_t(&v)[kPer]) {
+                                  return in_fours(v, [&](const int32_t(&q)[4]) { return hash_count<4>(ht, q); });
+                              });
+        }
+        if (kind == 0) acc0 += h; else acc1 += h;
+        __syncthreads();   // the table, s_item and s_chunk are reused by the next item
     }
 
-    // ---- wavefront items
+    // ---- wavefront items, static round-robin over all wavefronts.  Items
+    // are ordered heavy-first, so each wavefront gets one of the heaviest,
+    // then one of the next, and so on; no shared counter is needed.
     int32_t *tab = lds + (w << wave_log2);
-    for (;;) {
-        int32_t it = 0;
-        if (l == 0) it = atomicAdd(&q[1], 1);
-        it = __shfl(it, 0, kWave) + n_wg;
-        if (it >= n_all) break;
+    const int32_t G = (int32_t)gridDim.x * kIsectWaves;
+    for (int32_t it = n_wg + (int32_t)blockIdx.x * kIsectWaves + w; it < n_all; it += G) {
         const Item item = items[it];
         const int kind = item.code & 1;
         const int strat = item.code >> 1;
         const int32_t x = item.owner;
         const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
         const int32_t sx = list_size(kind, g.up0, g.rp1, x);
+        uint32_t h = 0;
         if (strat == TC_STRAT_WAVE_HASH) {
             const int lg = table_log2(sx, wave_log2);
-            const uint32_t mask = (1u << lg) - 1;
-            const int shift = 32 - lg;
-            for (int i = l; i <= (int)mask; i += kWave) tab[i] = kEmpty;
+            const HashTab ht = make_tab(tab, lg);
+            for (int i = l; i < (1 << lg); i += kWave) tab[i] = kEmpty;
             wave_lds_sync();
-            for (int i = l; i < sx; i += kWave) hash_insert(tab, mask, shift, a[i]);
+            for (int i = l; i < sx; i += kWave) hash_insert(ht, a[i]);
             wave_lds_sync();
-            acc[kind] += stream_partners(g, kind, x, sx, item.jb, item.je, 0, 1, [&](const int32_t *b, int32_t len) {
-                return probe_list(b, len, [&](int32_t v) { return hash_has(tab, mask, shift, v); });
-            });
-            wave_lds_sync();
+            for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave)
+                h += stream_chunk(g, kind, x, sx, p0, item.je, scr,
+                                  [&](const int32_t(&v)[kPer]) {
+                                  return in_fours(v, [&](const int32_t(&q)[4]) { return hash_count<4>(ht, q); });
+                              });
+            wave_lds_sync();   // lookups done before the next item clears the table
         } else if (strat == TC_STRAT_MERGE) {
-            acc[kind] += stream_partners(g, kind, x, sx, item.jb, item.je, 0, 1, [&](const int32_t *b, int32_t len) {
-                return merge_count(a, sx, b, len);
-            });
+            for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave) h += merge_chunk(g, kind, x, sx, a, p0, item.je);
         } else {
-            acc[kind] += stream_partners(g, kind, x, sx, item.jb, item.je, 0, 1, [&](const int32_t *b, int32_t len) {
-                return probe_list(b, len, [&](int32_t v) { return bsearch_has(a, sx, v); });
-            });
+            for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave)
+                h += stream_chunk(g, kind, x, sx, p0, item.je, scr,
+                                  [&](const int32_t(&v)[kPer]) {
+                                  return in_fours(v, [&](const int32_t(&q)[4]) { return search_count<4>(a, sx, q); });
+                              });
         }
+        if (kind == 0) acc0 += h; else acc1 += h;
     }
 
-    uint64_t t0 = wave_sum(acc[0]);
-    uint64_t t1 = wave_sum(acc[1]);
+    const uint64_t t0 = wave_sum(acc0);
+    const uint64_t t1 = wave_sum(acc1);
     if (l == 0) {
         if (t0) atomicAdd(&tri[0], (unsigned long long)t0);
         if (t1) atomicAdd(&tri[1], (unsigned long long)t1);
@@ -514,37 +742,43 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         hipLaunchKernelGGL(k_own, dim3(gp), dim3(kThreads), 0, s, n, pb.e0x2, pb.rp0, pb.c0, pb.up0, pb.rp1, L.cnt,
                            L.work);
         TC_HIP_TRY(hipGetLastError());
-        const unsigned gu = grid_for(2 * (int64_t)n, kThreads, (int64_t)di.cus * 4);
-        hipLaunchKernelGGL((k_items<0>), dim3(gu), dim3(kThreads), 0, s, n, pb.rp0, pb.up0, pb.rp1, L.cnt, L.work,
-                           sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats);
+        const unsigned gu = grid_for(2 * (int64_t)n, kItemThreads * kUnitsPerThread, (int64_t)1 << 30);
+        hipLaunchKernelGGL((k_items<0>), dim3(gu), dim3(kItemThreads), 0, s, n, pb.rp0, pb.up0, pb.rp1, L.cnt,
+                           L.work, sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats);
         TC_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_bucket_order, dim3(1), dim3(64), 0, s, L.bucket_items, sc, L.bucket_off, L.q);
+        hipLaunchKernelGGL(k_bucket_order, dim3(1), dim3(1024), 0, s, L.bucket_items, sc, L.bucket_off, L.q);
         TC_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL((k_items<1>), dim3(gu), dim3(kThreads), 0, s, n, pb.rp0, pb.up0, pb.rp1, L.cnt, L.work,
-                           sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats);
+        hipLaunchKernelGGL((k_items<1>), dim3(gu), dim3(kItemThreads), 0, s, n, pb.rp0, pb.up0, pb.rp1, L.cnt,
+                           L.work, sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats);
         TC_HIP_TRY(hipGetLastError());
     }
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev[1], s));
     if (n > 0) {
-        int lds_slots = 1 << wg_log2;
-        if ((kIsectWaves << wave_log2) > lds_slots) lds_slots = kIsectWaves << wave_log2;
-        const size_t lds_bytes = (size_t)lds_slots * sizeof(int32_t);
+        int table_ints = 1 << wg_log2;
+        if ((kIsectWaves << wave_log2) > table_ints) table_ints = kIsectWaves << wave_log2;
+        const size_t lds_bytes = (size_t)(table_ints + kIsectWaves * kScratchInts) * sizeof(int32_t);
         TC_HIP_TRY(hipFuncSetAttribute((const void *)k_isect, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds_bytes));
-        int per_cu = (int)((160 * 1024) / (lds_bytes + 1024));
-        if (per_cu > 4) per_cu = 4;
+        int per_cu = 1;
+        TC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_isect, kIsectThreads,
+                                                                 lds_bytes));
         if (per_cu < 1) per_cu = 1;
+        if (getenv("TC_LOG")) fprintf(stderr, "libtc: k_isect %d blocks/CU, %zu B LDS\n", per_cu, lds_bytes);
         const unsigned gi = cfg.grid_blocks > 0 ? (unsigned)cfg.grid_blocks : (unsigned)(di.cus * per_cu);
         Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1};
         hipLaunchKernelGGL(k_isect, dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items, L.q, wg_log2,
-                           wave_log2, L.stats + 8);
+                           wave_log2, table_ints, L.stats + 8);
         TC_HIP_TRY(hipGetLastError());
     }
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev[2], s));
-    unsigned long long h[16];
-    TC_HIP_TRY(hipMemcpyAsync(h, L.stats, sizeof(h), hipMemcpyDeviceToHost, s));
+    Mailbox mb;
+    TC_TRY(mailbox(&mb));
+    TC_TRY(mail_u64(reinterpret_cast<const uint64_t *>(L.stats), mb.dev, 16, s));
+    TC_TRY(mail_u64(reinterpret_cast<const uint64_t *>(pb.e0x2), mb.dev + 16, 1, s));
     TC_HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t *h = mb.host;
     if (out) {
+        out->e0x2 = (int64_t)h[16];
         out->T0 = h[8];
         out->T1 = h[9];
         out->units = (int64_t)h[0];

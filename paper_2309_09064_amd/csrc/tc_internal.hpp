@@ -63,6 +63,21 @@ struct DeviceInfo {
 };
 int device_info(DeviceInfo *out);
 
+// ------------------------------------------------------------------ mailbox
+
+// A 4 KB pinned host buffer, mapped into the device address space, private
+// to the calling host thread (allocated on its first use and kept until the
+// process ends).  Kernels write small results there; the host reads them
+// after synchronising the stream, without a device-to-host copy.
+struct Mailbox {
+    uint64_t *host = nullptr;
+    uint64_t *dev = nullptr;
+};
+int mailbox(Mailbox *out);
+// dst[i] = src[i] for i < count (count <= 64), one tiny kernel.
+int mail_u64(const uint64_t *src, uint64_t *dst, int count, hipStream_t s);
+int mail_i32(const int32_t *src, uint64_t *dst, hipStream_t s);
+
 // ------------------------------------------------------------------ device helpers
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -102,6 +117,19 @@ __device__ __forceinline__ int64_t row_of(const P *rp, int64_t lo, int64_t hi, i
     return lo;
 }
 
+// Rows spanned by the tile of CSR entries [t0, t1) (t0 < t1 <= rp[nrows]):
+// one thread searches, the block shares the range through `sh` (2 entries).
+// Ends with a barrier.  Threads then search only inside [lo, hi].
+template <class P>
+__device__ __forceinline__ void tile_rows(const P *rp, int64_t nrows, int64_t t0, int64_t t1, int64_t *sh) {
+    if (threadIdx.x == 0) {
+        const int64_t lo = row_of(rp, 0, nrows - 1, t0);
+        sh[0] = lo;
+        sh[1] = row_of(rp, lo, nrows - 1, t1 - 1);
+    }
+    __syncthreads();
+}
+
 // ------------------------------------------------------------------ scan
 
 // Exclusive prefix sum of n values (int32 or int64 input) into int32 or int64
@@ -129,6 +157,10 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
             void *ws, size_t ws_bytes, hipStream_t s);
 
 // Partition into N0 (rank-split rows) and N1
+// Padding (ints) on both sides of the N0/N1 list arrays that the
+// intersection kernel reads in 8-element runs.
+constexpr int kListPad = 16;
+
 struct PartBufs {
     int32_t *rp0, *c0, *up0, *rp1, *c1;   // outputs (rp* are n+1)
     int32_t *d0;                          // n: |N0(x)|
@@ -143,6 +175,7 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
 struct CountOut {
     uint64_t T0 = 0, T1 = 0;
     int64_t units = 0, items = 0, probes = 0, hashed = 0;
+    int64_t e0x2 = 0;   // 2|E0|
     int32_t strategy_items[TC_NUM_STRATEGIES] = {0, 0, 0, 0};
     float ms_bucket = 0.f, ms_isect = 0.f;
 };
@@ -150,7 +183,7 @@ struct CountCfg {
     int schedule = TC_SCHED_HEURISTIC;
     int force = TC_STRAT_AUTO;
     int wave_slots = 2048;
-    int wg_slots = 16384;
+    int wg_slots = 32768;
     int chunk_work = 16384;
     int grid_blocks = 0;
     int wave_max_owner = 0;

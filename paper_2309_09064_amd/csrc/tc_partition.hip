@@ -26,6 +26,7 @@ constexpr int kThreads = 256;
 constexpr int kRun = 8;
 constexpr int kBlockEntries = kThreads * kRun;
 constexpr int kWaves = kThreads / kWave;
+constexpr int kTileRowsMax = 1024;   // rows a tile may span and still count in LDS
 
 // rank(y) > rank(x) with rank = (degree, id), dx = deg(x)
 __device__ __forceinline__ bool rank_above(const int32_t *rp, int32_t y, int32_t x, int32_t dx) {
@@ -40,14 +41,36 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
                                                          int32_t *__restrict__ up0, int32_t *__restrict__ bh,
                                                          int32_t *__restrict__ bu) {
     __shared__ int32_t sh[kWaves], su[kWaves];
-    const int64_t e0 = (int64_t)blockIdx.x * kBlockEntries + (int64_t)threadIdx.x * kRun;
+    __shared__ int64_t rows[2];
+    __shared__ int32_t acc_h[kTileRowsMax], acc_u[kTileRowsMax];
+    const int64_t t0 = (int64_t)blockIdx.x * kBlockEntries;
+    tile_rows(rp, n, t0, t0 + kBlockEntries < nnz ? t0 + kBlockEntries : nnz, rows);
+    const int64_t r_lo = rows[0], r_hi = rows[1];
+    const int64_t nr = r_hi - r_lo + 1;
+    // rows of the tile are counted in LDS; only the two boundary rows can be
+    // shared with other tiles
+    const bool local = nr <= kTileRowsMax;
+    if (local)
+        for (int64_t i = threadIdx.x; i < nr; i += kThreads) { acc_h[i] = 0; acc_u[i] = 0; }
+    __syncthreads();
+    const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
     int32_t th = 0, tu = 0;
     if (e0 < nnz) {
         const int64_t e1 = e0 + kRun < nnz ? e0 + kRun : nnz;
-        int64_t x = row_of(rp, 0, n - 1, e0);
+        int64_t x = row_of(rp, r_lo, r_hi, e0);
         int64_t xe = rp[x + 1];
         int32_t lx = lev[x], dx = (int32_t)(xe - rp[x]);
         int32_t ch = 0, cu = 0;
+        auto flush = [&]() {
+            if (local) {
+                if (ch) atomicAdd(&acc_h[x - r_lo], ch);
+                if (cu) atomicAdd(&acc_u[x - r_lo], cu);
+            } else {
+                if (ch) atomicAdd(&d0[x], ch);
+                if (cu) atomicAdd(&up0[x], cu);
+            }
+            ch = cu = 0;
+        };
         uint8_t f[kRun];
 #pragma unroll
         for (int k = 0; k < kRun; ++k) f[k] = 0;
@@ -56,9 +79,7 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
             const int64_t e = e0 + k;
             if (e < e1) {
                 while (e >= xe) {
-                    if (ch) atomicAdd(&d0[x], ch);
-                    if (cu) atomicAdd(&up0[x], cu);
-                    ch = cu = 0;
+                    flush();
                     ++x;
                     xe = rp[x + 1];
                     lx = lev[x];
@@ -72,8 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
                 cu += up;
             }
         }
-        if (ch) atomicAdd(&d0[x], ch);
-        if (cu) atomicAdd(&up0[x], cu);
+        flush();
         uint64_t word = 0;
 #pragma unroll
         for (int k = 0; k < kRun; ++k) {
@@ -93,6 +113,19 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
     tu = wave_sum(tu);
     if (lane_id() == 0) { sh[threadIdx.x / kWave] = th; su[threadIdx.x / kWave] = tu; }
     __syncthreads();
+    if (local) {
+        for (int64_t i = threadIdx.x; i < nr; i += kThreads) {
+            const int64_t r = r_lo + i;
+            const int32_t h = acc_h[i], u = acc_u[i];
+            if (r == r_lo || r == r_hi) {
+                if (h) atomicAdd(&d0[r], h);
+                if (u) atomicAdd(&up0[r], u);
+            } else {
+                d0[r] = h;
+                up0[r] = u;
+            }
+        }
+    }
     if (threadIdx.x == 0) {
         int32_t a = 0, b = 0;
         for (int i = 0; i < kWaves; ++i) { a += sh[i]; b += su[i]; }
@@ -102,9 +135,10 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
 }
 
 __global__ void k_part_rp1(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ rp0,
-                           int32_t *__restrict__ rp1) {
+                           int32_t *__restrict__ rp1, int64_t *__restrict__ e0x2) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += (int64_t)gridDim.x * blockDim.x)
         rp1[x] = rp[x] - rp0[x];
+    if (e0x2 && blockIdx.x == 0 && threadIdx.x == 0) *e0x2 = rp0[n];
 }
 
 __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
@@ -116,7 +150,10 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
                                                             const int32_t *__restrict__ rpu,
                                                             int32_t *__restrict__ c0, int32_t *__restrict__ c1) {
     __shared__ int64_t wsum[kWaves];
-    const int64_t e0 = (int64_t)blockIdx.x * kBlockEntries + (int64_t)threadIdx.x * kRun;
+    __shared__ int64_t rows[2];
+    const int64_t t0 = (int64_t)blockIdx.x * kBlockEntries;
+    tile_rows(rp, n, t0, t0 + kBlockEntries < nnz ? t0 + kBlockEntries : nnz, rows);
+    const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
     const int64_t e1 = e0 < nnz ? (e0 + kRun < nnz ? e0 + kRun : nnz) : e0;
     uint8_t f[kRun];
     int64_t packed = 0;   // horizontal count << 32 | rank-above count
@@ -143,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
     if (e0 >= e1) return;
     int64_t H = (int64_t)bh_off[blockIdx.x] + (before >> 32);
     int64_t U = (int64_t)bu_off[blockIdx.x] + (before & 0xffffffffll);
-    int64_t x = row_of(rp, 0, n - 1, e0);
+    int64_t x = row_of(rp, rows[0], rows[1], e0);
     int64_t xe = rp[x + 1];
 #pragma unroll
     for (int k = 0; k < kRun; ++k) {
@@ -211,7 +248,8 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
     }
     TC_TRY(scan_exclusive_i32_to_i32(pb.d0, pb.rp0, n, L.scan, s));
     TC_TRY(scan_exclusive_i32_to_i32(pb.up0, pb.rpu, n, L.scan, s));
-    hipLaunchKernelGGL(k_part_rp1, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, n, rp, pb.rp0, pb.rp1);
+    hipLaunchKernelGGL(k_part_rp1, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, n, rp, pb.rp0, pb.rp1,
+                       pb.e0x2);
     TC_HIP_TRY(hipGetLastError());
     if (nnz > 0) {
         TC_TRY(scan_exclusive_i32_to_i32(L.bh, L.bh, nblk, L.scan, s));
@@ -219,10 +257,6 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
         hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, L.flags,
                            L.bh, L.bu, pb.rp0, pb.rpu, pb.c0, pb.c1);
         TC_HIP_TRY(hipGetLastError());
-    }
-    if (pb.e0x2) {
-        TC_HIP_TRY(hipMemsetAsync(pb.e0x2, 0, sizeof(int64_t), s));
-        TC_HIP_TRY(hipMemcpyAsync(pb.e0x2, pb.rp0 + n, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     }
     return TC_OK;
 }
