@@ -8,12 +8,22 @@ the CSR) and stays resident in HBM.
 
 Prints one JSON line.  Default workload: Graph500-style Kronecker graph,
 scale 20, edgefactor 16, initiator (.57, .19, .19, .05), seed 1.
+
+The roofline object describes the intersection kernel (k_isect): its
+algorithmic bytes per launch over its mean duration, taken from HIP events
+that the library records around the launch on its own stream during the
+timed steps.  Its `traffic` field comes from the committed counter summary
+in profiles/ (FETCH_SIZE + WRITE_SIZE, scaled by what the same counters read
+for a plain copy of known size) and is null when the kernel sources have
+changed since those counters were taken.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -24,6 +34,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "input edges/s + % HBM peak, plain vs learned-scheduled, counts bit-exact"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_isect_kronecker_s20_traffic.txt")
+KERNEL_SOURCES = ("paper_2309_09064_amd/csrc/tc_count.hip", "paper_2309_09064_amd/csrc/tc_internal.hpp")
+COPY_PROBE_BYTES = 1 << 30
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def b_alg(row_ptr, col, levels):
@@ -45,6 +66,38 @@ def b_alg(row_ptr, col, levels):
     return int(4 * smin + 4 * (d1.sum() + d0p.sum()) + 8 * len(eu) + 8 * n)
 
 
+def read_traffic(expect_hash):
+    """HBM bytes per k_isect launch from the committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    kv = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            m = re.match(r"^([a-z_0-9]+) = (\S+)\s*$", line)
+            if m:
+                kv[m.group(1)] = m.group(2)
+    try:
+        if kv["kernel_source_sha256"] != expect_hash:
+            return None
+        f_scale = float(kv["copy_bytes"]) / (1024.0 * float(kv["copy_fetch_kib"]))
+        w_scale = float(kv["copy_bytes"]) / (1024.0 * float(kv["copy_write_kib"]))
+        return 1024.0 * (float(kv["isect_fetch_kib"]) * f_scale + float(kv["isect_write_kib"]) * w_scale)
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
+def copy_probe(torch):
+    """A plain device copy of known size, for scaling the byte counters."""
+    a = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"# copy probe: 3 copies of {COPY_PROBE_BYTES} bytes", file=sys.stderr, flush=True)
+    del a, b
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,9 +106,12 @@ def main():
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported "
+                                   "(the multi-GPU sharding is described, not built)"}))
         sys.exit(2)
 
     import torch
@@ -63,40 +119,43 @@ def main():
     import paper_2309_09064_amd as tc
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch)
     n, src, dst = graphgen.kronecker(args.scale, 16, seed=args.seed)
     rp, col = tc.build_csr(n, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
     nnz = col.numel()
     m = nnz // 2
     print(f"# graph: kronecker scale {args.scale}, n={n}, m={m}", file=sys.stderr, flush=True)
 
-    counter = tc.Counter(n, nnz, tc.Options())
+    # TC_TIMING makes the library record HIP events around each phase on the
+    # stream it launches on; the cost is four event records per phase
+    counter = tc.Counter(n, nnz, tc.Options(timing=True))
     for _ in range(args.warmup):
-        res = counter(rp, col)
+        counter(rp, col)
     torch.cuda.synchronize()
+    results = []
     t0 = time.perf_counter()
-    Ts = []
     for _ in range(args.steps):
-        Ts.append(counter(rp, col).T)
+        results.append(counter(rp, col))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
-    assert len(set(Ts)) == 1, "count changed between steps"
-    T = Ts[0]
-    print(f"# timed: {args.steps} steps, {step_s * 1e3:.3f} ms/step, T={T}", file=sys.stderr, flush=True)
+    Ts = {r.T for r in results}
+    assert len(Ts) == 1, "count changed between steps"
+    r = results[-1]
+    T = r.T
+    ms = {k: float(np.mean([x.ms[k] for x in results])) for k in ("bfs", "partition", "bucket", "isect")}
+    print(f"# timed: {args.steps} steps, {step_s * 1e3:.3f} ms/step, T={T}; phase ms {ms}", file=sys.stderr,
+          flush=True)
 
-    # phase times from HIP events recorded on the library's stream
-    tcounter = tc.Counter(n, nnz, tc.Options(timing=True))
-    ph = {"bfs": [], "partition": [], "bucket": [], "isect": []}
-    for _ in range(max(3, min(args.steps, 10))):
-        r = tcounter(rp, col)
-        for k in ph:
-            ph[k].append(r.ms[k])
-    ms = {k: float(np.mean(v)) for k, v in ph.items()}
     lev, _ = tc.bfs_levels(rp, col)
     rp_h, col_h, lev_h = rp.cpu().numpy(), col.cpu().numpy(), lev.cpu().numpy()
     balg = b_alg(rp_h, col_h, lev_h)
     achieved = balg / (ms["isect"] * 1e-3) / 1e9
-    print(f"# phases ms: {ms}; B_alg={balg / 1e9:.3f} GB -> {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    default_workload = args.scale == 20 and args.seed == 1
+    traffic = read_traffic(kernel_source_hash()) if default_workload else None
+    print(f"# k_isect: B_alg={balg / 1e9:.3f} GB in {ms['isect']:.3f} ms -> {achieved:.0f} GB/s; "
+          f"counter traffic {traffic}", file=sys.stderr, flush=True)
 
     cpu = None
     exact = None
@@ -109,7 +168,8 @@ def main():
         t3 = time.perf_counter()
         exact = (ores.T == T) and (ores.T0 == r.T0) and (ores.T1 == r.T1)
         cpu = {"value": m / (t3 - t2), "unit": "input edges/s", "cores": 1, "kind": "oracle",
-               "sample": f"whole graph, one run of serial BFS levels + Alg. 4 (gcc -O2), {t3 - t2:.2f} s"}
+               "sample": f"the whole graph, one run of the oracle's serial BFS levels + Alg. 4 "
+                         f"(C, gcc -O2, one thread): {t3 - t2:.2f} s"}
 
     out = {
         "metric": METRIC,
@@ -130,8 +190,8 @@ def main():
                    "k_percent": round(100.0 * r.e0 / m, 2), "levels": r.levels, "counts_bit_exact": exact,
                    "phase_ms": ms, "items": r.items, "strategy_items": r.strategy_items},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_isect",
-                     "bytes_per_launch": balg},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_isect",
+                     "bytes_per_launch": balg, "ms_per_launch": ms["isect"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
