@@ -75,9 +75,21 @@ enum tc_strategy {
 };
 
 enum tc_schedule {
-    TC_SCHED_HEURISTIC = 0,   /* list-size thresholds                        */
-    TC_SCHED_MLP = 1          /* the loaded cost network (tc_sched_load)      */
+    TC_SCHED_HEURISTIC = 0,   /* owner-list-size thresholds                  */
+    TC_SCHED_TABLE = 1        /* one strategy per bucket from
+                                 opt->sched_table, e.g. the choice of the
+                                 learned cost network (tc_mlp_schedule)      */
 };
+
+/*
+ * Buckets.  The counting work is split into units (owner x, kind): kind 0
+ * intersects N0+ lists (T0), kind 1 intersects N1 lists (T1); the owner of a
+ * horizontal edge is the endpoint with the larger list.  A unit falls in
+ * bucket  b = (kind * 32 + ob) * 32 + pb  where ob = floor(log2 |owner list|)
+ * and pb = floor(log2 (mean size of the partner lists streamed against it)),
+ * both capped at 31.  Schedules assign one strategy per bucket.
+ */
+#define TC_NUM_BUCKETS 2048
 
 enum tc_flags {
     TC_VALIDATE = 1,          /* check CSR (sorted, symmetric-free checks,
@@ -87,9 +99,11 @@ enum tc_flags {
 
 typedef struct tc_options {
     int32_t schedule;         /* tc_schedule                                 */
-    int32_t force_strategy;   /* tc_strategy; >= 0 forces it on every bucket
-                                 (infeasible hash choices fall back to
-                                 TC_STRAT_BSEARCH)                           */
+    int32_t force_strategy;   /* tc_strategy; >= 0 forces it on every bucket.
+                                 A hash strategy whose table cannot hold a
+                                 bucket's owner lists is replaced: wavefront
+                                 by workgroup hash if that holds them, else
+                                 by TC_STRAT_BSEARCH                         */
     int32_t flags;            /* tc_flags bits                               */
     int32_t wave_slots;       /* LDS hash slots per wavefront (power of 2,
                                  64..2048); 0 = default 2048                 */
@@ -101,6 +115,11 @@ typedef struct tc_options {
                                  blocks as fit in LDS, at most 2 per CU      */
     int32_t wave_max_owner;   /* heuristic: largest owner list for the
                                  wavefront hash; 0 = wave_slots / 2          */
+    const int32_t *sched_table; /* device int32[TC_NUM_BUCKETS] strategies,
+                                 read when schedule == TC_SCHED_TABLE (NULL
+                                 otherwise).  A hash strategy in a bucket
+                                 whose owners exceed that table's capacity
+                                 is replaced as with force_strategy.         */
 } tc_options;
 
 /* Per-call statistics (host struct, all optional). */
@@ -188,6 +207,93 @@ int tc_count_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_byte
 uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                   const int32_t *d_levels, const tc_options *opt, tc_stats *stats, void *ws,
                   size_t ws_bytes, void *stream);
+
+/*
+ * tc_count plus a per-bucket cost profile, the training data of the learned
+ * schedule (not part of the paper: it only chooses among exact kernels).
+ * Uses the same workspace size as tc_count.  ADDS into
+ *   d_prof  uint64[TC_NUM_BUCKETS * TC_NUM_STRATEGIES * 3] device; for
+ *           bucket b and strategy s, at ((b * 4) + s) * 3:
+ *             [0] wavefront-ticks: elapsed ticks of the device's constant
+ *                 clock per work item, times the wavefronts the item holds
+ *                 (16 for TC_STRAT_WG_HASH, else 1), summed over items;
+ *             [1] elements: partner-list elements streamed plus owner-list
+ *                 elements, summed over the bucket's units (the same for
+ *                 every strategy);
+ *             [2] work items run.
+ * so several calls (graphs, forced strategies) accumulate into one profile;
+ * the caller zeroes it first.  Returns T like tc_count; the instrumented
+ * kernel is slower than tc_count's.
+ */
+uint64_t tc_count_profile(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                          const int32_t *d_levels, const tc_options *opt, tc_stats *stats,
+                          uint64_t *d_prof, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ cost network
+ *
+ * A small fully connected network predicts, for a bucket, the cost of each
+ * strategy (log2 of wavefront-ticks per element); the learned schedule takes
+ * the cheapest feasible one.  The network is not in the paper: it only picks
+ * which exact kernel counts a bucket, so it never changes a count.
+ *
+ *   a1 = relu(W1 x + b1),  a2 = relu(W2 a1 + b2),  y = W3 a2 + b3
+ *   x = (ob, pb, kind) of a bucket, as floats; y[k] = predicted cost of
+ *   strategy k (k < K; the schedule uses K = TC_NUM_STRATEGIES).
+ *
+ * Parameters: device float32, row-major, in the order W1[H][3], b1[H],
+ * W2[H][H], b2[H], W3[K][H], b3[K]; tc_mlp_param_count gives their number.
+ * Supported sizes: H in {8, 16, 32, 64}, 1 <= K <= 8.  A training row is
+ * (x[3], c, t): features, the strategy measured, its measured cost; the loss
+ * of R rows is (1/R) * sum 0.5 * (y[c] - t)^2, minimised by Adam.
+ */
+#define TC_MLP_IN 3
+
+int tc_mlp_param_count(int32_t hidden, int32_t k, int64_t *h_count);
+
+/* He-uniform weights, zero biases: W[i][j] = (2u - 1) * sqrt(6 / fan_in)
+ * with u = (SplitMix64(seed + index) >> 40) * 2^-24, index = the weight's
+ * position in the flat parameter array.  Deterministic. */
+int tc_mlp_init(float *d_params, int32_t hidden, int32_t k, uint64_t seed, void *stream);
+
+/* y[r][k] for rows r < rows; d_x float[rows][3], d_y float[rows][K]. */
+int tc_mlp_forward(const float *d_params, int32_t hidden, int32_t k, const float *d_x, int32_t rows,
+                   float *d_y, void *stream);
+
+/* Loss and gradient over rows r < rows (d_c int32[rows] in [0, K); a row
+ * with another index contributes nothing), d_t
+ * float[rows]); d_grad float[param_count] (same layout as the parameters),
+ * d_loss float[1] (NULL ok).  The sums over rows run in a fixed order in
+ * float64, so the result is deterministic.  rows >= 1. */
+int tc_mlp_grad_ws(int32_t hidden, int32_t k, int32_t rows, size_t *h_ws_bytes);
+int tc_mlp_grad(const float *d_params, int32_t hidden, int32_t k, const float *d_x, const int32_t *d_c,
+                const float *d_t, int32_t rows, float *d_grad, float *d_loss, void *ws, size_t ws_bytes,
+                void *stream);
+
+/* One Adam step (Kingma and Ba, with bias correction) on count parameters:
+ * m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ * p -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * step >= 1.  d_m and d_v start at zero. */
+int tc_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int64_t count, int32_t step,
+                float lr, float beta1, float beta2, float eps, void *stream);
+
+/* steps Adam steps on the full batch (gradient, then update), numbered
+ * first_step, first_step + 1, ...; d_loss float[steps] receives each step's
+ * loss before its update (NULL ok).  Workspace: tc_mlp_grad_ws plus the
+ * gradient, i.e. tc_mlp_train_ws. */
+int tc_mlp_train_ws(int32_t hidden, int32_t k, int32_t rows, size_t *h_ws_bytes);
+int tc_mlp_train(float *d_params, float *d_m, float *d_v, int32_t hidden, int32_t k, const float *d_x,
+                 const int32_t *d_c, const float *d_t, int32_t rows, int32_t first_step, int32_t steps, float lr,
+                 float beta1, float beta2, float eps, float *d_loss, void *ws, size_t ws_bytes, void *stream);
+
+/* The learned schedule: for every bucket b, the strategy with the smallest
+ * predicted cost among those feasible under opt (a wavefront or workgroup
+ * hash is feasible when ob <= log2(slots) - 2, i.e. the owner list fills at
+ * most half the table; binary search and merge always are).  Ties go to the
+ * lower strategy number.  K must be TC_NUM_STRATEGIES.
+ *   d_table  int32[TC_NUM_BUCKETS] device, output (for opt->sched_table)
+ *   d_cost   float[TC_NUM_BUCKETS][K] device, predicted costs, NULL ok */
+int tc_mlp_schedule(const float *d_params, int32_t hidden, int32_t k, const tc_options *opt, int32_t *d_table,
+                    float *d_cost, void *stream);
 
 /*
  * The two CSRs of the partition (Algorithm 4, partition loop), for tests and

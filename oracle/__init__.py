@@ -185,3 +185,44 @@ def vertex_triangles(g: CSR) -> np.ndarray:
     tv = np.zeros(max(g.n, 1), np.uint64)
     _load().orc_vertex_triangles(g.n, g.row_ptr, _col_or_dummy(g), tv)
     return tv[:g.n]
+
+
+def _floor_log2(v) -> np.ndarray:
+    """floor(log2 v) for integers v >= 1, and 0 for v <= 1."""
+    return np.array([max(int(x), 1).bit_length() - 1 for x in np.atleast_1d(v)], dtype=np.int64)
+
+
+def bucket_work(g: CSR, level: np.ndarray):
+    """Units and elements per schedule bucket (the library's work split, not
+    the paper's): for kind 0 the lists are N0+ (sizes |N0+|), for kind 1 the
+    N1 lists.  Each horizontal edge {x, y} belongs, per kind, to the endpoint
+    with the larger list (ties: larger id) unless the other list is empty.
+    Owner x of kind k forms one unit with cnt owned partners and work = the
+    sum of their list sizes; its bucket is (k * 32 + ob) * 32 + pb with
+    ob = floor(log2 |list(x)|), pb = floor(log2 (work // cnt)), both capped at
+    31; the unit adds work + |list(x)| elements.  Returns int64 arrays
+    units[2048], elements[2048]."""
+    p = partition(g, level)
+    n = g.n
+    sizes = [p.up0.astype(np.int64), np.diff(p.rp1).astype(np.int64)]
+    x = np.repeat(np.arange(n, dtype=np.int64), np.diff(p.rp0))   # every directed horizontal edge (x, y)
+    y = p.c0.astype(np.int64)
+    units = np.zeros(2048, dtype=np.int64)
+    elements = np.zeros(2048, dtype=np.int64)
+    for kind in (0, 1):
+        s = sizes[kind]
+        sx, sy = s[x], s[y]
+        own = (sy > 0) & ((sx > sy) | ((sx == sy) & (x > y)))
+        cnt = np.zeros(n, dtype=np.int64)
+        work = np.zeros(n, dtype=np.int64)
+        np.add.at(cnt, x[own], 1)
+        np.add.at(work, x[own], sy[own])
+        owners = np.nonzero(cnt)[0]
+        if len(owners) == 0:
+            continue
+        ob = np.minimum(_floor_log2(s[owners]), 31)
+        pb = np.minimum(_floor_log2(work[owners] // cnt[owners]), 31)
+        b = (kind * 32 + ob) * 32 + pb
+        np.add.at(units, b, 1)
+        np.add.at(elements, b, work[owners] + s[owners])
+    return units, elements

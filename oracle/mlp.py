@@ -100,3 +100,69 @@ def unflatten(flat, K: int, H: int = H_DEFAULT):
         out.append(np.asarray(flat[off:off + sz], dtype=np.float64).reshape(shp))
         off += sz
     return out
+
+
+# ---------------------------------------------------------------- initialisation
+
+GOLDEN = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def splitmix64_at(seed: int, index):
+    """The (index + 1)-th output of SplitMix64 (Steele, Lea and Flood, 2014)
+    started at ``seed``: mix(seed + (index + 1) * golden), in Python integers."""
+    out = []
+    for i in np.atleast_1d(np.asarray(index, dtype=np.uint64)).tolist():
+        z = (seed + (int(i) + 1) * GOLDEN) & _M64
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        out.append(z ^ (z >> 31))
+    return np.array(out, dtype=np.uint64)
+
+
+def init_he_uniform(K: int, H: int = H_DEFAULT, seed: int = 0):
+    """The library's initialisation, in float32: weight at flat index i is
+    (2u - 1) * float32(sqrt(6 / fan_in)) with u = (SplitMix64(seed, i) >> 40)
+    * 2^-24; biases are zero."""
+    flat = np.zeros(sum(int(np.prod(s)) for s in param_shapes(K, H)), dtype=np.float32)
+    off = 0
+    for shp in param_shapes(K, H):
+        sz = int(np.prod(shp))
+        if len(shp) == 2:
+            idx = np.arange(off, off + sz, dtype=np.uint64)
+            u = (splitmix64_at(seed, idx) >> np.uint64(40)).astype(np.float32) * np.float32(2.0 ** -24)
+            d = np.float32(2.0) * u - np.float32(1.0)
+            flat[off:off + sz] = d * np.float32(np.sqrt(6.0 / shp[1]))
+        off += sz
+    return flat
+
+
+# ---------------------------------------------------------------- schedule
+
+N_BUCKETS = 2048
+STRAT_WAVE_HASH, STRAT_WG_HASH, STRAT_BSEARCH, STRAT_MERGE = 0, 1, 2, 3
+
+
+def bucket_features(b):
+    """(ob, pb, kind) of bucket b = (kind * 32 + ob) * 32 + pb."""
+    b = np.asarray(b, dtype=np.int64)
+    return np.stack([(b >> 5) & 31, b & 31, b >> 10], axis=1).astype(np.float64)
+
+
+def schedule(params, wave_ob_max: int, wg_ob_max: int):
+    """Per bucket: predicted costs (float64), the cheapest feasible strategy
+    (ties to the lower number), and the gap to the runner-up (inf if it is
+    the only feasible one).  A wavefront / workgroup hash is feasible when
+    ob <= wave_ob_max / wg_ob_max; binary search and merge always are."""
+    b = np.arange(N_BUCKETS)
+    X = bucket_features(b)
+    y, _ = forward(params, X)
+    ob = X[:, 0]
+    feas = np.ones((N_BUCKETS, 4), dtype=bool)
+    feas[:, STRAT_WAVE_HASH] = ob <= wave_ob_max
+    feas[:, STRAT_WG_HASH] = ob <= wg_ob_max
+    yy = np.where(feas, y[:, :4], np.inf)
+    table = np.argmin(yy, axis=1)          # argmin returns the first (lowest) index on ties
+    srt = np.sort(yy, axis=1)
+    gap = srt[:, 1] - srt[:, 0]
+    return table.astype(np.int32), y, gap, feas

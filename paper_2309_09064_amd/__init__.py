@@ -13,13 +13,15 @@ from dataclasses import dataclass, field
 import torch
 
 from . import _capi
-from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_STRATEGIES, TC_SCHED_HEURISTIC, TC_SCHED_MLP,
-                    TC_STRAT_AUTO, TC_STRAT_BSEARCH, TC_STRAT_MERGE, TC_STRAT_WAVE_HASH, TC_STRAT_WG_HASH,
-                    TC_TIMING, TC_VALIDATE)
+from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_BUCKETS, TC_NUM_STRATEGIES, TC_SCHED_HEURISTIC,
+                    TC_SCHED_TABLE, TC_STRAT_AUTO, TC_STRAT_BSEARCH, TC_STRAT_MERGE, TC_STRAT_WAVE_HASH,
+                    TC_STRAT_WG_HASH, TC_TIMING, TC_VALIDATE)
 
-__all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count", "workspace",
+__all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count", "count_profile", "workspace",
+           "Counter", "CountResult", "new_profile",
            "STRATEGY_NAMES", "TC_STRAT_AUTO", "TC_STRAT_WAVE_HASH", "TC_STRAT_WG_HASH", "TC_STRAT_BSEARCH",
-           "TC_STRAT_MERGE", "TC_SCHED_HEURISTIC", "TC_SCHED_MLP", "TC_VALIDATE", "TC_TIMING"]
+           "TC_STRAT_MERGE", "TC_SCHED_HEURISTIC", "TC_SCHED_TABLE", "TC_NUM_BUCKETS", "TC_NUM_STRATEGIES",
+           "TC_VALIDATE", "TC_TIMING"]
 
 
 class TCError(RuntimeError):
@@ -67,10 +69,18 @@ class Options:
     chunk_work: int = 0
     grid_blocks: int = 0
     wave_max_owner: int = 0
+    sched_table: torch.Tensor | None = None   # int32[TC_NUM_BUCKETS] on the device: selects TC_SCHED_TABLE
 
     def to_c(self):
         o = _capi.tc_options()
-        o.schedule = self.schedule
+        if self.sched_table is not None:
+            t = self.sched_table
+            if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous() or t.numel() != TC_NUM_BUCKETS:
+                raise ValueError("sched_table must be a contiguous int32 CUDA tensor of TC_NUM_BUCKETS entries")
+            o.schedule = TC_SCHED_TABLE
+            o.sched_table = t.data_ptr()
+        else:
+            o.schedule = self.schedule
         o.force_strategy = self.force_strategy
         o.flags = (TC_VALIDATE if self.validate else 0) | (TC_TIMING if self.timing else 0)
         o.wave_slots = self.wave_slots
@@ -173,18 +183,51 @@ class Counter:
         self.ws_bytes = need.value
         self.ws = workspace(need.value, device)
 
-    def __call__(self, row_ptr, col, levels=None, stream=None) -> CountResult:
+    def __call__(self, row_ptr, col, levels=None, stream=None, profile=None) -> CountResult:
+        """Count; with ``profile`` (see :func:`new_profile`) the instrumented
+        kernels also add the per-bucket costs into it."""
         lib = _capi.load()
         st = _capi.tc_stats()
-        T = lib.tc_count(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(levels), ctypes.byref(self._opt),
-                         ctypes.byref(st), _ptr(self.ws), self.ws_bytes, _stream(stream))
+        if profile is None:
+            T = lib.tc_count(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(levels), ctypes.byref(self._opt),
+                             ctypes.byref(st), _ptr(self.ws), self.ws_bytes, _stream(stream))
+        else:
+            _check_profile(profile)
+            T = lib.tc_count_profile(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(levels),
+                                     ctypes.byref(self._opt), ctypes.byref(st), _ptr(profile), _ptr(self.ws),
+                                     self.ws_bytes, _stream(stream))
         if T == TC_COUNT_ERROR:
-            raise TCError(lib.tc_last_error(), "tc_count")
+            raise TCError(lib.tc_last_error(), "tc_count_profile" if profile is not None else "tc_count")
         return CountResult(
             T=int(T), T0=int(st.T0), T1=int(st.T1), e0=int(st.e0), units=int(st.units), items=int(st.items),
             probes=int(st.probes), hashed=int(st.hashed), levels=int(st.levels), bfs_rounds=int(st.bfs_rounds),
             ms={"bfs": st.ms_bfs, "partition": st.ms_partition, "bucket": st.ms_bucket, "isect": st.ms_isect},
             strategy_items={STRATEGY_NAMES[k]: int(st.strategy_items[k]) for k in range(TC_NUM_STRATEGIES)})
+
+
+PROFILE_LEN = TC_NUM_BUCKETS * TC_NUM_STRATEGIES * 3
+
+
+def new_profile(device=None) -> torch.Tensor:
+    """A zeroed per-(bucket, strategy) profile: int64 view of the C uint64
+    array, shape [TC_NUM_BUCKETS, TC_NUM_STRATEGIES, 3] = (wavefront-ticks,
+    elements, items)."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    return torch.zeros(TC_NUM_BUCKETS, TC_NUM_STRATEGIES, 3, dtype=torch.int64, device=dev)
+
+
+def _check_profile(p):
+    if p.dtype != torch.int64 or not p.is_cuda or not p.is_contiguous() or p.numel() != PROFILE_LEN:
+        raise ValueError("profile must come from new_profile()")
+
+
+def count_profile(row_ptr: torch.Tensor, col: torch.Tensor, profile: torch.Tensor, levels: torch.Tensor | None = None,
+                  options: Options | None = None, stream=None) -> CountResult:
+    """tc_count_profile: count and add the per-bucket costs into ``profile``."""
+    _require_i32_cuda(row_ptr, "row_ptr")
+    _require_i32_cuda(col, "col")
+    c = Counter(row_ptr.numel() - 1, col.numel(), options, row_ptr.device)
+    return c(row_ptr, col, levels, stream, profile=profile)
 
 
 def count(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor | None = None,

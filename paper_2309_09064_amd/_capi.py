@@ -31,7 +31,9 @@ TC_NUM_STRATEGIES = 4
 STRATEGY_NAMES = ["wave_hash", "wg_hash", "bsearch", "merge"]
 
 TC_SCHED_HEURISTIC = 0
-TC_SCHED_MLP = 1
+TC_SCHED_TABLE = 1
+TC_NUM_BUCKETS = 2048
+TC_MLP_IN = 3
 
 TC_VALIDATE = 1
 TC_TIMING = 2
@@ -47,6 +49,7 @@ class tc_options(ctypes.Structure):
         ("chunk_work", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
         ("wave_max_owner", ctypes.c_int32),
+        ("sched_table", ctypes.c_void_p),
     ]
 
 
@@ -74,6 +77,8 @@ _lib = None
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_f32 = ctypes.c_float
 _sz = ctypes.c_size_t
 _P = ctypes.POINTER
 
@@ -87,6 +92,18 @@ _SIGNATURES = {
     "tc_bfs_levels": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _P(_i32), _vp, _sz, _vp]),
     "tc_count_ws": (ctypes.c_int, [_i32, _i64, _P(tc_options), _P(_sz)]),
     "tc_count": (ctypes.c_uint64, [_i32, _i64, _vp, _vp, _vp, _P(tc_options), _P(tc_stats), _vp, _sz, _vp]),
+    "tc_count_profile": (ctypes.c_uint64, [_i32, _i64, _vp, _vp, _vp, _P(tc_options), _P(tc_stats), _vp, _vp, _sz,
+                                           _vp]),
+    "tc_mlp_param_count": (ctypes.c_int, [_i32, _i32, _P(_i64)]),
+    "tc_mlp_init": (ctypes.c_int, [_vp, _i32, _i32, _u64, _vp]),
+    "tc_mlp_forward": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp]),
+    "tc_mlp_grad_ws": (ctypes.c_int, [_i32, _i32, _i32, _P(_sz)]),
+    "tc_mlp_grad": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "tc_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _f32, _f32, _f32, _f32, _vp]),
+    "tc_mlp_train_ws": (ctypes.c_int, [_i32, _i32, _i32, _P(_sz)]),
+    "tc_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _f32, _f32, _f32,
+                                    _f32, _vp, _vp, _sz, _vp]),
+    "tc_mlp_schedule": (ctypes.c_int, [_vp, _i32, _i32, _P(tc_options), _vp, _vp, _vp]),
     "tc_partition_ws": (ctypes.c_int, [_i32, _i64, _P(_sz)]),
     "tc_partition": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _P(_i64), _vp, _sz,
                                     _vp]),

@@ -136,7 +136,7 @@ int make_cfg(const tc_options *opt, CountCfg *cfg, int *flags) {
     CountCfg c;
     *flags = 0;
     if (opt) {
-        if (opt->schedule != TC_SCHED_HEURISTIC && opt->schedule != TC_SCHED_MLP) return TC_ERR_ARG;
+        if (opt->schedule != TC_SCHED_HEURISTIC && opt->schedule != TC_SCHED_TABLE) return TC_ERR_ARG;
         if (opt->force_strategy < TC_STRAT_AUTO || opt->force_strategy >= TC_NUM_STRATEGIES) return TC_ERR_ARG;
         if (opt->wave_slots && (!is_pow2(opt->wave_slots) || opt->wave_slots < 64 || opt->wave_slots > 2048))
             return TC_ERR_ARG;
@@ -144,6 +144,7 @@ int make_cfg(const tc_options *opt, CountCfg *cfg, int *flags) {
             return TC_ERR_ARG;
         if (opt->chunk_work < 0 || opt->grid_blocks < 0 || opt->wave_max_owner < 0) return TC_ERR_ARG;
         c.schedule = opt->schedule;
+        c.table = opt->schedule == TC_SCHED_TABLE ? opt->sched_table : nullptr;
         c.force = opt->force_strategy;
         if (opt->wave_slots) c.wave_slots = opt->wave_slots;
         if (opt->wg_slots) c.wg_slots = opt->wg_slots;
@@ -219,6 +220,9 @@ CountPlan carve_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels) {
 }
 
 }  // namespace
+
+int options_cfg(const tc_options *opt, CountCfg *cfg, int *flags) { return make_cfg(opt, cfg, flags); }
+
 }  // namespace tc
 
 using namespace tc;
@@ -367,14 +371,17 @@ int tc_count_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_byte
     return fail(TC_OK);
 }
 
-uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
-                  const tc_options *opt, tc_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                    const int32_t *d_levels, const tc_options *opt, tc_stats *stats, uint64_t *d_prof, void *ws,
+                    size_t ws_bytes, void *stream) {
     int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
     if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
     CountCfg cfg;
     int flags;
     rc = make_cfg(opt, &cfg, &flags);
     if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
+    if (cfg.schedule == TC_SCHED_TABLE && !cfg.table) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
+    cfg.prof = reinterpret_cast<unsigned long long *>(d_prof);
     size_t need = 0;
     {
         Carver c(nullptr, 0);
@@ -446,6 +453,18 @@ uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_
     for (auto &e : ev) if (e) (void)hipEventDestroy(e);
     fail(TC_OK);
     return co.T0 + co.T1;
+}
+
+uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
+                  const tc_options *opt, tc_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream);
+}
+
+uint64_t tc_count_profile(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                          const int32_t *d_levels, const tc_options *opt, tc_stats *stats, uint64_t *d_prof,
+                          void *ws, size_t ws_bytes, void *stream) {
+    if (!d_prof) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
+    return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, d_prof, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -38,7 +38,7 @@ constexpr int32_t kEmpty = -1;
 
 struct Item {
     int32_t owner;
-    int32_t code;   // kind | strategy << 1
+    int32_t code;   // kind | strategy << 1 | bucket << 3
     int32_t jb, je; // range of c0 positions (owner's N0 row) holding partners
 };
 
@@ -186,7 +186,8 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
                                                          int32_t *__restrict__ bucket_items,
                                                          const int32_t *__restrict__ bucket_off,
                                                          int32_t *__restrict__ bucket_cur, Item *__restrict__ items,
-                                                         unsigned long long *__restrict__ stats) {
+                                                         unsigned long long *__restrict__ stats,
+                                                         unsigned long long *__restrict__ prof) {
     __shared__ int32_t hist[kBuckets];
     __shared__ int32_t bbase[kFill ? kBuckets : 1];
     for (int i = threadIdx.x; i < kBuckets; i += kItemThreads) hist[i] = 0;
@@ -222,6 +223,8 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
         st[k] = s;
         nchs[k] = (int32_t)nch;
         loc[k] = atomicAdd(&hist[b], (int32_t)nch);
+        if (!kFill && prof)   // profile: the bucket's elements (partners streamed + owner list)
+            atomicAdd(&prof[(b * TC_NUM_STRATEGIES + s) * 3 + 1], w + (unsigned long long)sx);
         if (!kFill) {
             const unsigned long long nc = (unsigned long long)nch;
             ++units;
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
         const int32_t jb = rp0[x], je = rp0[x + 1];
         const int64_t len = je - jb;
         const int32_t pos = bbase[bk[k]] + loc[k];
-        const int32_t code = (int32_t)(u & 1) | (st[k] << 1);
+        const int32_t code = (int32_t)(u & 1) | (st[k] << 1) | (bk[k] << 3);
         for (int32_t c = 0; c < nchs[k]; ++c) {
             Item it;
             it.owner = x;
@@ -568,9 +571,14 @@ __device__ __forceinline__ int table_log2(int32_t sx, int max_log2) {
     return lg;
 }
 
+// kProf adds the profile: per (bucket, strategy) the wavefront-ticks of the
+// items (elapsed constant-clock ticks times the wavefronts an item occupies)
+// and the item count, accumulated into prof[(b * 4 + s) * 3 + {0, 2}].
+template <bool kProf>
 __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__restrict__ items,
                                                           int32_t *__restrict__ q, int wg_log2, int wave_log2,
-                                                          int table_ints, unsigned long long *__restrict__ tri) {
+                                                          int table_ints, unsigned long long *__restrict__ tri,
+                                                          unsigned long long *__restrict__ prof) {
     extern __shared__ int32_t lds[];
     __shared__ int32_t s_item, s_chunk;
     const int32_t n_wg = q[2], n_all = q[3];
@@ -587,6 +595,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         __syncthreads();
         const int32_t it = s_item;
         if (it >= n_wg) break;
+        const uint64_t t_beg = kProf ? wall_clock64() : 0;
         const Item item = items[it];
         const int kind = item.code & 1;
         const int32_t x = item.owner;
@@ -612,6 +621,11 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         }
         if (kind == 0) acc0 += h; else acc1 += h;
         __syncthreads();   // the table, s_item and s_chunk are reused by the next item
+        if (kProf && threadIdx.x == 0) {
+            unsigned long long *pr = prof + ((item.code >> 3) * TC_NUM_STRATEGIES + TC_STRAT_WG_HASH) * 3;
+            atomicAdd(&pr[0], (unsigned long long)(wall_clock64() - t_beg) * kIsectWaves);
+            atomicAdd(&pr[2], 1ull);
+        }
     }
 
     // ---- wavefront items, static round-robin over all wavefronts.  Items
@@ -620,9 +634,10 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
     int32_t *tab = lds + (w << wave_log2);
     const int32_t G = (int32_t)gridDim.x * kIsectWaves;
     for (int32_t it = n_wg + (int32_t)blockIdx.x * kIsectWaves + w; it < n_all; it += G) {
+        const uint64_t t_beg = kProf ? wall_clock64() : 0;
         const Item item = items[it];
         const int kind = item.code & 1;
-        const int strat = item.code >> 1;
+        const int strat = (item.code >> 1) & 3;
         const int32_t x = item.owner;
         const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
         const int32_t sx = list_size(kind, g.up0, g.rp1, x);
@@ -650,6 +665,11 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
                               });
         }
         if (kind == 0) acc0 += h; else acc1 += h;
+        if (kProf && l == 0) {
+            unsigned long long *pr = prof + ((item.code >> 3) * TC_NUM_STRATEGIES + strat) * 3;
+            atomicAdd(&pr[0], (unsigned long long)(wall_clock64() - t_beg));
+            atomicAdd(&pr[2], 1ull);
+        }
     }
 
     const uint64_t t0 = wave_sum(acc0);
@@ -744,12 +764,12 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         TC_HIP_TRY(hipGetLastError());
         const unsigned gu = grid_for(2 * (int64_t)n, kItemThreads * kUnitsPerThread, (int64_t)1 << 30);
         hipLaunchKernelGGL((k_items<0>), dim3(gu), dim3(kItemThreads), 0, s, n, pb.rp0, pb.up0, pb.rp1, L.cnt,
-                           L.work, sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats);
+                           L.work, sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats, cfg.prof);
         TC_HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_bucket_order, dim3(1), dim3(1024), 0, s, L.bucket_items, sc, L.bucket_off, L.q);
         TC_HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL((k_items<1>), dim3(gu), dim3(kItemThreads), 0, s, n, pb.rp0, pb.up0, pb.rp1, L.cnt,
-                           L.work, sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats);
+                           L.work, sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats, nullptr);
         TC_HIP_TRY(hipGetLastError());
     }
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev[1], s));
@@ -757,17 +777,20 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         int table_ints = 1 << wg_log2;
         if ((kIsectWaves << wave_log2) > table_ints) table_ints = kIsectWaves << wave_log2;
         const size_t lds_bytes = (size_t)(table_ints + kIsectWaves * kScratchInts) * sizeof(int32_t);
-        TC_HIP_TRY(hipFuncSetAttribute((const void *)k_isect, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds_bytes));
+        const void *kern = cfg.prof ? (const void *)k_isect<true> : (const void *)k_isect<false>;
+        TC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
         int per_cu = 1;
-        TC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_isect, kIsectThreads,
-                                                                 lds_bytes));
+        TC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kIsectThreads, lds_bytes));
         if (per_cu < 1) per_cu = 1;
         if (getenv("TC_LOG")) fprintf(stderr, "libtc: k_isect %d blocks/CU, %zu B LDS\n", per_cu, lds_bytes);
         const unsigned gi = cfg.grid_blocks > 0 ? (unsigned)cfg.grid_blocks : (unsigned)(di.cus * per_cu);
         Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1};
-        hipLaunchKernelGGL(k_isect, dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items, L.q, wg_log2,
-                           wave_log2, table_ints, L.stats + 8);
+        if (cfg.prof)
+            hipLaunchKernelGGL(k_isect<true>, dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items, L.q,
+                               wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof);
+        else
+            hipLaunchKernelGGL(k_isect<false>, dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items, L.q,
+                               wg_log2, wave_log2, table_ints, L.stats + 8, nullptr);
         TC_HIP_TRY(hipGetLastError());
     }
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev[2], s));

@@ -188,8 +188,11 @@ struct CountCfg {
     int grid_blocks = 0;
     int wave_max_owner = 0;
     const int32_t *table = nullptr;   // device per-bucket strategies (schedule)
+    unsigned long long *prof = nullptr;   // device per-(bucket, strategy) profile, or NULL
     bool timing = false;
 };
+// Checked options -> configuration (TC_ERR_ARG for invalid options).
+int options_cfg(const tc_options *opt, CountCfg *cfg, int *flags);
 size_t count_ws_bytes(int32_t n, int64_t nnz);
 int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, CountOut *out,
               void *ws, size_t ws_bytes, hipStream_t s);

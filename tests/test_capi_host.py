@@ -111,3 +111,53 @@ def test_build_csr_rejects_before_device(lib):
                             None) == _capi.TC_ERR_OVERFLOW
     assert lib.tc_build_csr(10, 5, fake, fake, fake, fake, 10, ctypes.byref(nnz), fake, 8,
                             None) == _capi.TC_ERR_WORKSPACE
+
+
+def test_table_schedule_needs_a_table_before_device(lib):
+    fake = ctypes.c_void_p(0x1000)
+    opt = _capi.tc_options()
+    opt.schedule = _capi.TC_SCHED_TABLE
+    out = ctypes.c_size_t()
+    assert lib.tc_count_ws(10, 20, ctypes.byref(opt), ctypes.byref(out)) == _capi.TC_OK   # size needs no table
+    T = lib.tc_count(10, 20, fake, fake, None, ctypes.byref(opt), None, fake, 1 << 30, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_ARG
+
+
+def test_count_profile_needs_a_buffer_before_device(lib):
+    fake = ctypes.c_void_p(0x1000)
+    T = lib.tc_count_profile(10, 20, fake, fake, None, None, None, None, fake, 1 << 30, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_ARG
+
+
+@pytest.mark.parametrize("H,K,ok", [(8, 4, True), (32, 4, True), (64, 8, True), (16, 1, True), (12, 4, False),
+                                    (32, 0, False), (32, 9, False), (128, 4, False)])
+def test_mlp_sizes(lib, H, K, ok):
+    cnt = ctypes.c_int64()
+    rc = lib.tc_mlp_param_count(H, K, ctypes.byref(cnt))
+    if ok:
+        assert rc == _capi.TC_OK and cnt.value == 3 * H + H + H * H + H + K * H + K
+    else:
+        assert rc == _capi.TC_ERR_ARG
+
+
+def test_mlp_args_rejected_before_device(lib):
+    fake = ctypes.c_void_p(0x1000)
+    sz = ctypes.c_size_t()
+    assert lib.tc_mlp_grad_ws(32, 4, 0, ctypes.byref(sz)) == _capi.TC_ERR_ARG
+    assert lib.tc_mlp_grad_ws(32, 4, 10, ctypes.byref(sz)) == _capi.TC_OK and sz.value >= 10 * (4 * 32 + 2) * 4
+    assert lib.tc_mlp_train_ws(32, 4, 10, ctypes.byref(sz)) == _capi.TC_OK
+    # missing workspace / too small / misaligned
+    assert lib.tc_mlp_grad(fake, 32, 4, fake, fake, fake, 10, fake, None, None, 0, None) == _capi.TC_ERR_WORKSPACE
+    assert lib.tc_mlp_grad(fake, 32, 4, fake, fake, fake, 10, fake, None, fake, 64, None) == _capi.TC_ERR_WORKSPACE
+    # Adam: step 0, beta outside [0, 1), negative lr
+    assert lib.tc_mlp_adam(fake, fake, fake, fake, 10, 0, 0.01, 0.9, 0.999, 1e-8, None) == _capi.TC_ERR_ARG
+    assert lib.tc_mlp_adam(fake, fake, fake, fake, 10, 1, 0.01, 1.0, 0.999, 1e-8, None) == _capi.TC_ERR_ARG
+    assert lib.tc_mlp_adam(fake, fake, fake, fake, 10, 1, -0.01, 0.9, 0.999, 1e-8, None) == _capi.TC_ERR_ARG
+    assert lib.tc_mlp_adam(fake, fake, fake, fake, 0, 1, 0.01, 0.9, 0.999, 1e-8, None) == _capi.TC_OK   # no-op
+    # the schedule needs K = 4 strategies and valid options
+    opt = _capi.tc_options()
+    assert lib.tc_mlp_schedule(fake, 32, 3, ctypes.byref(opt), fake, None, None) == _capi.TC_ERR_ARG
+    opt.wave_slots = 100
+    assert lib.tc_mlp_schedule(fake, 32, 4, ctypes.byref(opt), fake, None, None) == _capi.TC_ERR_ARG
+    assert lib.tc_mlp_forward(fake, 32, 4, fake, 0, fake, None) == _capi.TC_OK   # zero rows: no-op
+    assert lib.tc_mlp_forward(fake, 32, 4, fake, -1, fake, None) == _capi.TC_ERR_ARG
