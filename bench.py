@@ -9,6 +9,9 @@ the CSR) and stays resident in HBM.
 Prints one JSON line.  Default workload: Graph500-style Kronecker graph,
 scale 20, edgefactor 16, initiator (.57, .19, .19, .05), seed 1.
 
+`value` is the heuristic ("plain") schedule; `config.learned_schedule` holds the
+same steps under the learned cost network's strategy table.
+
 The roofline object describes the intersection kernel (k_isect): its
 algorithmic bytes per launch over its mean duration, taken from HIP events
 that the library records around the launch on its own stream during the
@@ -98,6 +101,24 @@ def copy_probe(torch):
     del a, b
 
 
+def timed_steps(counter, rp, col, steps, warmup):
+    """Mean wall time per step (seconds) and the per-step results."""
+    import torch
+    for _ in range(warmup):
+        counter(rp, col)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        results.append(counter(rp, col))
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, results
+
+
+def phase_means(results):
+    return {k: float(np.mean([x.ms[k] for x in results])) for k in ("bfs", "partition", "bucket", "isect")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +127,7 @@ def main():
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-schedule leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -130,23 +152,33 @@ def main():
     # TC_TIMING makes the library record HIP events around each phase on the
     # stream it launches on; the cost is four event records per phase
     counter = tc.Counter(n, nnz, tc.Options(timing=True))
-    for _ in range(args.warmup):
-        counter(rp, col)
-    torch.cuda.synchronize()
-    results = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        results.append(counter(rp, col))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    step_s = (t1 - t0) / args.steps
+    step_s, results = timed_steps(counter, rp, col, args.steps, args.warmup)
     Ts = {r.T for r in results}
     assert len(Ts) == 1, "count changed between steps"
     r = results[-1]
     T = r.T
-    ms = {k: float(np.mean([x.ms[k] for x in results])) for k in ("bfs", "partition", "bucket", "isect")}
+    ms = phase_means(results)
     print(f"# timed: {args.steps} steps, {step_s * 1e3:.3f} ms/step, T={T}; phase ms {ms}", file=sys.stderr,
           flush=True)
+
+    learned = None
+    if not args.no_learned:
+        # learned schedule: profile this graph under each forced strategy,
+        # train the cost network on the profile, schedule (all untimed), then
+        # time the same steps with the network's strategy table
+        from paper_2309_09064_amd import sched
+        t_l0 = time.perf_counter()
+        table, net, ds, losses = sched.learn_schedule([(rp, col)], steps=3000, lr=1e-2)
+        t_l1 = time.perf_counter()
+        lcounter = tc.Counter(n, nnz, tc.Options(timing=True, sched_table=table))
+        lstep_s, lres = timed_steps(lcounter, rp, col, args.steps, args.warmup)
+        assert all(x.T == T for x in lres), "learned schedule changed the count"
+        lms = phase_means(lres)
+        learned = {"value": m / lstep_s, "ms_per_step": lstep_s * 1e3, "phase_ms": lms,
+                   "strategy_items": lres[-1].strategy_items, "train_rows": int(len(ds.c)),
+                   "final_loss": float(losses[-1]), "profile_and_train_s": t_l1 - t_l0,
+                   "trained_on": "this graph's own profile (one untimed pass per forced strategy)"}
+        print(f"# learned schedule: {lstep_s * 1e3:.3f} ms/step; phase ms {lms}", file=sys.stderr, flush=True)
 
     lev, _ = tc.bfs_levels(rp, col)
     rp_h, col_h, lev_h = rp.cpu().numpy(), col.cpu().numpy(), lev.cpu().numpy()
@@ -188,7 +220,8 @@ def main():
                                f"seed {args.seed}, int32 CSR, heuristic schedule",
                    "n": n, "m": m, "triangles": T, "T0": r.T0, "T1": r.T1, "e0": r.e0,
                    "k_percent": round(100.0 * r.e0 / m, 2), "levels": r.levels, "counts_bit_exact": exact,
-                   "phase_ms": ms, "items": r.items, "strategy_items": r.strategy_items},
+                   "phase_ms": ms, "items": r.items, "strategy_items": r.strategy_items,
+                   "learned_schedule": learned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_isect",
                      "bytes_per_launch": balg, "ms_per_launch": ms["isect"]},

@@ -243,8 +243,9 @@ uint64_t tc_count_profile(int32_t n, int64_t nnz, const int32_t *d_row_ptr, cons
  * Parameters: device float32, row-major, in the order W1[H][3], b1[H],
  * W2[H][H], b2[H], W3[K][H], b3[K]; tc_mlp_param_count gives their number.
  * Supported sizes: H in {8, 16, 32, 64}, 1 <= K <= 8.  A training row is
- * (x[3], c, t): features, the strategy measured, its measured cost; the loss
- * of R rows is (1/R) * sum 0.5 * (y[c] - t)^2, minimised by Adam.
+ * (x[3], c, t, w): features, the strategy measured, its measured cost, a
+ * weight w >= 0 (all 1 when d_w is NULL); the loss of R rows is
+ * sum w * 0.5 * (y[c] - t)^2 / sum w, minimised by Adam.
  */
 #define TC_MLP_IN 3
 
@@ -259,15 +260,16 @@ int tc_mlp_init(float *d_params, int32_t hidden, int32_t k, uint64_t seed, void 
 int tc_mlp_forward(const float *d_params, int32_t hidden, int32_t k, const float *d_x, int32_t rows,
                    float *d_y, void *stream);
 
-/* Loss and gradient over rows r < rows (d_c int32[rows] in [0, K); a row
- * with another index contributes nothing), d_t
- * float[rows]); d_grad float[param_count] (same layout as the parameters),
+/* Loss and gradient over rows r < rows: d_c int32[rows] in [0, K) (a row
+ * with another index contributes nothing but still counts in sum w), d_t
+ * float[rows], d_w float[rows] or NULL; the sum of the weights must be
+ * positive.  d_grad float[param_count] (same layout as the parameters),
  * d_loss float[1] (NULL ok).  The sums over rows run in a fixed order in
  * float64, so the result is deterministic.  rows >= 1. */
 int tc_mlp_grad_ws(int32_t hidden, int32_t k, int32_t rows, size_t *h_ws_bytes);
 int tc_mlp_grad(const float *d_params, int32_t hidden, int32_t k, const float *d_x, const int32_t *d_c,
-                const float *d_t, int32_t rows, float *d_grad, float *d_loss, void *ws, size_t ws_bytes,
-                void *stream);
+                const float *d_t, const float *d_w, int32_t rows, float *d_grad, float *d_loss, void *ws,
+                size_t ws_bytes, void *stream);
 
 /* One Adam step (Kingma and Ba, with bias correction) on count parameters:
  * m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
@@ -282,8 +284,9 @@ int tc_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, in
  * gradient, i.e. tc_mlp_train_ws. */
 int tc_mlp_train_ws(int32_t hidden, int32_t k, int32_t rows, size_t *h_ws_bytes);
 int tc_mlp_train(float *d_params, float *d_m, float *d_v, int32_t hidden, int32_t k, const float *d_x,
-                 const int32_t *d_c, const float *d_t, int32_t rows, int32_t first_step, int32_t steps, float lr,
-                 float beta1, float beta2, float eps, float *d_loss, void *ws, size_t ws_bytes, void *stream);
+                 const int32_t *d_c, const float *d_t, const float *d_w, int32_t rows, int32_t first_step,
+                 int32_t steps, float lr, float beta1, float beta2, float eps, float *d_loss, void *ws,
+                 size_t ws_bytes, void *stream);
 
 /* The learned schedule: for every bucket b, the strategy with the smallest
  * predicted cost among those feasible under opt (a wavefront or workgroup

@@ -7,8 +7,9 @@ kernel runs a bucket of work, so it never changes a count.  Its definition:
     a2 = relu(W2 a1 + b2)       W2: [H, H]
     y  = W3 a2 + b3             W3: [K, H]     (one predicted cost per candidate)
 
-A training row is (x, c, t): features x, candidate index c, measured target t.
-The loss over a batch of B rows is  (1/B) * sum_i 0.5 * (y_i[c_i] - t_i)^2.
+A training row is (x, c, t, w): features x, candidate index c, measured
+target t, weight w >= 0 (1 when no weights are given).  The loss over a
+batch is  sum_i w_i * 0.5 * (y_i[c_i] - t_i)^2 / sum_i w_i.
 The optimiser is Adam (Kingma and Ba, 2015) with bias correction.
 Parameters are stored row-major as float arrays in the order
 W1, b1, W2, b2, W3, b3.
@@ -48,22 +49,28 @@ def forward(params, X):
     return y, (X, z1, a1, z2, a2)
 
 
-def loss(params, X, c, t):
+def _weights(w, B):
+    return np.ones(B) if w is None else np.asarray(w, dtype=np.float64)
+
+
+def loss(params, X, c, t, w=None):
     y, _ = forward(params, X)
     B = X.shape[0]
+    w = _weights(w, B)
     r = y[np.arange(B), c] - t
-    return 0.5 * float(np.mean(r * r))
+    return 0.5 * float(np.sum(w * r * r) / np.sum(w))
 
 
-def loss_and_grad(params, X, c, t):
+def loss_and_grad(params, X, c, t, w=None):
     """Loss and gradients (same order as ``params``) by backpropagation."""
     W1, b1, W2, b2, W3, b3 = params
     y, (X, z1, a1, z2, a2) = forward(params, X)
     B = X.shape[0]
+    w = _weights(w, B)
     r = y[np.arange(B), c] - t
-    L = 0.5 * float(np.mean(r * r))
+    L = 0.5 * float(np.sum(w * r * r) / np.sum(w))
     dy = np.zeros_like(y)
-    dy[np.arange(B), c] = r / B
+    dy[np.arange(B), c] = w * r / np.sum(w)
     gW3 = dy.T @ a2
     gb3 = dy.sum(axis=0)
     da2 = dy @ W3

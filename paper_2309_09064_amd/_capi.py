@@ -98,11 +98,11 @@ _SIGNATURES = {
     "tc_mlp_init": (ctypes.c_int, [_vp, _i32, _i32, _u64, _vp]),
     "tc_mlp_forward": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp]),
     "tc_mlp_grad_ws": (ctypes.c_int, [_i32, _i32, _i32, _P(_sz)]),
-    "tc_mlp_grad": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "tc_mlp_grad": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     "tc_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _f32, _f32, _f32, _f32, _vp]),
     "tc_mlp_train_ws": (ctypes.c_int, [_i32, _i32, _i32, _P(_sz)]),
-    "tc_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _f32, _f32, _f32,
-                                    _f32, _vp, _vp, _sz, _vp]),
+    "tc_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _f32, _f32,
+                                    _f32, _f32, _vp, _vp, _sz, _vp]),
     "tc_mlp_schedule": (ctypes.c_int, [_vp, _i32, _i32, _P(tc_options), _vp, _vp, _vp]),
     "tc_partition_ws": (ctypes.c_int, [_i32, _i64, _P(_sz)]),
     "tc_partition": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _P(_i64), _vp, _sz,

@@ -133,12 +133,14 @@ __global__ __launch_bounds__(kRowThreads) void k_mlp_forward(const float *__rest
 // ---------------------------------------------------------------- gradient
 
 // Per row: a1, a2, dz1, dz2 (H each), dy at the measured output, the row's
-// loss term.  Row stride 4H + 2 floats.
+// loss term, all before the division by the total weight W (applied to the
+// sums).  Row stride 4H + 2 floats.
 template <int H>
 __global__ __launch_bounds__(kRowThreads) void k_mlp_rows(const float *__restrict__ params, Net n,
                                                             const float *__restrict__ X,
                                                             const int32_t *__restrict__ C,
-                                                            const float *__restrict__ Tgt, int32_t rows,
+                                                            const float *__restrict__ Tgt,
+                                                            const float *__restrict__ Wt, int32_t rows,
                                                             float *__restrict__ rowbuf) {
     extern __shared__ float sp[];
     load_params(sp, params, n.P);
@@ -155,7 +157,8 @@ __global__ __launch_bounds__(kRowThreads) void k_mlp_rows(const float *__restric
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) yc = k == c ? y[k] : yc;
     const float res = live ? yc - Tgt[r] : 0.f;
-    const float dyc = res / (float)rows;
+    const float w = Wt ? Wt[r] : 1.f;
+    const float dyc = w * res;
     const float *W2 = sp + n.oW2, *W3 = sp + n.oW3;
     float dz2[H];
 #pragma unroll
@@ -175,23 +178,30 @@ __global__ __launch_bounds__(kRowThreads) void k_mlp_rows(const float *__restric
         o[3 * H + j] = dz2[j];
     }
     o[4 * H] = dyc;
-    o[4 * H + 1] = 0.5f * res * res;
+    o[4 * H + 1] = 0.5f * w * res * res;
 }
 
 // One thread per parameter (plus one for the loss): its sum over all rows,
-// in row order, in float64.
+// in row order, in float64, divided by the total weight W (the row count
+// when there are no weights).
 __global__ __launch_bounds__(kRowThreads) void k_mlp_sums(Net n, const float *__restrict__ X,
-                                                            const int32_t *__restrict__ C, int32_t rows,
+                                                            const int32_t *__restrict__ C,
+                                                            const float *__restrict__ Wt, int32_t rows,
                                                             const float *__restrict__ rowbuf,
                                                             float *__restrict__ grad, float *__restrict__ loss) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p > n.P) return;
     const int H = n.H;
     const int64_t S = 4 * H + 2;
+    double wsum = rows;
+    if (Wt) {
+        wsum = 0.0;
+        for (int32_t r = 0; r < rows; ++r) wsum += Wt[r];
+    }
     double acc = 0.0;
     if (p == n.P) {
         for (int32_t r = 0; r < rows; ++r) acc += (double)rowbuf[r * S + 4 * H + 1];
-        if (loss) loss[0] = (float)(acc / rows);
+        if (loss) loss[0] = (float)(acc / wsum);
         return;
     }
     if (p < n.ob1) {                       // W1[j][q] = sum dz1[j] x[q]
@@ -215,7 +225,7 @@ __global__ __launch_bounds__(kRowThreads) void k_mlp_sums(Net n, const float *__
         for (int32_t r = 0; r < rows; ++r)
             if (C[r] == k) acc += rowbuf[r * S + 4 * H];
     }
-    grad[p] = (float)acc;
+    grad[p] = (float)(acc / wsum);
 }
 
 // ---------------------------------------------------------------- Adam
@@ -296,11 +306,11 @@ struct LaunchForward {
 
 template <int H>
 struct LaunchRows {
-    static int run(const float *params, Net n, const float *X, const int32_t *C, const float *T, int32_t rows,
-                   float *rowbuf, hipStream_t s) {
+    static int run(const float *params, Net n, const float *X, const int32_t *C, const float *T, const float *W,
+                   int32_t rows, float *rowbuf, hipStream_t s) {
         const unsigned g = (unsigned)((rows + kRowThreads - 1) / kRowThreads);
         hipLaunchKernelGGL(k_mlp_rows<H>, dim3(g), dim3(kRowThreads), n.P * sizeof(float), s, params, n, X, C, T,
-                           rows, rowbuf);
+                           W, rows, rowbuf);
         TC_HIP_TRY(hipGetLastError());
         return TC_OK;
     }
@@ -320,11 +330,11 @@ struct LaunchSchedule {
 
 size_t rowbuf_bytes(int H, int32_t rows) { return (size_t)rows * (4 * H + 2) * sizeof(float); }
 
-int grad_run(const float *params, Net n, const float *X, const int32_t *C, const float *T, int32_t rows,
-             float *grad, float *loss, float *rowbuf, hipStream_t s) {
-    TC_TRY(by_hidden<LaunchRows>(n.H, params, n, X, C, T, rows, rowbuf, s));
+int grad_run(const float *params, Net n, const float *X, const int32_t *C, const float *T, const float *W,
+             int32_t rows, float *grad, float *loss, float *rowbuf, hipStream_t s) {
+    TC_TRY(by_hidden<LaunchRows>(n.H, params, n, X, C, T, W, rows, rowbuf, s));
     const unsigned g = (unsigned)((n.P + 1 + kRowThreads - 1) / kRowThreads);
-    hipLaunchKernelGGL(k_mlp_sums, dim3(g), dim3(kRowThreads), 0, s, n, X, C, rows, rowbuf, grad, loss);
+    hipLaunchKernelGGL(k_mlp_sums, dim3(g), dim3(kRowThreads), 0, s, n, X, C, W, rows, rowbuf, grad, loss);
     TC_HIP_TRY(hipGetLastError());
     return TC_OK;
 }
@@ -398,8 +408,8 @@ int tc_mlp_grad_ws(int32_t hidden, int32_t k, int32_t rows, size_t *h_ws_bytes) 
 }
 
 int tc_mlp_grad(const float *d_params, int32_t hidden, int32_t k, const float *d_x, const int32_t *d_c,
-                const float *d_t, int32_t rows, float *d_grad, float *d_loss, void *ws, size_t ws_bytes,
-                void *stream) {
+                const float *d_t, const float *d_w, int32_t rows, float *d_grad, float *d_loss, void *ws,
+                size_t ws_bytes, void *stream) {
     if (!valid_hk(hidden, k) || rows < 1) return ret(TC_ERR_ARG);
     if (!d_params || !d_x || !d_c || !d_t || !d_grad) return ret(TC_ERR_ARG);
     Carver c(ws, ws_bytes);
@@ -408,7 +418,7 @@ int tc_mlp_grad(const float *d_params, int32_t hidden, int32_t k, const float *d
     DeviceInfo di;
     int rc = device_info(&di);
     if (rc != TC_OK) return ret(rc);
-    return ret(grad_run(d_params, net_of(hidden, k), d_x, d_c, d_t, rows, d_grad, d_loss, rowbuf,
+    return ret(grad_run(d_params, net_of(hidden, k), d_x, d_c, d_t, d_w, rows, d_grad, d_loss, rowbuf,
                         static_cast<hipStream_t>(stream)));
 }
 
@@ -434,7 +444,8 @@ int tc_mlp_train_ws(int32_t hidden, int32_t k, int32_t rows, size_t *h_ws_bytes)
 }
 
 int tc_mlp_train(float *d_params, float *d_m, float *d_v, int32_t hidden, int32_t k, const float *d_x,
-                 const int32_t *d_c, const float *d_t, int32_t rows, int32_t first_step, int32_t steps, float lr,
+                 const int32_t *d_c, const float *d_t, const float *d_w, int32_t rows, int32_t first_step,
+                 int32_t steps, float lr,
                  float beta1, float beta2, float eps, float *d_loss, void *ws, size_t ws_bytes, void *stream) {
     if (!valid_hk(hidden, k) || rows < 1 || steps < 0) return ret(TC_ERR_ARG);
     if (!adam_args_ok(first_step, lr, beta1, beta2, eps)) return ret(TC_ERR_ARG);
@@ -450,7 +461,7 @@ int tc_mlp_train(float *d_params, float *d_m, float *d_v, int32_t hidden, int32_
     if (rc != TC_OK) return ret(rc);
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int32_t i = 0; i < steps; ++i) {
-        rc = grad_run(d_params, n, d_x, d_c, d_t, rows, grad, d_loss ? d_loss + i : nullptr, rowbuf, s);
+        rc = grad_run(d_params, n, d_x, d_c, d_t, d_w, rows, grad, d_loss ? d_loss + i : nullptr, rowbuf, s);
         if (rc != TC_OK) return ret(rc);
         rc = adam_run(d_params, grad, d_m, d_v, n.P, first_step + i, lr, beta1, beta2, eps, s);
         if (rc != TC_OK) return ret(rc);

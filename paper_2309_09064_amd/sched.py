@@ -61,18 +61,18 @@ class CostNet:
                                            _stream()), "tc_mlp_forward")
         return Y
 
-    def grad(self, X, c, t):
+    def grad(self, X, c, t, w=None):
         """(loss, gradient) on the batch, without an update."""
         lib = _capi.load()
-        X, c, t = self._batch(X, c, t)
+        X, c, t, w = self._batch(X, c, t, w)
         rows = X.shape[0]
         need = ctypes.c_size_t()
         _check(lib.tc_mlp_grad_ws(self.hidden, self.k, rows, ctypes.byref(need)), "tc_mlp_grad_ws")
         ws = workspace(need.value, self.device)
         g = torch.empty_like(self.params)
         loss = torch.empty(1, dtype=torch.float32, device=self.device)
-        _check(lib.tc_mlp_grad(_ptr(self.params), self.hidden, self.k, _ptr(X), _ptr(c), _ptr(t), rows, _ptr(g),
-                               _ptr(loss), _ptr(ws), need.value, _stream()), "tc_mlp_grad")
+        _check(lib.tc_mlp_grad(_ptr(self.params), self.hidden, self.k, _ptr(X), _ptr(c), _ptr(t), _ptr(w), rows,
+                               _ptr(g), _ptr(loss), _ptr(ws), need.value, _stream()), "tc_mlp_grad")
         return float(loss.item()), g
 
     def adam(self, grad: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -80,17 +80,18 @@ class CostNet:
         _check(_capi.load().tc_mlp_adam(_ptr(self.params), _ptr(grad), _ptr(self.m), _ptr(self.v), self.count,
                                         self.step, lr, beta1, beta2, eps, _stream()), "tc_mlp_adam")
 
-    def train(self, X, c, t, steps: int, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8) -> np.ndarray:
+    def train(self, X, c, t, steps: int, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, w=None) -> np.ndarray:
         """``steps`` full-batch Adam steps; returns each step's loss."""
         lib = _capi.load()
-        X, c, t = self._batch(X, c, t)
+        X, c, t, w = self._batch(X, c, t, w)
         rows = X.shape[0]
         need = ctypes.c_size_t()
         _check(lib.tc_mlp_train_ws(self.hidden, self.k, rows, ctypes.byref(need)), "tc_mlp_train_ws")
         ws = workspace(need.value, self.device)
         losses = torch.empty(max(steps, 1), dtype=torch.float32, device=self.device)
         _check(lib.tc_mlp_train(_ptr(self.params), _ptr(self.m), _ptr(self.v), self.hidden, self.k, _ptr(X),
-                                _ptr(c), _ptr(t), rows, self.step + 1, steps, lr, beta1, beta2, eps, _ptr(losses),
+                                _ptr(c), _ptr(t), _ptr(w), rows, self.step + 1, steps, lr, beta1, beta2, eps,
+                                _ptr(losses),
                                 _ptr(ws), need.value, _stream()), "tc_mlp_train")
         self.step += steps
         return losses[:steps].cpu().numpy()
@@ -105,15 +106,19 @@ class CostNet:
                                             _ptr(cost), _stream()), "tc_mlp_schedule")
         return (table, cost) if with_cost else table
 
-    def _batch(self, X, c, t):
+    def _batch(self, X, c, t, w=None):
         X = torch.as_tensor(X, dtype=torch.float32).to(self.device).contiguous()
         c = torch.as_tensor(c, dtype=torch.int32).to(self.device).contiguous()
         t = torch.as_tensor(t, dtype=torch.float32).to(self.device).contiguous()
+        if w is not None:
+            w = torch.as_tensor(w, dtype=torch.float32).to(self.device).contiguous()
         if X.ndim != 2 or X.shape[1] != TC_MLP_IN or c.shape != (X.shape[0],) or t.shape != (X.shape[0],):
             raise ValueError("batch shapes: X [R, 3], c [R], t [R]")
+        if w is not None and (w.shape != (X.shape[0],) or bool((w < 0).any()) or float(w.sum()) <= 0):
+            raise ValueError("weights: [R], non-negative, positive sum")
         if X.shape[0] < 1:
             raise ValueError("empty batch")
-        return X, c, t
+        return X, c, t, w
 
 
 def collect_profile(graphs, options: Options | None = None, strategies=range(TC_NUM_STRATEGIES), repeats: int = 1,
@@ -141,28 +146,34 @@ class Dataset:
     t: np.ndarray        # [R] float32 log2(wavefront-ticks per element)
     bucket: np.ndarray   # [R] bucket id
     elements: np.ndarray  # [R] elements behind the row
+    w: np.ndarray        # [R] float32 training weight
 
 
-def dataset(profile: torch.Tensor, min_elements: int = 1 << 14) -> Dataset:
+def dataset(profile: torch.Tensor, min_elements: int = 1 << 14, weight_power: float = 1.0) -> Dataset:
     """Training rows from a profile: every (bucket, strategy) that ran at
-    least one item over at least ``min_elements`` elements."""
+    least one item over at least ``min_elements`` elements.  A row weighs
+    (elements / max elements) ** weight_power: the time a schedule costs is
+    the elements-weighted sum of its per-element costs, so errors on large
+    buckets matter in proportion."""
     p = profile.cpu().numpy().astype(np.float64)
     ticks, elems, items = p[..., 0], p[..., 1], p[..., 2]
     b, s = np.nonzero((items > 0) & (elems >= min_elements) & (ticks > 0))
     t = np.log2(ticks[b, s] / elems[b, s])
+    e = elems[b, s]
+    w = (e / e.max()) ** weight_power if len(e) else e
     return Dataset(X=bucket_features(b), c=s.astype(np.int32), t=t.astype(np.float32), bucket=b,
-                   elements=elems[b, s])
+                   elements=e, w=w.astype(np.float32))
 
 
 def learn_schedule(graphs, options: Options | None = None, seed: int = 0, steps: int = 3000, lr: float = 1e-2,
-                   repeats: int = 1, min_elements: int = 1 << 14):
+                   repeats: int = 1, min_elements: int = 1 << 14, weight_power: float = 1.0):
     """Profile, train, schedule.  Returns (table, net, dataset, losses)."""
     prof = collect_profile(graphs, options, repeats=repeats)
-    ds = dataset(prof, min_elements)
+    ds = dataset(prof, min_elements, weight_power)
     if len(ds.c) == 0:
         raise ValueError("the profile holds no bucket with enough work to learn from")
     net = CostNet(seed=seed)
-    losses = net.train(ds.X, ds.c, ds.t, steps, lr=lr)
+    losses = net.train(ds.X, ds.c, ds.t, steps, lr=lr, w=ds.w)
     return net.schedule(options), net, ds, losses
 
 

@@ -147,8 +147,8 @@ def test_mlp_args_rejected_before_device(lib):
     assert lib.tc_mlp_grad_ws(32, 4, 10, ctypes.byref(sz)) == _capi.TC_OK and sz.value >= 10 * (4 * 32 + 2) * 4
     assert lib.tc_mlp_train_ws(32, 4, 10, ctypes.byref(sz)) == _capi.TC_OK
     # missing workspace / too small / misaligned
-    assert lib.tc_mlp_grad(fake, 32, 4, fake, fake, fake, 10, fake, None, None, 0, None) == _capi.TC_ERR_WORKSPACE
-    assert lib.tc_mlp_grad(fake, 32, 4, fake, fake, fake, 10, fake, None, fake, 64, None) == _capi.TC_ERR_WORKSPACE
+    assert lib.tc_mlp_grad(fake, 32, 4, fake, fake, fake, None, 10, fake, None, None, 0, None) == _capi.TC_ERR_WORKSPACE
+    assert lib.tc_mlp_grad(fake, 32, 4, fake, fake, fake, None, 10, fake, None, fake, 64, None) == _capi.TC_ERR_WORKSPACE
     # Adam: step 0, beta outside [0, 1), negative lr
     assert lib.tc_mlp_adam(fake, fake, fake, fake, 10, 0, 0.01, 0.9, 0.999, 1e-8, None) == _capi.TC_ERR_ARG
     assert lib.tc_mlp_adam(fake, fake, fake, fake, 10, 1, 0.01, 1.0, 0.999, 1e-8, None) == _capi.TC_ERR_ARG

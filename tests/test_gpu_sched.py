@@ -79,6 +79,23 @@ def test_forward(sched, H, K, rows):
     assert close(y, want, np.abs(want).max())
 
 
+@pytest.mark.parametrize("H,K,rows", [(8, 4, 40), (32, 4, 700)])
+def test_weighted_gradient(sched, H, K, rows):
+    net = sched.CostNet(H, K, seed=rows + 1)
+    X = features(rows, rows + 3)
+    rng = np.random.default_rng(rows + 4)
+    c = rng.integers(0, K, rows).astype(np.int32)
+    t = rng.normal(0, 3, rows).astype(np.float32)
+    w = rng.uniform(0, 5, rows).astype(np.float32)
+    w[::5] = 0.0
+    loss, g = net.grad(X, c, t, w)
+    L, grads = mlp.loss_and_grad(oracle_params(net), X.astype(np.float64), c, t.astype(np.float64),
+                                 w.astype(np.float64))
+    assert abs(loss - L) <= 1e-5 * (1 + L)
+    for a, b in zip(mlp.unflatten(g.cpu().numpy(), K, H), grads):
+        assert np.all(np.abs(a - b) <= 1e-4 * np.abs(b).max() + 1e-7)
+
+
 @pytest.mark.parametrize("H,K,rows", [(8, 4, 17), (32, 4, 1000), (64, 8, 513)])
 def test_gradient(sched, H, K, rows):
     net = sched.CostNet(H, K, seed=rows)

@@ -17,20 +17,21 @@ def batch(K, B=17, seed=0):
     return X, c, t
 
 
-@pytest.mark.parametrize("K,H", [(4, 8), (6, 32)])
-def test_gradients_match_finite_differences(K, H):
+@pytest.mark.parametrize("K,H,weighted", [(4, 8, False), (6, 32, False), (4, 8, True)])
+def test_gradients_match_finite_differences(K, H, weighted):
     params = mlp.init_params(K, H, seed=K)
     X, c, t = batch(K)
-    _, grads = mlp.loss_and_grad(params, X, c, t)
+    w = np.random.default_rng(5).uniform(0, 2, len(t)) if weighted else None
+    _, grads = mlp.loss_and_grad(params, X, c, t, w)
     h = 1e-6
     for p, g in zip(params, grads):
         flat, gflat = p.reshape(-1), g.reshape(-1)
         for i in range(0, flat.size, max(1, flat.size // 40)):
             old = flat[i]
             flat[i] = old + h
-            lp = mlp.loss(params, X, c, t)
+            lp = mlp.loss(params, X, c, t, w)
             flat[i] = old - h
-            lm = mlp.loss(params, X, c, t)
+            lm = mlp.loss(params, X, c, t, w)
             flat[i] = old
             fd = (lp - lm) / (2 * h)
             assert abs(fd - gflat[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, gflat[i])
@@ -61,3 +62,16 @@ def test_adam_first_step_is_lr_times_sign():
         nz = g != 0
         assert np.allclose((b - a)[nz], 0.01 * np.sign(g[nz]))
         assert np.array_equal(a[~nz], b[~nz])
+
+
+def test_weights_scale_free_and_equal_to_duplicated_rows():
+    params = mlp.init_params(4, 8, seed=2)
+    X, c, t = batch(4, B=9)
+    L1, g1 = mlp.loss_and_grad(params, X, c, t)
+    L2, g2 = mlp.loss_and_grad(params, X, c, t, np.full(9, 3.5))        # a constant weight changes nothing
+    assert np.isclose(L1, L2) and all(np.allclose(a, b) for a, b in zip(g1, g2))
+    w = np.array([2, 1, 1, 1, 1, 1, 1, 1, 0], dtype=np.float64)          # weight 2 = the row twice, 0 = dropped
+    Lw, gw = mlp.loss_and_grad(params, X, c, t, w)
+    idx = [0, 0, 1, 2, 3, 4, 5, 6, 7]
+    Ld, gd = mlp.loss_and_grad(params, X[idx], c[idx], t[idx])
+    assert np.isclose(Lw, Ld) and all(np.allclose(a, b) for a, b in zip(gw, gd))
