@@ -209,6 +209,27 @@ uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_
                   size_t ws_bytes, void *stream);
 
 /*
+ * Many graphs in one call.  The batch is one CSR over the disjoint union of
+ * its graphs, vertex ids global: graph g owns the vertex range
+ * [h_vtx_off[g], h_vtx_off[g+1]) and its rows hold only its own vertices.
+ * Every phase runs once over the union (one persistent intersection launch
+ * drains a single work queue for all graphs); a component never spans two
+ * graphs, so each graph's levels, T0 and T1 are those it has on its own.
+ *   graphs     number of graphs (>= 0)
+ *   h_vtx_off  host int64[graphs + 1]: 0 = off[0] <= off[1] <= ... <=
+ *              off[graphs] = n (empty graphs allowed)
+ *   d_counts   device uint64[graphs], output: triangles of each graph
+ * Returns the total over all graphs, or TC_COUNT_ERROR.  TC_ERR_ARG for bad
+ * offsets; with TC_VALIDATE, TC_ERR_INVALID_CSR also when an edge joins two
+ * graphs.  Synchronises.
+ */
+int tc_count_batched_ws(int32_t graphs, int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_bytes);
+uint64_t tc_count_batched(int32_t graphs, const int64_t *h_vtx_off, int32_t n, int64_t nnz,
+                          const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
+                          const tc_options *opt, uint64_t *d_counts, tc_stats *stats, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/*
  * tc_count plus a per-bucket cost profile, the training data of the learned
  * schedule (not part of the paper: it only chooses among exact kernels).
  * Uses the same workspace size as tc_count.  ADDS into

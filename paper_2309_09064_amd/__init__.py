@@ -18,6 +18,7 @@ from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_BUCKETS, TC_NUM_STRAT
                     TC_STRAT_WG_HASH, TC_TIMING, TC_VALIDATE)
 
 __all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count", "count_profile", "workspace",
+           "count_batched", "pack_csr",
            "Counter", "CountResult", "new_profile",
            "STRATEGY_NAMES", "TC_STRAT_AUTO", "TC_STRAT_WAVE_HASH", "TC_STRAT_WG_HASH", "TC_STRAT_BSEARCH",
            "TC_STRAT_MERGE", "TC_SCHED_HEURISTIC", "TC_SCHED_TABLE", "TC_NUM_BUCKETS", "TC_NUM_STRATEGIES",
@@ -228,6 +229,60 @@ def count_profile(row_ptr: torch.Tensor, col: torch.Tensor, profile: torch.Tenso
     _require_i32_cuda(col, "col")
     c = Counter(row_ptr.numel() - 1, col.numel(), options, row_ptr.device)
     return c(row_ptr, col, levels, stream, profile=profile)
+
+
+def _result(T, st) -> CountResult:
+    return CountResult(
+        T=int(T), T0=int(st.T0), T1=int(st.T1), e0=int(st.e0), units=int(st.units), items=int(st.items),
+        probes=int(st.probes), hashed=int(st.hashed), levels=int(st.levels), bfs_rounds=int(st.bfs_rounds),
+        ms={"bfs": st.ms_bfs, "partition": st.ms_partition, "bucket": st.ms_bucket, "isect": st.ms_isect},
+        strategy_items={STRATEGY_NAMES[k]: int(st.strategy_items[k]) for k in range(TC_NUM_STRATEGIES)})
+
+
+def pack_csr(graphs):
+    """Union CSR of several device CSRs [(row_ptr, col), ...]: global ids,
+    plus the host int64 vertex offsets ``vtx_off`` (len(graphs) + 1)."""
+    import numpy as np
+    sizes = [int(rp.numel()) - 1 for rp, _ in graphs]
+    nnzs = [int(c.numel()) for _, c in graphs]
+    voff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eoff = np.concatenate([[0], np.cumsum(nnzs)]).astype(np.int64)
+    if voff[-1] >= 2 ** 31 or eoff[-1] >= 2 ** 31:
+        raise ValueError("the union does not fit an int32 CSR")
+    dev = graphs[0][0].device if graphs else torch.device("cuda", torch.cuda.current_device())
+    rps = [rp[:-1] + int(eoff[g]) for g, (rp, _) in enumerate(graphs)]
+    cols = [c + int(voff[g]) for g, (_, c) in enumerate(graphs)]
+    row_ptr = torch.cat(rps + [torch.tensor([int(eoff[-1])], dtype=torch.int32, device=dev)])
+    col = torch.cat(cols) if cols else torch.zeros(0, dtype=torch.int32, device=dev)
+    return row_ptr.to(torch.int32).contiguous(), col.to(torch.int32).contiguous(), voff
+
+
+def count_batched(row_ptr: torch.Tensor, col: torch.Tensor, vtx_off, levels: torch.Tensor | None = None,
+                  options: Options | None = None, stream=None):
+    """Per-graph triangle counts of a packed batch (see :func:`pack_csr`).
+    Returns (counts: int64 tensor viewing the uint64 counts, CountResult of
+    the whole union)."""
+    import numpy as np
+    _require_i32_cuda(row_ptr, "row_ptr")
+    _require_i32_cuda(col, "col")
+    if levels is not None:
+        _require_i32_cuda(levels, "levels")
+    off = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    graphs = len(off) - 1
+    n, nnz = row_ptr.numel() - 1, col.numel()
+    lib = _capi.load()
+    opt = (options or Options()).to_c()
+    need = ctypes.c_size_t()
+    _check(lib.tc_count_batched_ws(graphs, n, nnz, ctypes.byref(opt), ctypes.byref(need)), "tc_count_batched_ws")
+    ws = workspace(need.value, row_ptr.device)
+    counts = torch.empty(max(graphs, 1), dtype=torch.int64, device=row_ptr.device)
+    st = _capi.tc_stats()
+    T = lib.tc_count_batched(graphs, off.ctypes.data_as(ctypes.c_void_p), n, nnz, _ptr(row_ptr), _ptr(col),
+                             _ptr(levels), ctypes.byref(opt), _ptr(counts), ctypes.byref(st), _ptr(ws),
+                             need.value, _stream(stream))
+    if T == TC_COUNT_ERROR:
+        raise TCError(lib.tc_last_error(), "tc_count_batched")
+    return counts[:graphs], _result(T, st)
 
 
 def count(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor | None = None,

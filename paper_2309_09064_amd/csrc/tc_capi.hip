@@ -184,6 +184,47 @@ int fail(int code) {
 
 // ---------------------------------------------------------------- tc_count layout
 
+// ---------------------------------------------------------------- batches
+
+// gid[v] = the graph whose vertex range [off[g], off[g+1]) holds v.
+__global__ void k_batch_gid(int32_t graphs, const int64_t *__restrict__ off, int32_t n, int32_t *__restrict__ gid) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t lo = 0, hi = graphs - 1;   // last g with off[g] <= v
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    gid[v] = lo;
+}
+
+// bad |= 1 when an edge joins two graphs of the batch.
+__global__ void k_batch_check(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                              const int32_t *__restrict__ gid, int32_t *__restrict__ bad) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int32_t gx = gid[x];
+    for (int32_t e = rp[x]; e < rp[x + 1]; ++e) {
+        const int32_t y = col[e];
+        if (y < 0 || y >= n || gid[y] != gx) {
+            atomicOr(bad, 1);
+            return;
+        }
+    }
+}
+
+struct BatchPlan {
+    int64_t *off;
+    int32_t *gid;
+};
+
+BatchPlan carve_batch(Carver &c, int32_t graphs, int32_t n) {
+    BatchPlan B;
+    B.off = c.take<int64_t>((size_t)graphs + 1);
+    B.gid = c.take<int32_t>(n > 0 ? n : 1);
+    return B;
+}
+
 struct CountPlan {
     int32_t *levels;
     PartBufs pb;
@@ -371,11 +412,26 @@ int tc_count_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_byte
     return fail(TC_OK);
 }
 
+struct BatchArgs {
+    int32_t graphs;
+    const int64_t *h_off;
+    uint64_t *d_counts;
+};
+
 static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                     const int32_t *d_levels, const tc_options *opt, tc_stats *stats, uint64_t *d_prof, void *ws,
-                    size_t ws_bytes, void *stream) {
+                    size_t ws_bytes, void *stream, const BatchArgs *batch = nullptr) {
     int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
     if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
+    if (batch) {   // offsets: 0 = off[0] <= off[1] <= ... <= off[graphs] = n
+        if (batch->graphs < 0 || !batch->h_off || (batch->graphs > 0 && !batch->d_counts)) {
+            fail(TC_ERR_ARG);
+            return TC_COUNT_ERROR;
+        }
+        bool ok = batch->h_off[0] == 0 && batch->h_off[batch->graphs] == n;
+        for (int32_t g = 0; ok && g < batch->graphs; ++g) ok = batch->h_off[g] <= batch->h_off[g + 1];
+        if (!ok || (batch->graphs == 0 && n != 0)) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
+    }
     CountCfg cfg;
     int flags;
     rc = make_cfg(opt, &cfg, &flags);
@@ -386,6 +442,7 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
     {
         Carver c(nullptr, 0);
         carve_plan(c, n, nnz, true);
+        if (batch) carve_batch(c, batch->graphs, n);
         need = c.used();
     }
     rc = check_ws(ws, ws_bytes, need);
@@ -394,6 +451,11 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
     rc = device_info(&di);
     if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (batch && batch->graphs > 0 &&
+        hipMemsetAsync(batch->d_counts, 0, sizeof(uint64_t) * (size_t)batch->graphs, s) != hipSuccess) {
+        fail(TC_ERR_HIP);
+        return TC_COUNT_ERROR;
+    }
     if (n == 0) {   // no vertices, no triangles
         if (stats) memset(stats, 0, sizeof(*stats));
         fail(TC_OK);
@@ -404,6 +466,31 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
     if (flags & TC_VALIDATE) {
         rc = validate_device(n, nnz, d_row_ptr, d_col_idx, d_levels, P.flag, s);
         if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
+    }
+    if (batch) {
+        const BatchPlan B = carve_batch(c, batch->graphs, n);
+        if (hipMemcpyAsync(B.off, batch->h_off, sizeof(int64_t) * ((size_t)batch->graphs + 1), hipMemcpyHostToDevice,
+                           s) != hipSuccess) {
+            fail(TC_ERR_HIP);
+            return TC_COUNT_ERROR;
+        }
+        const unsigned gb = (unsigned)(((int64_t)n + 255) / 256);
+        hipLaunchKernelGGL(k_batch_gid, dim3(gb), dim3(256), 0, s, batch->graphs, B.off, n, B.gid);
+        if (hipGetLastError() != hipSuccess) { fail(TC_ERR_HIP); return TC_COUNT_ERROR; }
+        if (flags & TC_VALIDATE) {
+            int32_t bad = 0;
+            if (hipMemsetAsync(P.flag, 0, sizeof(int32_t), s) != hipSuccess) { fail(TC_ERR_HIP); return TC_COUNT_ERROR; }
+            hipLaunchKernelGGL(k_batch_check, dim3(gb), dim3(256), 0, s, n, d_row_ptr, d_col_idx, B.gid, P.flag);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(&bad, P.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                fail(TC_ERR_HIP);
+                return TC_COUNT_ERROR;
+            }
+            if (bad) { fail(TC_ERR_INVALID_CSR); return TC_COUNT_ERROR; }
+        }
+        cfg.gid = B.gid;
+        cfg.batch_counts = reinterpret_cast<unsigned long long *>(batch->d_counts);
     }
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     const bool timing = (flags & TC_TIMING) != 0;
@@ -458,6 +545,28 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
 uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
                   const tc_options *opt, tc_stats *stats, void *ws, size_t ws_bytes, void *stream) {
     return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream);
+}
+
+int tc_count_batched_ws(int32_t graphs, int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_bytes) {
+    if (!h_ws_bytes || graphs < 0) return fail(TC_ERR_ARG);
+    int rc = check_graph_args(n, nnz, (const void *)1, (const void *)1);
+    if (rc != TC_OK) return fail(rc);
+    CountCfg cfg;
+    int flags;
+    rc = make_cfg(opt, &cfg, &flags);
+    if (rc != TC_OK) return fail(rc);
+    Carver c(nullptr, 0);
+    carve_plan(c, n, nnz, true);
+    carve_batch(c, graphs, n);
+    *h_ws_bytes = c.used();
+    return fail(TC_OK);
+}
+
+uint64_t tc_count_batched(int32_t graphs, const int64_t *h_vtx_off, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
+                          const int32_t *d_col_idx, const int32_t *d_levels, const tc_options *opt,
+                          uint64_t *d_counts, tc_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    const BatchArgs b{graphs, h_vtx_off, d_counts};
+    return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, &b);
 }
 
 uint64_t tc_count_profile(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,

@@ -571,14 +571,22 @@ __device__ __forceinline__ int table_log2(int32_t sx, int max_log2) {
     return lg;
 }
 
+// Per-graph counts of a batch: the graph of every vertex and one counter
+// per graph.
+struct Batch {
+    const int32_t *gid;
+    unsigned long long *counts;
+};
+
 // kProf adds the profile: per (bucket, strategy) the wavefront-ticks of the
 // items (elapsed constant-clock ticks times the wavefronts an item occupies)
 // and the item count, accumulated into prof[(b * 4 + s) * 3 + {0, 2}].
-template <bool kProf>
+// kBatch adds each item's hits to the counter of the owner's graph.
+template <bool kProf, bool kBatch>
 __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__restrict__ items,
                                                           int32_t *__restrict__ q, int wg_log2, int wave_log2,
                                                           int table_ints, unsigned long long *__restrict__ tri,
-                                                          unsigned long long *__restrict__ prof) {
+                                                          unsigned long long *__restrict__ prof, Batch bt) {
     extern __shared__ int32_t lds[];
     __shared__ int32_t s_item, s_chunk;
     const int32_t n_wg = q[2], n_all = q[3];
@@ -620,6 +628,10 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
                               });
         }
         if (kind == 0) acc0 += h; else acc1 += h;
+        if (kBatch) {
+            const unsigned long long hs = wave_sum((unsigned long long)h);
+            if (l == 0 && hs) atomicAdd(&bt.counts[bt.gid[x]], hs);
+        }
         __syncthreads();   // the table, s_item and s_chunk are reused by the next item
         if (kProf && threadIdx.x == 0) {
             unsigned long long *pr = prof + ((item.code >> 3) * TC_NUM_STRATEGIES + TC_STRAT_WG_HASH) * 3;
@@ -665,6 +677,10 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
                               });
         }
         if (kind == 0) acc0 += h; else acc1 += h;
+        if (kBatch) {
+            const unsigned long long hs = wave_sum((unsigned long long)h);
+            if (l == 0 && hs) atomicAdd(&bt.counts[bt.gid[x]], hs);
+        }
         if (kProf && l == 0) {
             unsigned long long *pr = prof + ((item.code >> 3) * TC_NUM_STRATEGIES + strat) * 3;
             atomicAdd(&pr[0], (unsigned long long)(wall_clock64() - t_beg));
@@ -777,7 +793,9 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         int table_ints = 1 << wg_log2;
         if ((kIsectWaves << wave_log2) > table_ints) table_ints = kIsectWaves << wave_log2;
         const size_t lds_bytes = (size_t)(table_ints + kIsectWaves * kScratchInts) * sizeof(int32_t);
-        const void *kern = cfg.prof ? (const void *)k_isect<true> : (const void *)k_isect<false>;
+        const bool batch = cfg.gid != nullptr;
+        const void *kern = cfg.prof ? (batch ? (const void *)k_isect<true, true> : (const void *)k_isect<true, false>)
+                                    : (batch ? (const void *)k_isect<false, true> : (const void *)k_isect<false, false>);
         TC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
         int per_cu = 1;
         TC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kIsectThreads, lds_bytes));
@@ -785,12 +803,19 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         if (getenv("TC_LOG")) fprintf(stderr, "libtc: k_isect %d blocks/CU, %zu B LDS\n", per_cu, lds_bytes);
         const unsigned gi = cfg.grid_blocks > 0 ? (unsigned)cfg.grid_blocks : (unsigned)(di.cus * per_cu);
         Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1};
-        if (cfg.prof)
-            hipLaunchKernelGGL(k_isect<true>, dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items, L.q,
-                               wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof);
+        const Batch bt{cfg.gid, cfg.batch_counts};
+        if (cfg.prof && batch)
+            hipLaunchKernelGGL((k_isect<true, true>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items, L.q,
+                               wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof, bt);
+        else if (cfg.prof)
+            hipLaunchKernelGGL((k_isect<true, false>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
+                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof, bt);
+        else if (batch)
+            hipLaunchKernelGGL((k_isect<false, true>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
+                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, bt);
         else
-            hipLaunchKernelGGL(k_isect<false>, dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items, L.q,
-                               wg_log2, wave_log2, table_ints, L.stats + 8, nullptr);
+            hipLaunchKernelGGL((k_isect<false, false>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
+                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, bt);
         TC_HIP_TRY(hipGetLastError());
     }
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev[2], s));

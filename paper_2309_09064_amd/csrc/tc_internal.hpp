@@ -189,6 +189,8 @@ struct CountCfg {
     int wave_max_owner = 0;
     const int32_t *table = nullptr;   // device per-bucket strategies (schedule)
     unsigned long long *prof = nullptr;   // device per-(bucket, strategy) profile, or NULL
+    const int32_t *gid = nullptr;         // batch: graph of every vertex, or NULL
+    unsigned long long *batch_counts = nullptr;   // batch: one count per graph (zeroed by the caller)
     bool timing = false;
 };
 // Checked options -> configuration (TC_ERR_ARG for invalid options).

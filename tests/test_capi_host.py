@@ -161,3 +161,22 @@ def test_mlp_args_rejected_before_device(lib):
     assert lib.tc_mlp_schedule(fake, 32, 4, ctypes.byref(opt), fake, None, None) == _capi.TC_ERR_ARG
     assert lib.tc_mlp_forward(fake, 32, 4, fake, 0, fake, None) == _capi.TC_OK   # zero rows: no-op
     assert lib.tc_mlp_forward(fake, 32, 4, fake, -1, fake, None) == _capi.TC_ERR_ARG
+
+
+@pytest.mark.parametrize("off,n", [([1, 5, 10], 10), ([0, 6, 5], 5), ([0, 5, 9], 10), ([0], 3)])
+def test_batch_offsets_rejected_before_device(lib, off, n):
+    fake = ctypes.c_void_p(0x1000)
+    o = (ctypes.c_int64 * len(off))(*off)
+    T = lib.tc_count_batched(len(off) - 1, o, n, 20, fake, fake, None, None, fake, None, fake, 1 << 30, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_ARG
+
+
+def test_batch_needs_counts_buffer(lib):
+    fake = ctypes.c_void_p(0x1000)
+    o = (ctypes.c_int64 * 3)(0, 4, 10)
+    T = lib.tc_count_batched(2, o, 10, 20, fake, fake, None, None, None, None, fake, 1 << 30, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_ARG
+    sz, sz1 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.tc_count_batched_ws(2, 10, 20, None, ctypes.byref(sz)) == _capi.TC_OK
+    assert lib.tc_count_ws(10, 20, None, ctypes.byref(sz1)) == _capi.TC_OK
+    assert sz.value > sz1.value
