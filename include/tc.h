@@ -100,10 +100,11 @@ enum tc_flags {
 typedef struct tc_options {
     int32_t schedule;         /* tc_schedule                                 */
     int32_t force_strategy;   /* tc_strategy; >= 0 forces it on every bucket.
-                                 A hash strategy whose table cannot hold a
-                                 bucket's owner lists is replaced: wavefront
-                                 by workgroup hash if that holds them, else
-                                 by TC_STRAT_BSEARCH                         */
+                                 A wavefront hash whose table cannot hold a
+                                 bucket's owner lists becomes the workgroup
+                                 hash, which cuts an owner list longer than
+                                 half its table into value-range slices
+                                 (one work item each)                        */
     int32_t flags;            /* tc_flags bits                               */
     int32_t wave_slots;       /* LDS hash slots per wavefront (power of 2,
                                  64..2048); 0 = default 2048                 */
@@ -310,10 +311,10 @@ int tc_mlp_train(float *d_params, float *d_m, float *d_v, int32_t hidden, int32_
                  size_t ws_bytes, void *stream);
 
 /* The learned schedule: for every bucket b, the strategy with the smallest
- * predicted cost among those feasible under opt (a wavefront or workgroup
- * hash is feasible when ob <= log2(slots) - 2, i.e. the owner list fills at
- * most half the table; binary search and merge always are).  Ties go to the
- * lower strategy number.  K must be TC_NUM_STRATEGIES.
+ * predicted cost among those feasible under opt (the wavefront hash is
+ * feasible when ob <= log2(wave_slots) - 2, i.e. the owner list fills at most
+ * half its table; the workgroup hash, binary search and merge always are).
+ * Ties go to the lower strategy number.  K must be TC_NUM_STRATEGIES.
  *   d_table  int32[TC_NUM_BUCKETS] device, output (for opt->sched_table)
  *   d_cost   float[TC_NUM_BUCKETS][K] device, predicted costs, NULL ok */
 int tc_mlp_schedule(const float *d_params, int32_t hidden, int32_t k, const tc_options *opt, int32_t *d_table,

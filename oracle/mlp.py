@@ -156,18 +156,17 @@ def bucket_features(b):
     return np.stack([(b >> 5) & 31, b & 31, b >> 10], axis=1).astype(np.float64)
 
 
-def schedule(params, wave_ob_max: int, wg_ob_max: int):
+def schedule(params, wave_ob_max: int):
     """Per bucket: predicted costs (float64), the cheapest feasible strategy
-    (ties to the lower number), and the gap to the runner-up (inf if it is
-    the only feasible one).  A wavefront / workgroup hash is feasible when
-    ob <= wave_ob_max / wg_ob_max; binary search and merge always are."""
+    (ties to the lower number), and the gap to the runner-up.  The wavefront
+    hash is feasible when ob <= wave_ob_max; the workgroup hash (which slices
+    long owner lists), binary search and merge always are."""
     b = np.arange(N_BUCKETS)
     X = bucket_features(b)
     y, _ = forward(params, X)
     ob = X[:, 0]
     feas = np.ones((N_BUCKETS, 4), dtype=bool)
     feas[:, STRAT_WAVE_HASH] = ob <= wave_ob_max
-    feas[:, STRAT_WG_HASH] = ob <= wg_ob_max
     yy = np.where(feas, y[:, :4], np.inf)
     table = np.argmin(yy, axis=1)          # argmin returns the first (lowest) index on ties
     srt = np.sort(yy, axis=1)

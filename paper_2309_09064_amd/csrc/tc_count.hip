@@ -38,7 +38,7 @@ constexpr int32_t kEmpty = -1;
 
 struct Item {
     int32_t owner;
-    int32_t code;   // kind | strategy << 1 | bucket << 3
+    int32_t code;   // kind | strategy << 1 | bucket << 3 | owner slice << 14
     int32_t jb, je; // range of c0 positions (owner's N0 row) holding partners
 };
 
@@ -69,24 +69,38 @@ struct SchedCfg {
     const int32_t *table;  // per-bucket strategy (nullable -> heuristic)
     int32_t force;         // >= 0: this strategy everywhere it is feasible
     int32_t wave_ob_max;   // largest owner-size class a wavefront table holds
-    int32_t wg_ob_max;     // largest owner-size class the workgroup table holds
+    int32_t wg_ob_max;     // largest owner-size class the workgroup table holds whole
+    int32_t wg_cap_log2;   // log2 of the owner elements one workgroup table holds
+    int32_t wg_slicing;    // longer owner lists are sliced (else they are searched)
     int32_t heur_wave_ob;  // heuristic: wavefront table up to this class
     int32_t chunk_work;    // probe elements per wavefront item
 };
 
 // Strategy of a bucket.  Feasibility depends only on the owner-size class
 // ob = floor(log2 |owner list|): a table of 2^k slots takes classes
-// ob <= k - 2, i.e. lists shorter than half the table.
+// ob <= k - 2, i.e. lists shorter than half the table.  The workgroup hash
+// takes any owner while slicing is on: a list longer than half its table is
+// cut into value-range slices that each fill at most half of it, one work
+// item per slice.
 __device__ __forceinline__ int strategy_for(const SchedCfg &c, int b) {
     const int ob = (b >> 5) & 31;
+    const bool wg_ok = ob <= c.wg_ob_max || c.wg_slicing;
     int s;
     if (c.force >= 0) s = c.force;
     else if (c.table) s = c.table[b];
-    else s = ob <= c.heur_wave_ob ? TC_STRAT_WAVE_HASH : (ob <= c.wg_ob_max ? TC_STRAT_WG_HASH : TC_STRAT_BSEARCH);
-    if (s == TC_STRAT_WAVE_HASH && ob > c.wave_ob_max) s = ob <= c.wg_ob_max ? TC_STRAT_WG_HASH : TC_STRAT_BSEARCH;
-    if (s == TC_STRAT_WG_HASH && ob > c.wg_ob_max) s = TC_STRAT_BSEARCH;
+    else s = ob <= c.heur_wave_ob ? TC_STRAT_WAVE_HASH : (wg_ok ? TC_STRAT_WG_HASH : TC_STRAT_BSEARCH);
+    if (s == TC_STRAT_WAVE_HASH && ob > c.wave_ob_max) s = wg_ok ? TC_STRAT_WG_HASH : TC_STRAT_BSEARCH;
+    if (s == TC_STRAT_WG_HASH && !wg_ok) s = TC_STRAT_BSEARCH;
     if (s < 0 || s >= TC_NUM_STRATEGIES) s = TC_STRAT_BSEARCH;
     return s;
+}
+
+constexpr int kSliceShift = 14;          // slice index in the item code's top 18 bits
+constexpr int kMaxSlicesLog2 = 32 - kSliceShift;
+
+// Slices of an owner list of sx elements under the workgroup hash.
+__device__ __forceinline__ int32_t owner_slices(int32_t sx, int cap_log2) {
+    return (int32_t)(((int64_t)sx + (1 << cap_log2) - 1) >> cap_log2);
 }
 
 // ---------------------------------------------------------------- ownership
@@ -195,13 +209,14 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
     const int64_t total = 2 * (int64_t)n;
     const int64_t u0 = ((int64_t)blockIdx.x * kItemThreads + threadIdx.x) * kUnitsPerThread;
     int bk[kUnitsPerThread], loc[kUnitsPerThread], st[kUnitsPerThread];
-    int32_t nchs[kUnitsPerThread];
+    int32_t nchs[kUnitsPerThread], nsls[kUnitsPerThread];
     unsigned long long units = 0, probes = 0, hashed = 0, ps0 = 0, ps1 = 0, ps2 = 0, ps3 = 0;
 #pragma unroll
     for (int k = 0; k < kUnitsPerThread; ++k) {
         const int64_t u = u0 + k;
         bk[k] = -1;
         nchs[k] = 0;
+        nsls[k] = 1;
         loc[k] = 0;
         st[k] = 0;
         const int32_t c = u < total ? cnt[u] : 0;
@@ -215,18 +230,23 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
         const int64_t target = (int64_t)sc.chunk_work * (s == TC_STRAT_WG_HASH ? kWgItemWaves : 1);
         const int32_t jb = rp0[x], je = rp0[x + 1];
         const int32_t minp = s == TC_STRAT_WG_HASH ? kMinPartnersPerWgItem : kMinPartnersPerItem;
-        int64_t nch = ((int64_t)w + target - 1) / target;
-        const int64_t cap = (je - jb + minp - 1) / minp;
+        // a sliced owner: each slice streams about w / nsl elements; the
+        // items of a unit stay at most slices + partner chunks in number
+        const int32_t nsl = s == TC_STRAT_WG_HASH ? owner_slices(sx, sc.wg_cap_log2) : 1;
+        int64_t nch = ((int64_t)w / nsl + target - 1) / target;
+        int64_t cap = (je - jb + minp - 1) / minp;
+        if (nsl > 1) cap = (cap + nsl - 1) / nsl;
         if (nch > cap) nch = cap;
         if (nch < 1) nch = 1;
         bk[k] = b;
         st[k] = s;
         nchs[k] = (int32_t)nch;
-        loc[k] = atomicAdd(&hist[b], (int32_t)nch);
+        nsls[k] = nsl;
+        loc[k] = atomicAdd(&hist[b], (int32_t)nch * nsl);
         if (!kFill && prof)   // profile: the bucket's elements (partners streamed + owner list)
             atomicAdd(&prof[(b * TC_NUM_STRATEGIES + s) * 3 + 1], w + (unsigned long long)sx);
         if (!kFill) {
-            const unsigned long long nc = (unsigned long long)nch;
+            const unsigned long long nc = (unsigned long long)nch * (unsigned long long)nsl;
             ++units;
             probes += w;
             hashed += (unsigned long long)sx * nc;
@@ -265,14 +285,15 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
         const int64_t len = je - jb;
         const int32_t pos = bbase[bk[k]] + loc[k];
         const int32_t code = (int32_t)(u & 1) | (st[k] << 1) | (bk[k] << 3);
-        for (int32_t c = 0; c < nchs[k]; ++c) {
-            Item it;
-            it.owner = x;
-            it.code = code;
-            it.jb = jb + (int32_t)(len * c / nchs[k]);
-            it.je = jb + (int32_t)(len * (c + 1) / nchs[k]);
-            items[pos + c] = it;
-        }
+        for (int32_t si = 0; si < nsls[k]; ++si)
+            for (int32_t c = 0; c < nchs[k]; ++c) {
+                Item it;
+                it.owner = x;
+                it.code = (int32_t)((uint32_t)code | ((uint32_t)si << kSliceShift));
+                it.jb = jb + (int32_t)(len * c / nchs[k]);
+                it.je = jb + (int32_t)(len * (c + 1) / nchs[k]);
+                items[pos + si * nchs[k] + c] = it;
+            }
     }
 }
 
@@ -501,13 +522,24 @@ __device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t x, 
 // step (kPer loads in flight per lane); the list an element belongs to is
 // found from a ballot of the marked list starts in the window and a
 // popcount, O(1) per element.
+// With `sliced`, only the part of each partner list with values in
+// [lo, hi) is streamed (two binary searches per partner).
 template <class Count>
 __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p0,
-                                                 int32_t je, int32_t *scr, Count count) {
+                                                 int32_t je, int32_t *scr, Count count, bool sliced = false,
+                                                 int32_t lo = 0, int32_t hi = 0) {
     static_assert(kPer == 8, "a lane reads its window markers as one 64-bit word");
     const int l = lane_id();
     int32_t sy, yb;
-    const bool mine = partner_at(g, kind, x, sx, p0 + l, je, sy, yb);
+    bool mine = partner_at(g, kind, x, sx, p0 + l, je, sy, yb);
+    const int32_t *lists = kind == 0 ? g.c0 : g.c1;
+    if (sliced && mine) {
+        const int32_t b = lower_idx(lists + yb, sy, lo);
+        const int32_t e = lower_idx(lists + yb, sy, hi);
+        yb += b;
+        sy = e - b;
+        mine = sy > 0;   // two lists may not start at one window offset
+    }
     const uint64_t m = __ballot(mine);
     if (m == 0) return 0u;
     uint8_t *marker = reinterpret_cast<uint8_t *>(scr);
@@ -517,7 +549,6 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     const int32_t start = incl - len;
     const int32_t total = __shfl(incl, kWave - 1, kWave);
     if (mine) pinfo[__popcll(m & ((1ull << l) - 1))] = make_int2(start, yb);
-    const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     const uint64_t le = (l == kWave - 1) ? ~0ull : ((2ull << l) - 1);
     uint32_t hits = 0;
     int32_t before = 0;   // lists that start before the current window
@@ -609,12 +640,19 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const int32_t x = item.owner;
         const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
         const int32_t sx = list_size(kind, g.up0, g.rp1, x);
-        const int lg = table_log2(sx, wg_log2);
+        // the owner slice of this item: positions [a_lo, a_hi), values [lo, hi)
+        const int32_t nsl = owner_slices(sx, wg_log2 - 1);
+        const int32_t si = (int32_t)((uint32_t)item.code >> kSliceShift);
+        const int32_t a_lo = (int32_t)((int64_t)sx * si / nsl), a_hi = (int32_t)((int64_t)sx * (si + 1) / nsl);
+        const bool sliced = nsl > 1;
+        const int32_t lo = sliced ? a[a_lo] : 0;
+        const int32_t hi = sliced && a_hi < sx ? a[a_hi] : INT32_MAX;
+        const int lg = table_log2(a_hi - a_lo, wg_log2);
         const HashTab ht = make_tab(lds, lg);
         if (threadIdx.x == 0) s_chunk = 0;
         for (int i = threadIdx.x; i < (1 << lg); i += kIsectThreads) lds[i] = kEmpty;
         __syncthreads();
-        for (int i = threadIdx.x; i < sx; i += kIsectThreads) hash_insert(ht, a[i]);
+        for (int i = a_lo + (int)threadIdx.x; i < a_hi; i += kIsectThreads) hash_insert(ht, a[i]);
         __syncthreads();
         uint32_t h = 0;
         for (;;) {
@@ -625,7 +663,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             h += stream_chunk(g, kind, x, sx, p0, item.je, scr,
                               [&](const int32_t(&v)[kPer]) {
                                   return in_fours(v, [&](const int32_t(&q)[4]) { return hash_count<4>(ht, q); });
-                              });
+                              }, sliced, lo, hi);
         }
         if (kind == 0) acc0 += h; else acc1 += h;
         if (kBatch) {
@@ -634,7 +672,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         }
         __syncthreads();   // the table, s_item and s_chunk are reused by the next item
         if (kProf && threadIdx.x == 0) {
-            unsigned long long *pr = prof + ((item.code >> 3) * TC_NUM_STRATEGIES + TC_STRAT_WG_HASH) * 3;
+            unsigned long long *pr = prof + (((item.code >> 3) & (kBuckets - 1)) * TC_NUM_STRATEGIES + TC_STRAT_WG_HASH) * 3;
             atomicAdd(&pr[0], (unsigned long long)(wall_clock64() - t_beg) * kIsectWaves);
             atomicAdd(&pr[2], 1ull);
         }
@@ -682,7 +720,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             if (l == 0 && hs) atomicAdd(&bt.counts[bt.gid[x]], hs);
         }
         if (kProf && l == 0) {
-            unsigned long long *pr = prof + ((item.code >> 3) * TC_NUM_STRATEGIES + strat) * 3;
+            unsigned long long *pr = prof + (((item.code >> 3) & (kBuckets - 1)) * TC_NUM_STRATEGIES + strat) * 3;
             atomicAdd(&pr[0], (unsigned long long)(wall_clock64() - t_beg));
             atomicAdd(&pr[2], 1ull);
         }
@@ -758,6 +796,11 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     sc.force = cfg.force;
     sc.wave_ob_max = wave_log2 - 2;
     sc.wg_ob_max = wg_log2 - 2;
+    sc.wg_cap_log2 = wg_log2 - 1;
+    {   // slicing needs at most 2^18 slices per owner list (list length <= min(n - 1, nnz))
+        const int64_t longest = (int64_t)n - 1 < nnz ? (int64_t)n - 1 : nnz;
+        sc.wg_slicing = longest <= ((int64_t)1 << (kMaxSlicesLog2 + sc.wg_cap_log2)) ? 1 : 0;
+    }
     sc.heur_wave_ob = cfg.wave_max_owner > 0 ? ilog2_host(cfg.wave_max_owner) : wave_log2 - 2;
     sc.chunk_work = cfg.chunk_work;
 

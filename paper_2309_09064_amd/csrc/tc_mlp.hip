@@ -247,8 +247,7 @@ __global__ void k_mlp_adam(float *__restrict__ params, const float *__restrict__
 
 template <int H>
 __global__ __launch_bounds__(kRowThreads) void k_mlp_schedule(const float *__restrict__ params, Net n,
-                                                                int wave_ob_max, int wg_ob_max,
-                                                                int32_t *__restrict__ table,
+                                                                int wave_ob_max, int32_t *__restrict__ table,
                                                                 float *__restrict__ cost) {
     extern __shared__ float sp[];
     load_params(sp, params, n.P);
@@ -262,8 +261,7 @@ __global__ __launch_bounds__(kRowThreads) void k_mlp_schedule(const float *__res
     float best_y = y[TC_STRAT_BSEARCH];
 #pragma unroll
     for (int k = 0; k < TC_NUM_STRATEGIES; ++k) {
-        const bool feasible = k == TC_STRAT_WAVE_HASH ? ob <= wave_ob_max
-                              : k == TC_STRAT_WG_HASH ? ob <= wg_ob_max : true;
+        const bool feasible = k == TC_STRAT_WAVE_HASH ? ob <= wave_ob_max : true;
         if (feasible && (y[k] < best_y || (y[k] == best_y && k < best))) {
             best = k;
             best_y = y[k];
@@ -318,11 +316,10 @@ struct LaunchRows {
 
 template <int H>
 struct LaunchSchedule {
-    static int run(const float *params, Net n, int wave_ob_max, int wg_ob_max, int32_t *table, float *cost,
-                   hipStream_t s) {
+    static int run(const float *params, Net n, int wave_ob_max, int32_t *table, float *cost, hipStream_t s) {
         const unsigned g = (unsigned)((TC_NUM_BUCKETS + kRowThreads - 1) / kRowThreads);
         hipLaunchKernelGGL(k_mlp_schedule<H>, dim3(g), dim3(kRowThreads), n.P * sizeof(float), s, params, n,
-                           wave_ob_max, wg_ob_max, table, cost);
+                           wave_ob_max, table, cost);
         TC_HIP_TRY(hipGetLastError());
         return TC_OK;
     }
@@ -479,8 +476,8 @@ int tc_mlp_schedule(const float *d_params, int32_t hidden, int32_t k, const tc_o
     DeviceInfo di;
     rc = device_info(&di);
     if (rc != TC_OK) return ret(rc);
-    const int wave_ob_max = ilog2i(cfg.wave_slots) - 2, wg_ob_max = ilog2i(cfg.wg_slots) - 2;
-    return ret(by_hidden<LaunchSchedule>(hidden, d_params, net_of(hidden, k), wave_ob_max, wg_ob_max, d_table, d_cost,
+    const int wave_ob_max = ilog2i(cfg.wave_slots) - 2;
+    return ret(by_hidden<LaunchSchedule>(hidden, d_params, net_of(hidden, k), wave_ob_max, d_table, d_cost,
                                          static_cast<hipStream_t>(stream)));
 }
 

@@ -193,6 +193,20 @@ def test_count_tiles_and_grids(tc, name, cfg):
     check_count(tc, graph(name), tc.Options(**cfg))
 
 
+@pytest.mark.parametrize("cfg", [dict(wave_slots=64, wg_slots=1024, force_strategy=1),
+                                 dict(wave_slots=64, wg_slots=2048), dict(wave_slots=128, wg_slots=1024, chunk_work=256)])
+def test_count_sliced_owner_lists(tc, cfg):
+    # owner lists longer than half the workgroup table are hashed slice by
+    # slice: with every edge horizontal (levels 0) the N0+ lists of a dense
+    # graph reach several slices
+    for g in (complete(700), gnp(900, 0.5, 7), graph("kron14")):
+        res = check_count(tc, g, tc.Options(**cfg), levels=np.zeros(g.n, np.int32))
+        assert res.T1 == 0
+        check_count(tc, g, tc.Options(**cfg))
+    rp, col = to_gpu(complete(700))
+    assert tc.count(rp, col, dev(np.zeros(700, np.int32)), tc.Options(**cfg)).T == 700 * 699 * 698 // 6
+
+
 def test_count_closed_forms(tc):
     from _graphs import book, complete_tripartite, choose
     for n in (3, 5, 9, 20):

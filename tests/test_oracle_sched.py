@@ -55,26 +55,27 @@ def _const_net(costs, H=8):
     return ps
 
 
-def _expect(pref, wave_ob_max, wg_ob_max):
+def _expect(pref, wave_ob_max):
     """Cheapest feasible by a preference order, per bucket."""
     out = np.zeros(2048, np.int32)
     for b in range(2048):
         ob = (b >> 5) & 31
-        feas = {0: ob <= wave_ob_max, 1: ob <= wg_ob_max, 2: True, 3: True}
+        feas = {0: ob <= wave_ob_max, 1: True, 2: True, 3: True}
         out[b] = next(s for s in pref if feas[s])
     return out
 
 
-@pytest.mark.parametrize("wave,wg", [(9, 13), (4, 8), (0, 8)])
-def test_schedule_constant_costs(wave, wg):
-    t, y, gap, feas = mlp.schedule(_const_net([0.0, 1.0, 2.0, 3.0]), wave, wg)
-    assert np.array_equal(t, _expect([0, 1, 2, 3], wave, wg))
-    t, *_ = mlp.schedule(_const_net([3.0, 2.0, 1.0, 0.0]), wave, wg)
+@pytest.mark.parametrize("wave", [9, 4, 0])
+def test_schedule_constant_costs(wave):
+    t, y, gap, feas = mlp.schedule(_const_net([0.0, 1.0, 2.0, 3.0]), wave)
+    assert np.array_equal(t, _expect([0, 1, 2, 3], wave))
+    assert np.array_equal(np.nonzero(t == 0)[0], np.nonzero(((np.arange(2048) >> 5) & 31) <= wave)[0])
+    t, *_ = mlp.schedule(_const_net([3.0, 2.0, 1.0, 0.0]), wave)
     assert np.all(t == 3)
-    t, *_ = mlp.schedule(_const_net([1.0, 1.0, 1.0, 1.0]), wave, wg)   # ties: lowest number
-    assert np.array_equal(t, _expect([0, 1, 2, 3], wave, wg))
-    t, *_ = mlp.schedule(_const_net([5.0, 0.5, 1.0, 2.0]), wave, wg)
-    assert np.array_equal(t, _expect([1, 2, 3, 0], wave, wg))
+    t, *_ = mlp.schedule(_const_net([1.0, 1.0, 1.0, 1.0]), wave)   # ties: lowest number
+    assert np.array_equal(t, _expect([0, 1, 2, 3], wave))
+    t, *_ = mlp.schedule(_const_net([0.5, 5.0, 1.0, 2.0]), wave)
+    assert np.array_equal(t, _expect([0, 2, 3, 1], wave))
 
 
 def test_schedule_cost_growing_with_owner_class():
@@ -86,7 +87,7 @@ def test_schedule_cost_growing_with_owner_class():
     ps[2][0, 0] = 1.0
     ps[4][0, 0] = 1.0
     ps[5][:] = [0.0, 100.0, 5.0, 100.0]
-    t, y, gap, _ = mlp.schedule(ps, 31, 31)
+    t, y, gap, _ = mlp.schedule(ps, 31)
     ob = (np.arange(2048) >> 5) & 31
     assert np.allclose(y[:, 0], ob)
     assert np.array_equal(t, np.where(ob <= 5, 0, 2))
