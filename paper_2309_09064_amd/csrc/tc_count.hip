@@ -367,39 +367,47 @@ __device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
     }
 }
 
-// Membership of up to kPer keys (negative = absent slot), the lookups of all
-// keys interleaved so their LDS reads overlap.
+// Membership of up to kPer keys (negative = absent slot).  Every key's home
+// bucket is read once, unconditionally and interleaved; a key whose home
+// bucket is full and holds no match (rare at the tables' load) then follows
+// its probe chain, one pending key at a time per lane.  Keeping the common
+// case free of per-key predication is what bounds the instruction count:
+// the slowest of a wavefront's keys no longer sets the work of all of them.
 template <int kPer>
 __device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (&v)[kPer]) {
     uint32_t b[kPer];
-    bool live[kPer];
-    bool any = false;
+    int4 q[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) b[u] = home_bucket(t, v[u]);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) q[u] = *reinterpret_cast<const int4 *>(&t.tab[4 * b[u]]);
+    uint32_t hits = 0, pend = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-        live[u] = v[u] >= 0;
-        b[u] = home_bucket(t, v[u]);
-        any |= live[u];
+        const int32_t x = v[u];
+        const bool m = (q[u].x == x) | (q[u].y == x) | (q[u].z == x) | (q[u].w == x);
+        const bool live = x >= 0;
+        hits += (live & m) ? 1u : 0u;
+        pend |= (live & !m & (q[u].w != kEmpty)) ? (1u << u) : 0u;
     }
-    uint32_t hits = 0;
-    while (any) {
-        int4 q[kPer];
+    while (pend) {
+        const int u = __builtin_ctz(pend);
+        pend &= pend - 1;
+        int32_t x = v[0];
+        uint32_t bb = b[0];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u)
-            if (live[u]) q[u] = *reinterpret_cast<const int4 *>(&t.tab[4 * b[u]]);
-        any = false;
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            if (!live[u]) continue;
-            const int32_t x = v[u];
-            if (q[u].x == x || q[u].y == x || q[u].z == x || q[u].w == x) {
+        for (int j = 1; j < kPer; ++j) {
+            x = u == j ? v[j] : x;
+            bb = u == j ? b[j] : bb;
+        }
+        for (;;) {
+            bb = (bb + 1) & t.bmask;
+            const int4 r = *reinterpret_cast<const int4 *>(&t.tab[4 * bb]);
+            if (r.x == x || r.y == x || r.z == x || r.w == x) {
                 ++hits;
-                live[u] = false;
-            } else if (q[u].w == kEmpty) {
-                live[u] = false;
-            } else {
-                b[u] = (b[u] + 1) & t.bmask;
-                any = true;
+                break;
             }
+            if (r.w == kEmpty) break;
         }
     }
     return hits;
@@ -596,9 +604,12 @@ __device__ __forceinline__ uint32_t merge_chunk(const Graph &g, int kind, int32_
     return hits;
 }
 
+// Table size for sx keys: load at most 1/8 where the space allows (probe
+// chains then almost never leave the home bucket), never above max_log2;
+// feasibility guarantees load at most 1/2 at the cap.
 __device__ __forceinline__ int table_log2(int32_t sx, int max_log2) {
     int lg = 6;   // at least 64 slots
-    while (lg < max_log2 && (1 << lg) < 2 * sx) ++lg;
+    while (lg < max_log2 && (1 << lg) < 8 * sx) ++lg;
     return lg;
 }
 
@@ -650,7 +661,8 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const int lg = table_log2(a_hi - a_lo, wg_log2);
         const HashTab ht = make_tab(lds, lg);
         if (threadIdx.x == 0) s_chunk = 0;
-        for (int i = threadIdx.x; i < (1 << lg); i += kIsectThreads) lds[i] = kEmpty;
+        for (int i = threadIdx.x; i < (1 << lg) / 4; i += kIsectThreads)
+            reinterpret_cast<int4 *>(lds)[i] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
         __syncthreads();
         for (int i = a_lo + (int)threadIdx.x; i < a_hi; i += kIsectThreads) hash_insert(ht, a[i]);
         __syncthreads();
@@ -695,7 +707,8 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         if (strat == TC_STRAT_WAVE_HASH) {
             const int lg = table_log2(sx, wave_log2);
             const HashTab ht = make_tab(tab, lg);
-            for (int i = l; i < (1 << lg); i += kWave) tab[i] = kEmpty;
+            for (int i = l; i < (1 << lg) / 4; i += kWave)
+                reinterpret_cast<int4 *>(tab)[i] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
             wave_lds_sync();
             for (int i = l; i < sx; i += kWave) hash_insert(ht, a[i]);
             wave_lds_sync();
