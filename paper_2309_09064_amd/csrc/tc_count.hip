@@ -558,31 +558,49 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     const int32_t total = __shfl(incl, kWave - 1, kWave);
     if (mine) pinfo[__popcll(m & ((1ull << l) - 1))] = make_int2(start, yb);
     const uint64_t le = (l == kWave - 1) ? ~0ull : ((2ull << l) - 1);
-    uint32_t hits = 0;
     int32_t before = 0;   // lists that start before the current window
-    for (int32_t base = 0; base < total; base += kPer * kWave) {
+    constexpr int32_t kStep = kPer * kWave;
+    // loads of the window at `base`: lane l takes elements base + 64u + l;
+    // slots past the end read element 0 of the list array and are masked
+    // when consumed, so the loads need no branch and stay in flight
+    auto gather = [&](int32_t base, int32_t (&v)[kPer]) {
         const int32_t o = start - base;
-        const bool mark = mine && o >= 0 && o < kPer * kWave;
+        const bool mark = mine && o >= 0 && o < kStep;
         const int mslot = (o & 63) * kPer + (o >> 6);
         if (mark) marker[mslot] = 1;
         wave_lds_sync();
         const uint64_t mk = *reinterpret_cast<const uint64_t *>(marker + l * kPer);
         wave_lds_sync();
         if (mark) marker[mslot] = 0;
-        int32_t v[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const uint64_t mw = __ballot((mk >> (8 * u)) & 0xffu);
             const int32_t k = before + __popcll(mw & le) - 1;
             before += __popcll(mw);
             const int32_t f = base + u * kWave + l;
-            v[u] = -1;
-            if (f < total) {
-                const int2 pi = pinfo[k];
-                v[u] = lists[pi.y + f - pi.x];
-            }
+            const bool in = f < total;
+            const int2 pi = pinfo[in ? k : 0];
+            v[u] = lists[in ? pi.y + f - pi.x : 0];
         }
-        hits += count(v);
+    };
+    auto masked = [&](int32_t base, int32_t (&v)[kPer]) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) v[u] = base + u * kWave + l < total ? v[u] : -1;
+    };
+    // software pipeline: the next window's loads are issued before this
+    // window's lookups, so their latency overlaps the LDS probes
+    uint32_t hits = 0;
+    int32_t va[kPer];
+    gather(0, va);
+    for (int32_t base = 0;; base += kStep) {
+        int32_t vb[kPer];
+        const bool more = base + kStep < total;
+        if (more) gather(base + kStep, vb);
+        masked(base, va);
+        hits += count(va);
+        if (!more) break;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) va[u] = vb[u];
     }
     wave_lds_sync();   // pinfo is rewritten by the next batch
     return hits;
