@@ -357,6 +357,16 @@ __device__ __forceinline__ uint32_t home_bucket(const HashTab &t, int32_t v) {
     return ((uint32_t)v * 0x9E3779B1u) >> t.shift;
 }
 
+// Whether bucket q holds x: the smallest of the four xors is zero exactly
+// when a slot equals x (xor + min instead of four compares whose boolean
+// reduction the compiler expands into mask arithmetic).
+__device__ __forceinline__ bool bucket_has(const int4 &q, int32_t x) {
+    const uint32_t ux = (uint32_t)x;
+    const uint32_t a = min((uint32_t)q.x ^ ux, (uint32_t)q.y ^ ux);
+    const uint32_t b = min((uint32_t)q.z ^ ux, (uint32_t)q.w ^ ux);
+    return min(a, b) == 0u;
+}
+
 __device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
     uint32_t b = home_bucket(t, v);
     for (;;) {
@@ -385,7 +395,7 @@ __device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int32_t x = v[u];
-        const bool m = (q[u].x == x) | (q[u].y == x) | (q[u].z == x) | (q[u].w == x);
+        const bool m = bucket_has(q[u], x);
         const bool live = x >= 0;
         hits += (live & m) ? 1u : 0u;
         pend |= (live & !m & (q[u].w != kEmpty)) ? (1u << u) : 0u;
@@ -403,7 +413,7 @@ __device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (
         for (;;) {
             bb = (bb + 1) & t.bmask;
             const int4 r = *reinterpret_cast<const int4 *>(&t.tab[4 * bb]);
-            if (r.x == x || r.y == x || r.z == x || r.w == x) {
+            if (bucket_has(r, x)) {
                 ++hits;
                 break;
             }
