@@ -582,15 +582,23 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
         const uint64_t mk = *reinterpret_cast<const uint64_t *>(marker + l * kPer);
         wave_lds_sync();
         if (mark) marker[mslot] = 0;
+        // a slot past the end belongs to the last list (no list starts
+        // after it), so clamping its position to total - 1 keeps every
+        // address valid without a branch; such slots are masked later
+        int32_t k[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const uint64_t mw = __ballot((mk >> (8 * u)) & 0xffu);
-            const int32_t k = before + __popcll(mw & le) - 1;
+            k[u] = max(before + __popcll(mw & le) - 1, 0);
             before += __popcll(mw);
-            const int32_t f = base + u * kWave + l;
-            const bool in = f < total;
-            const int2 pi = pinfo[in ? k : 0];
-            v[u] = lists[in ? pi.y + f - pi.x : 0];
+        }
+        int2 pi[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) pi[u] = pinfo[k[u]];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int32_t f = min(base + u * kWave + l, total - 1);
+            v[u] = lists[pi[u].y + f - pi[u].x];
         }
     };
     auto masked = [&](int32_t base, int32_t (&v)[kPer]) {
