@@ -70,7 +70,9 @@ enum tc_strategy {
     TC_STRAT_WAVE_HASH = 0,   /* owner list in a wavefront-private LDS hash   */
     TC_STRAT_WG_HASH = 1,     /* owner list in a workgroup-shared LDS hash    */
     TC_STRAT_BSEARCH = 2,     /* binary search in the owner's global list     */
-    TC_STRAT_MERGE = 3,       /* two-pointer merge of the two sorted lists    */
+    TC_STRAT_MERGE = 3,       /* two-pointer merge of the two sorted lists:
+                                 one lane per item for owner lists below
+                                 32, else the wavefront per partner          */
     TC_NUM_STRATEGIES = 4
 };
 
@@ -116,6 +118,10 @@ typedef struct tc_options {
                                  blocks as fit in LDS, at most 2 per CU      */
     int32_t wave_max_owner;   /* heuristic: largest owner list for the
                                  wavefront hash; 0 = wave_slots / 2          */
+    int32_t merge_max_owner;  /* heuristic: owner lists up to this size (at
+                                 most 31) take the lane merge (one lane per
+                                 item of at most 32 partners); 0 = default
+                                 7, -1 = never                               */
     const int32_t *sched_table; /* device int32[TC_NUM_BUCKETS] strategies,
                                  read when schedule == TC_SCHED_TABLE (NULL
                                  otherwise).  A hash strategy in a bucket
@@ -229,6 +235,13 @@ uint64_t tc_count_batched(int32_t graphs, const int64_t *h_vtx_off, int32_t n, i
                           const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
                           const tc_options *opt, uint64_t *d_counts, tc_stats *stats, void *ws, size_t ws_bytes,
                           void *stream);
+
+/*
+ * The strategy every bucket gets from tc_count under opt for a graph of n
+ * vertices and nnz CSR entries: force_strategy, the table or the heuristic,
+ * after the feasibility rules.  d_table: device int32[TC_NUM_BUCKETS].
+ */
+int tc_schedule_table(int32_t n, int64_t nnz, const tc_options *opt, int32_t *d_table, void *stream);
 
 /*
  * tc_count plus a per-bucket cost profile, the training data of the learned

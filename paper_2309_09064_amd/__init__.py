@@ -18,7 +18,7 @@ from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_BUCKETS, TC_NUM_STRAT
                     TC_STRAT_WG_HASH, TC_TIMING, TC_VALIDATE)
 
 __all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count", "count_profile", "workspace",
-           "count_batched", "pack_csr",
+           "count_batched", "pack_csr", "schedule_table",
            "Counter", "CountResult", "new_profile",
            "STRATEGY_NAMES", "TC_STRAT_AUTO", "TC_STRAT_WAVE_HASH", "TC_STRAT_WG_HASH", "TC_STRAT_BSEARCH",
            "TC_STRAT_MERGE", "TC_SCHED_HEURISTIC", "TC_SCHED_TABLE", "TC_NUM_BUCKETS", "TC_NUM_STRATEGIES",
@@ -70,6 +70,7 @@ class Options:
     chunk_work: int = 0
     grid_blocks: int = 0
     wave_max_owner: int = 0
+    merge_max_owner: int = 0            # 0 = default (7), -1 = never
     sched_table: torch.Tensor | None = None   # int32[TC_NUM_BUCKETS] on the device: selects TC_SCHED_TABLE
 
     def to_c(self):
@@ -89,6 +90,7 @@ class Options:
         o.chunk_work = self.chunk_work
         o.grid_blocks = self.grid_blocks
         o.wave_max_owner = self.wave_max_owner
+        o.merge_max_owner = self.merge_max_owner
         return o
 
 
@@ -204,6 +206,16 @@ class Counter:
             probes=int(st.probes), hashed=int(st.hashed), levels=int(st.levels), bfs_rounds=int(st.bfs_rounds),
             ms={"bfs": st.ms_bfs, "partition": st.ms_partition, "bucket": st.ms_bucket, "isect": st.ms_isect},
             strategy_items={STRATEGY_NAMES[k]: int(st.strategy_items[k]) for k in range(TC_NUM_STRATEGIES)})
+
+
+def schedule_table(n: int, nnz: int, options: Options | None = None, device=None, stream=None) -> torch.Tensor:
+    """The strategy tc_count gives every bucket under ``options`` for a graph
+    of n vertices and nnz entries (int32 device tensor of TC_NUM_BUCKETS)."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    opt = (options or Options()).to_c()
+    t = torch.empty(TC_NUM_BUCKETS, dtype=torch.int32, device=dev)
+    _check(_capi.load().tc_schedule_table(n, nnz, ctypes.byref(opt), _ptr(t), _stream(stream)), "tc_schedule_table")
+    return t
 
 
 PROFILE_LEN = TC_NUM_BUCKETS * TC_NUM_STRATEGIES * 3

@@ -49,6 +49,7 @@ class tc_options(ctypes.Structure):
         ("chunk_work", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
         ("wave_max_owner", ctypes.c_int32),
+        ("merge_max_owner", ctypes.c_int32),
         ("sched_table", ctypes.c_void_p),
     ]
 
@@ -97,6 +98,7 @@ _SIGNATURES = {
     "tc_count_batched_ws": (ctypes.c_int, [_i32, _i32, _i64, _P(tc_options), _P(_sz)]),
     "tc_count_batched": (ctypes.c_uint64, [_i32, _vp, _i32, _i64, _vp, _vp, _vp, _P(tc_options), _vp, _P(tc_stats),
                                            _vp, _sz, _vp]),
+    "tc_schedule_table": (ctypes.c_int, [_i32, _i64, _P(tc_options), _vp, _vp]),
     "tc_mlp_param_count": (ctypes.c_int, [_i32, _i32, _P(_i64)]),
     "tc_mlp_init": (ctypes.c_int, [_vp, _i32, _i32, _u64, _vp]),
     "tc_mlp_forward": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp]),

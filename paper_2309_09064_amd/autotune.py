@@ -143,8 +143,8 @@ def tune(row_ptr, col, levels=None, space: dict = SPACE, repeats: int = 3, base:
             return float(np.median(ms[1:]))
 
     start = {"chunk_work": 16384, "wave_slots": 2048, "wg_slots": 32768, "grid_blocks": 0}
-    default_ms = float(timer(dict(start)))
     best, best_ms, evals = coordinate_descent(timer, start, space)
+    default_ms = next(c for p, c in evals if p == start)   # the search's own timing of the defaults
     report = {"signature": graph_signature(row_ptr, col), "default_ms": default_ms, "best_ms": best_ms,
               "best": best, "evaluations": len(evals)}
     if cache is not None:

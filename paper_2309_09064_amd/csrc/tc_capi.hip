@@ -151,6 +151,8 @@ int make_cfg(const tc_options *opt, CountCfg *cfg, int *flags) {
         if (opt->chunk_work) c.chunk_work = opt->chunk_work;
         c.grid_blocks = opt->grid_blocks;
         c.wave_max_owner = opt->wave_max_owner;
+        if (opt->merge_max_owner < -1 || opt->merge_max_owner > 31) return TC_ERR_ARG;
+        c.merge_max_owner = opt->merge_max_owner;
         if (opt->flags & ~(TC_VALIDATE | TC_TIMING)) return TC_ERR_ARG;
         *flags = opt->flags;
     }
@@ -567,6 +569,21 @@ uint64_t tc_count_batched(int32_t graphs, const int64_t *h_vtx_off, int32_t n, i
                           uint64_t *d_counts, tc_stats *stats, void *ws, size_t ws_bytes, void *stream) {
     const BatchArgs b{graphs, h_vtx_off, d_counts};
     return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, &b);
+}
+
+int tc_schedule_table(int32_t n, int64_t nnz, const tc_options *opt, int32_t *d_table, void *stream) {
+    int rc = check_graph_args(n, nnz, (const void *)1, (const void *)1);
+    if (rc != TC_OK) return fail(rc);
+    if (!d_table) return fail(TC_ERR_ARG);
+    CountCfg cfg;
+    int flags;
+    rc = make_cfg(opt, &cfg, &flags);
+    if (rc != TC_OK) return fail(rc);
+    if (cfg.schedule == TC_SCHED_TABLE && !cfg.table) return fail(TC_ERR_ARG);
+    DeviceInfo di;
+    rc = device_info(&di);
+    if (rc != TC_OK) return fail(rc);
+    return fail(schedule_table_run(n, nnz, cfg, d_table, static_cast<hipStream_t>(stream)));
 }
 
 uint64_t tc_count_profile(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,

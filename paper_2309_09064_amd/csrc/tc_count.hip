@@ -35,6 +35,8 @@ constexpr int kMinPartnersPerItem = 8;     // wavefront items
 constexpr int kMinPartnersPerWgItem = 4096; // workgroup items
 constexpr int kWgItemWaves = 4 * kIsectWaves; // a workgroup item holds this many wavefront items of work
 constexpr int32_t kEmpty = -1;
+constexpr int kLaneMergeOb = 4;            // merge items with owner lists below 32: one lane each
+constexpr int kLanePartners = 32;          // row positions per lane item
 
 struct Item {
     int32_t owner;
@@ -73,6 +75,7 @@ struct SchedCfg {
     int32_t wg_cap_log2;   // log2 of the owner elements one workgroup table holds
     int32_t wg_slicing;    // longer owner lists are sliced (else they are searched)
     int32_t heur_wave_ob;  // heuristic: wavefront table up to this class
+    int32_t heur_merge_ob; // heuristic: lane merge up to this class (-1: never)
     int32_t chunk_work;    // probe elements per wavefront item
 };
 
@@ -88,6 +91,7 @@ __device__ __forceinline__ int strategy_for(const SchedCfg &c, int b) {
     int s;
     if (c.force >= 0) s = c.force;
     else if (c.table) s = c.table[b];
+    else if (ob <= c.heur_merge_ob) s = TC_STRAT_MERGE;
     else s = ob <= c.heur_wave_ob ? TC_STRAT_WAVE_HASH : (wg_ok ? TC_STRAT_WG_HASH : TC_STRAT_BSEARCH);
     if (s == TC_STRAT_WAVE_HASH && ob > c.wave_ob_max) s = wg_ok ? TC_STRAT_WG_HASH : TC_STRAT_BSEARCH;
     if (s == TC_STRAT_WG_HASH && !wg_ok) s = TC_STRAT_BSEARCH;
@@ -237,6 +241,8 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
         int64_t cap = (je - jb + minp - 1) / minp;
         if (nsl > 1) cap = (cap + nsl - 1) / nsl;
         if (nch > cap) nch = cap;
+        if (s == TC_STRAT_MERGE && ((b >> 5) & 31) <= kLaneMergeOb)   // one lane walks an item's partners
+            nch = (je - jb + kLanePartners - 1) / kLanePartners;
         if (nch < 1) nch = 1;
         bk[k] = b;
         st[k] = s;
@@ -301,36 +307,44 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
 // queue larger owners first.  One block: place every bucket's item count at
 // its queue position, exclusive-scan the 4096 positions, read offsets back.
 // q[2] = workgroup items, q[3] = all items.
+// Three sections: workgroup-table items, then wavefront items, then the
+// lane items (merge strategy with owner lists below 2^(kLaneMergeOb + 1)),
+// which wavefronts take 64 at a time, one per lane.
 __device__ __forceinline__ int queue_pos(const SchedCfg &sc, int b) {
     const int ob = (b >> 5) & 31, pb = b & 31, kind = b >> 10;
-    const bool wg = strategy_for(sc, b) == TC_STRAT_WG_HASH;
-    return (wg ? 0 : kBuckets) + ((31 - ob) * 32 + (31 - pb)) * 2 + kind;
+    const int s = strategy_for(sc, b);
+    const int section = s == TC_STRAT_WG_HASH ? 0 : (s == TC_STRAT_MERGE && ob <= kLaneMergeOb ? 2 : 1);
+    return section * kBuckets + ((31 - ob) * 32 + (31 - pb)) * 2 + kind;
 }
 
 __global__ __launch_bounds__(1024) void k_bucket_order(const int32_t *__restrict__ bucket_items, SchedCfg sc,
                                                         int32_t *__restrict__ bucket_off, int32_t *__restrict__ q) {
-    __shared__ int32_t A[2 * kBuckets];
+    constexpr int kPerThread = 3 * kBuckets / 1024;
+    __shared__ int32_t A[3 * kBuckets];
     __shared__ int32_t wtot[16];
     const int t = threadIdx.x;
-    for (int i = t; i < 2 * kBuckets; i += 1024) A[i] = 0;
+    for (int i = t; i < 3 * kBuckets; i += 1024) A[i] = 0;
     __syncthreads();
     for (int b = t; b < kBuckets; b += 1024) A[queue_pos(sc, b)] = bucket_items[b];
     __syncthreads();
-    int32_t v[4];
+    int32_t v[kPerThread];
     int32_t sum = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) { v[j] = A[4 * t + j]; sum += v[j]; }
+    for (int j = 0; j < kPerThread; ++j) { v[j] = A[kPerThread * t + j]; sum += v[j]; }
     const int32_t inc = wave_incl_scan(sum);
     if (lane_id() == kWave - 1) wtot[t / kWave] = inc;
     __syncthreads();
     int32_t run = inc - sum;
     for (int i = 0; i < t / kWave; ++i) run += wtot[i];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) { A[4 * t + j] = run; run += v[j]; }
+    for (int j = 0; j < kPerThread; ++j) { A[kPerThread * t + j] = run; run += v[j]; }
     if (t == 1023) q[3] = run;
     __syncthreads();
     for (int b = t; b < kBuckets; b += 1024) bucket_off[b] = A[queue_pos(sc, b)];
-    if (t == 0) q[2] = A[kBuckets];
+    if (t == 0) {
+        q[2] = A[kBuckets];       // first wavefront item
+        q[4] = A[2 * kBuckets];   // first lane item
+    }
 }
 
 // ---------------------------------------------------------------- probes
@@ -624,6 +638,37 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     return hits;
 }
 
+// Merge strategy for a small owner, one lane per item: the lane walks the
+// item's partners and merges each owned partner list (never longer than the
+// owner's) with the owner list.  Hits of this lane.
+__device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, int32_t x, int32_t jb, int32_t je) {
+    const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
+    const int32_t sx = list_size(kind, g.up0, g.rp1, x);
+    const int32_t *lists = kind == 0 ? g.c0 : g.c1;
+    uint32_t hits = 0;
+    for (int32_t p = jb; p < je; ++p) {
+        int32_t sy, yb;
+        if (!partner_at(g, kind, x, sx, p, je, sy, yb)) continue;   // owned: sx >= sy >= 1
+        const int32_t *b = lists + yb;
+        int32_t i = 0, j = 0, ai = a[0], bj = b[0];
+        for (;;) {
+            if (ai == bj) {
+                ++hits;
+                if (++i >= sx || ++j >= sy) break;
+                ai = a[i];
+                bj = b[j];
+            } else if (ai < bj) {
+                if (++i >= sx) break;
+                ai = a[i];
+            } else {
+                if (++j >= sy) break;
+                bj = b[j];
+            }
+        }
+    }
+    return hits;
+}
+
 // Merge strategy: partners one at a time, each merged against the owner list.
 __device__ __forceinline__ uint32_t merge_chunk(const Graph &g, int kind, int32_t x, int32_t sx, const int32_t *a,
                                                 int32_t p0, int32_t je) {
@@ -731,7 +776,8 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
     // then one of the next, and so on; no shared counter is needed.
     int32_t *tab = lds + (w << wave_log2);
     const int32_t G = (int32_t)gridDim.x * kIsectWaves;
-    for (int32_t it = n_wg + (int32_t)blockIdx.x * kIsectWaves + w; it < n_all; it += G) {
+    const int32_t n_lane0 = q[4];
+    for (int32_t it = n_wg + (int32_t)blockIdx.x * kIsectWaves + w; it < n_lane0; it += G) {
         const uint64_t t_beg = kProf ? wall_clock64() : 0;
         const Item item = items[it];
         const int kind = item.code & 1;
@@ -772,6 +818,30 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             unsigned long long *pr = prof + (((item.code >> 3) & (kBuckets - 1)) * TC_NUM_STRATEGIES + strat) * 3;
             atomicAdd(&pr[0], (unsigned long long)(wall_clock64() - t_beg));
             atomicAdd(&pr[2], 1ull);
+        }
+    }
+
+    // ---- lane items: groups of 64 consecutive items, one per lane
+    for (int32_t g0 = n_lane0 + ((int32_t)blockIdx.x * kIsectWaves + w) * kWave; g0 < n_all; g0 += G * kWave) {
+        const uint64_t t_beg = kProf ? wall_clock64() : 0;
+        const int32_t it = g0 + l;
+        int32_t code = 0;
+        if (it < n_all) {
+            const Item item = items[it];
+            const int kind = item.code & 1;
+            code = item.code;
+            const uint32_t h = lane_merge_item(g, kind, item.owner, item.jb, item.je);
+            if (kind == 0) acc0 += h; else acc1 += h;
+            if (kBatch && h) atomicAdd(&bt.counts[bt.gid[item.owner]], (unsigned long long)h);
+        }
+        if (kProf) {   // the group holds the wavefront until its slowest lane ends: 1/64 of that per item
+            const uint64_t t_group = wall_clock64() - t_beg;
+            if (it < n_all) {
+                unsigned long long *pr =
+                    prof + (((code >> 3) & (kBuckets - 1)) * TC_NUM_STRATEGIES + TC_STRAT_MERGE) * 3;
+                atomicAdd(&pr[0], (unsigned long long)(t_group + kWave - 1) / kWave);
+                atomicAdd(&pr[2], 1ull);
+            }
         }
     }
 
@@ -831,13 +901,7 @@ int ilog2_host(int v) {
     return k;
 }
 
-int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, CountOut *out, void *ws,
-              size_t ws_bytes, hipStream_t s) {
-    Carver c(ws, ws_bytes);
-    CountLayout L = carve_count(c, n, nnz);
-    if (!c.fits()) return TC_ERR_WORKSPACE;
-    DeviceInfo di;
-    TC_TRY(device_info(&di));
+static SchedCfg sched_cfg(int32_t n, int64_t nnz, const CountCfg &cfg) {
     const int wave_log2 = ilog2_host(cfg.wave_slots);
     const int wg_log2 = ilog2_host(cfg.wg_slots);
     SchedCfg sc;
@@ -851,7 +915,33 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         sc.wg_slicing = longest <= ((int64_t)1 << (kMaxSlicesLog2 + sc.wg_cap_log2)) ? 1 : 0;
     }
     sc.heur_wave_ob = cfg.wave_max_owner > 0 ? ilog2_host(cfg.wave_max_owner) : wave_log2 - 2;
+    sc.heur_merge_ob = cfg.merge_max_owner < 0 ? -1 : ilog2_host(cfg.merge_max_owner > 0 ? cfg.merge_max_owner : 7);
+    if (sc.heur_merge_ob > kLaneMergeOb) sc.heur_merge_ob = kLaneMergeOb;
     sc.chunk_work = cfg.chunk_work;
+    return sc;
+}
+
+static __global__ void k_schedule_table(SchedCfg sc, int32_t *__restrict__ out) {
+    const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b < kBuckets) out[b] = strategy_for(sc, b);
+}
+
+int schedule_table_run(int32_t n, int64_t nnz, const CountCfg &cfg, int32_t *table, hipStream_t s) {
+    hipLaunchKernelGGL(k_schedule_table, dim3(kBuckets / 256), dim3(256), 0, s, sched_cfg(n, nnz, cfg), table);
+    TC_HIP_TRY(hipGetLastError());
+    return TC_OK;
+}
+
+int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, CountOut *out, void *ws,
+              size_t ws_bytes, hipStream_t s) {
+    Carver c(ws, ws_bytes);
+    CountLayout L = carve_count(c, n, nnz);
+    if (!c.fits()) return TC_ERR_WORKSPACE;
+    DeviceInfo di;
+    TC_TRY(device_info(&di));
+    const int wave_log2 = ilog2_host(cfg.wave_slots);
+    const int wg_log2 = ilog2_host(cfg.wg_slots);
+    const SchedCfg sc = sched_cfg(n, nnz, cfg);
 
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (cfg.timing) {

@@ -187,6 +187,7 @@ struct CountCfg {
     int chunk_work = 16384;
     int grid_blocks = 0;
     int wave_max_owner = 0;
+    int merge_max_owner = 0;
     const int32_t *table = nullptr;   // device per-bucket strategies (schedule)
     unsigned long long *prof = nullptr;   // device per-(bucket, strategy) profile, or NULL
     const int32_t *gid = nullptr;         // batch: graph of every vertex, or NULL
@@ -196,6 +197,9 @@ struct CountCfg {
 // Checked options -> configuration (TC_ERR_ARG for invalid options).
 int options_cfg(const tc_options *opt, CountCfg *cfg, int *flags);
 size_t count_ws_bytes(int32_t n, int64_t nnz);
+// The strategy each bucket gets under cfg for a graph of n vertices and nnz
+// entries (force, table or heuristic, after the feasibility rules).
+int schedule_table_run(int32_t n, int64_t nnz, const CountCfg &cfg, int32_t *table, hipStream_t s);
 int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, CountOut *out,
               void *ws, size_t ws_bytes, hipStream_t s);
 

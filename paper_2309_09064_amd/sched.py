@@ -3,9 +3,15 @@
 Not part of the paper's method.  Every strategy counts exactly, so the
 schedule only decides speed.  The cycle:
 
-1. ``collect_profile``: count graphs with each strategy forced in turn,
-   with the instrumented kernels (``tc_count_profile``), which accumulate
-   per (bucket, strategy) the wavefront-ticks spent and the elements handled.
+1. ``collect_profile``: count graphs with the instrumented kernels
+   (``tc_count_profile``), which accumulate per (bucket, strategy) the
+   wavefront-ticks spent and the elements handled.  In the default
+   "context" mode the buckets are split into four random groups and each
+   group in turn runs each strategy while the other buckets keep the
+   heuristic's choice, so every (bucket, strategy) cost is measured once
+   inside a realistic mix (costs measured with one strategy forced
+   everywhere do not carry over: e.g. binary search then competes only with
+   itself for memory).
 2. ``dataset``: one training row per (bucket, strategy) with enough work:
    features (ob, pb, kind) of the bucket, the strategy, and the target
    log2(wavefront-ticks per element).
@@ -25,7 +31,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import Counter, Options, TCError, _capi, _check, _ptr, _stream, new_profile, workspace
+from . import Counter, Options, TCError, _capi, _check, _ptr, _stream, new_profile, schedule_table, workspace
 from ._capi import TC_MLP_IN, TC_NUM_BUCKETS, TC_NUM_STRATEGIES
 
 HIDDEN = 32
@@ -122,17 +128,36 @@ class CostNet:
 
 
 def collect_profile(graphs, options: Options | None = None, strategies=range(TC_NUM_STRATEGIES), repeats: int = 1,
-                    profile: torch.Tensor | None = None) -> torch.Tensor:
-    """Profile every (row_ptr, col[, levels]) graph under each forced
-    strategy; returns the accumulated profile [TC_NUM_BUCKETS, 4, 3]."""
+                    profile: torch.Tensor | None = None, mode: str = "context", groups: int = 4,
+                    seed: int = 0) -> torch.Tensor:
+    """Profile every (row_ptr, col[, levels]) graph; returns the accumulated
+    profile [TC_NUM_BUCKETS, 4, 3].  ``mode`` "context": per group of
+    buckets and strategy, one run with that group switched to the strategy
+    and the rest on the heuristic's choice; "forced": one run per strategy
+    forced on every bucket."""
+    if mode not in ("context", "forced"):
+        raise ValueError("mode is 'context' or 'forced'")
     base = options or Options()
     prof = profile if profile is not None else new_profile()
+    rng = np.random.default_rng(seed)
     for g in graphs:
         rp, col = g[0], g[1]
         lev = g[2] if len(g) > 2 else None
-        for s in strategies:
-            o = Options(**{**base.__dict__, "force_strategy": int(s), "sched_table": None})
-            cnt = Counter(rp.numel() - 1, col.numel(), o, rp.device)
+        n, nnz = rp.numel() - 1, col.numel()
+        runs = []
+        if mode == "forced":
+            runs = [Options(**{**base.__dict__, "force_strategy": int(s), "sched_table": None}) for s in strategies]
+        else:
+            heur = schedule_table(n, nnz, Options(**{**base.__dict__, "sched_table": None}), rp.device).cpu().numpy()
+            grp = rng.permutation(TC_NUM_BUCKETS) % groups
+            for r in range(groups):
+                for s in strategies:
+                    t = heur.copy()
+                    t[grp == r] = int(s)
+                    runs.append(Options(**{**base.__dict__, "force_strategy": -1,
+                                           "sched_table": torch.from_numpy(t).to(rp.device)}))
+        for o in runs:
+            cnt = Counter(n, nnz, o, rp.device)
             cnt(rp, col, lev)          # warm (not profiled)
             for _ in range(repeats):
                 cnt(rp, col, lev, profile=prof)

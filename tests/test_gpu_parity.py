@@ -187,7 +187,8 @@ def test_count_strategy_invariance(tc, name, strategy):
 
 @pytest.mark.parametrize("cfg", [dict(wave_slots=64, wg_slots=1024), dict(wave_slots=128, wg_slots=1024, chunk_work=64),
                                  dict(chunk_work=1), dict(grid_blocks=1), dict(grid_blocks=3, wave_slots=256),
-                                 dict(wave_max_owner=8)])
+                                 dict(wave_max_owner=8), dict(merge_max_owner=31), dict(merge_max_owner=-1),
+                                 dict(merge_max_owner=1, wave_slots=64)])
 @pytest.mark.parametrize("name", ["kron14", "chunglu14", "er_dense"])
 def test_count_tiles_and_grids(tc, name, cfg):
     check_count(tc, graph(name), tc.Options(**cfg))

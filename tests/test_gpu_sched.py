@@ -251,3 +251,41 @@ def test_arbitrary_tables_count_exactly(tc, seed):
     bad = torch.zeros(2048, dtype=torch.int64, device="cuda")
     with pytest.raises(ValueError):
         tc.Options(sched_table=bad).to_c()
+
+
+def test_schedule_table_entry_point(tc):
+    # the effective table: forced strategies everywhere feasible, the
+    # heuristic's three owner-size ranges, and a given table after feasibility
+    t = tc.schedule_table(1000, 10000).cpu().numpy()
+    ob = (np.arange(2048) >> 5) & 31
+    assert np.all(t[ob <= 2] == 3) and np.all(t[(ob > 2) & (ob <= 9)] == 0) and np.all(t[ob > 9] == 1)
+    t = tc.schedule_table(1000, 10000, tc.Options(force_strategy=0, wave_slots=64)).cpu().numpy()
+    assert np.all(t[ob <= 4] == 0) and np.all(t[ob > 4] == 1)
+    t = tc.schedule_table(1000, 10000, tc.Options(merge_max_owner=-1)).cpu().numpy()
+    assert not np.any(t == 3)
+    given = dev(np.full(2048, 0))
+    t = tc.schedule_table(1000, 10000, tc.Options(sched_table=given, wave_slots=256)).cpu().numpy()
+    assert np.all(t[ob <= 6] == 0) and np.all(t[ob > 6] == 1)
+
+
+def test_learned_schedule_gain_is_measured(tc, sched):
+    # what the trained network gains over the heuristic on one graph: the
+    # counts are identical; the ratio of intersection times is reported
+    g = kron(16, seed=11)
+    rp, col = to_gpu(g)
+    lev, _ = tc.bfs_levels(rp, col)
+    table, net, ds, losses = sched.learn_schedule([(rp, col, lev)], steps=1500, lr=5e-3)
+
+    def isect_ms(opts):
+        c = tc.Counter(g.n, g.nnz, opts)
+        ms = []
+        for _ in range(6):
+            r = c(rp, col, lev)
+            ms.append(r.ms["isect"])
+        return r.T, float(np.median(ms[1:]))
+
+    Th, th = isect_ms(tc.Options(timing=True))
+    Tl, tl = isect_ms(tc.Options(timing=True, sched_table=table))
+    assert Th == Tl == oracle.alg4(g).T
+    print(f"\nlearned / heuristic intersection time: {tl / th:.3f} ({tl:.3f} ms vs {th:.3f} ms)")
+    assert tl < 1.5 * th
