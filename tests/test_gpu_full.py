@@ -1,13 +1,18 @@
 """Full-size parity on the large configurations: Kronecker scale 24 and the
 Chung-Lu power-law graph with n = 2^22.  The oracle computes the BFS levels
 and the partition of these graphs in seconds, so those are compared element
-by element.  The oracle's count of a graph this size takes many minutes, so
-the count is checked through properties that hold at any size: T is the same
-for every valid level assignment (the cover-edge argument: any L with
-|L(u) - L(v)| <= 1 on every edge), for every forced strategy, T = T0 + T1,
-|E0| equals the horizontal edges of the levels, and L = 0 (every edge
-horizontal) gives T1 = 0."""
+by element.  The oracle's count of a graph this size takes minutes to most
+of an hour, so its T, T0, T1 and |E0| are stored in tests/golden/
+large_counts.txt (written by tests/golden/make_large_counts.py, which calls
+the oracle only) and compared bit for bit; the count is also checked through
+properties that hold at any size: T is the same for every valid level
+assignment (the cover-edge argument: any L with |L(u) - L(v)| <= 1 on every
+edge), for every forced strategy, T = T0 + T1, |E0| equals the horizontal
+edges of the levels, and L = 0 (every edge horizontal) gives T1 = 0."""
+
 from __future__ import annotations
+
+import os
 
 import numpy as np
 import pytest
@@ -63,10 +68,27 @@ def test_levels_and_partition_full(tc, big):
     assert part["e0"] * 2 == e0x2
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_counts.txt")
+GOLDEN_NAME = {"kronecker24": "kronecker24", "chunglu22": "chunglu22"}
+
+
+def golden_counts():
+    out = {}
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                name, n, m, T, T0, T1, e0 = line.split()
+                out[name] = tuple(int(v) for v in (n, m, T, T0, T1, e0))
+    return out
+
+
 def test_count_properties_full(tc, big):
     name, n, rp, col, g = big
     lev, _ = tc.bfs_levels(rp, col)
     base = tc.count(rp, col)
+    gn, gm, gT, gT0, gT1, ge0 = golden_counts()[GOLDEN_NAME[name]]
+    assert (n, g.nnz // 2) == (gn, gm)
+    assert (base.T, base.T0, base.T1, base.e0) == (gT, gT0, gT1, ge0)
     assert base.T == base.T0 + base.T1 and base.T1 > 0
     # |E0| from the levels, on the host
     deg = np.diff(g.row_ptr)
