@@ -405,14 +405,22 @@ __device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (
     for (int u = 0; u < kPer; ++u) b[u] = home_bucket(t, v[u]);
 #pragma unroll
     for (int u = 0; u < kPer; ++u) q[u] = *reinterpret_cast<const int4 *>(&t.tab[4 * b[u]]);
-    uint32_t hits = 0, pend = 0;
+    uint32_t hits = 0;
+    bool any_pend = false;   // a wavefront mask: no per-lane bits in the common case
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int32_t x = v[u];
         const bool m = bucket_has(q[u], x);
         const bool live = x >= 0;
         hits += (live & m) ? 1u : 0u;
-        pend |= (live & !m & (q[u].w != kEmpty)) ? (1u << u) : 0u;
+        any_pend |= live & !m & (q[u].w != kEmpty);
+    }
+    if (__ballot(any_pend) == 0) return hits;
+    uint32_t pend = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int32_t x = v[u];
+        pend |= ((x >= 0) & !bucket_has(q[u], x) & (q[u].w != kEmpty)) ? (1u << u) : 0u;
     }
     while (pend) {
         const int u = __builtin_ctz(pend);
@@ -620,17 +628,19 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
         for (int u = 0; u < kPer; ++u) v[u] = base + u * kWave + l < total ? v[u] : -1;
     };
     // software pipeline: the next window's loads are issued before this
-    // window's lookups, so their latency overlaps the LDS probes
+    // window's lookups, so their latency overlaps the LDS probes.  The next
+    // gather is unconditional (past the end it reads clamped, valid
+    // addresses) so that every iteration has the same loads in flight and the
+    // wait before the lookups covers only this window's loads.
     uint32_t hits = 0;
     int32_t va[kPer];
     gather(0, va);
     for (int32_t base = 0;; base += kStep) {
         int32_t vb[kPer];
-        const bool more = base + kStep < total;
-        if (more) gather(base + kStep, vb);
+        gather(base + kStep, vb);
         masked(base, va);
         hits += count(va);
-        if (!more) break;
+        if (base + kStep >= total) break;
 #pragma unroll
         for (int u = 0; u < kPer; ++u) va[u] = vb[u];
     }
