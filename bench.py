@@ -161,6 +161,24 @@ def main():
     print(f"# timed: {args.steps} steps, {step_s * 1e3:.3f} ms/step, T={T}; phase ms {ms}", file=sys.stderr,
           flush=True)
 
+    # context: the same kernels with every edge horizontal (L = 0): plain
+    # forward-hashed counting of the whole graph, no BFS (the paper's FH/FHD
+    # comparison, Table I)
+    zero = torch.zeros(n, dtype=torch.int32, device="cuda")
+    fcounter = tc.Counter(n, nnz, tc.Options(timing=True))
+    for _ in range(args.warmup):
+        fcounter(rp, col, zero)
+    torch.cuda.synchronize()
+    fres = []
+    t_f0 = time.perf_counter()
+    for _ in range(args.steps):
+        fres.append(fcounter(rp, col, zero))
+    torch.cuda.synchronize()
+    fstep_s = (time.perf_counter() - t_f0) / args.steps
+    assert all(x.T == T for x in fres), "forward-hashed count differs"
+    forward_hashed = {"value": m / fstep_s, "ms_per_step": fstep_s * 1e3, "phase_ms": phase_means(fres)}
+    print(f"# forward-hashed (L = 0): {fstep_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+
     learned = None
     if not args.no_learned:
         # learned schedule: profile this graph under each forced strategy,
@@ -221,7 +239,7 @@ def main():
                    "n": n, "m": m, "triangles": T, "T0": r.T0, "T1": r.T1, "e0": r.e0,
                    "k_percent": round(100.0 * r.e0 / m, 2), "levels": r.levels, "counts_bit_exact": exact,
                    "phase_ms": ms, "items": r.items, "strategy_items": r.strategy_items,
-                   "learned_schedule": learned},
+                   "learned_schedule": learned, "forward_hashed_same_kernels": forward_hashed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_isect",
                      "bytes_per_launch": balg, "ms_per_launch": ms["isect"]},
