@@ -251,6 +251,7 @@ CountPlan carve_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels) {
     P.pb.d0 = c.take<int32_t>(nn);
     P.pb.rpu = c.take<int32_t>(nn + 1);
     P.pb.e0x2 = c.take<int64_t>(1);
+    P.pb.vrec = c.take<int4>(nn);
     P.flag = c.take<int32_t>(64);
     size_t sb = bfs_ws_bytes(n, nnz);
     size_t t = partition_ws_bytes(n, nnz);

@@ -113,8 +113,8 @@ __device__ __forceinline__ int32_t owner_slices(int32_t sx, int cap_log2) {
 __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__restrict__ e0x2p,
                                                    const int32_t *__restrict__ rp0,
                                                    const int32_t *__restrict__ c0, const int32_t *__restrict__ up0,
-                                                   const int32_t *__restrict__ rp1, int32_t *__restrict__ cnt,
-                                                   unsigned long long *__restrict__ work) {
+                                                   const int32_t *__restrict__ rp1, const int4 *__restrict__ vrec,
+                                                   int32_t *__restrict__ cnt, unsigned long long *__restrict__ work) {
     __shared__ int64_t rows[2];
     __shared__ int32_t acc_n[2][kOwnRowsMax];
     __shared__ unsigned long long acc_w[2][kOwnRowsMax];
@@ -160,7 +160,8 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
                     s1x = rp1[x + 1] - rp1[x];
                 }
                 const int32_t y = c0[e];
-                const int32_t s0y = up0[y], s1y = rp1[y + 1] - rp1[y];
+                const int4 ry = vrec[y];
+                const int32_t s0y = ry.y, s1y = ry.w;
                 if (owns(s0x, s0y, (int32_t)x, y)) { ++n0; w0 += (unsigned)s0y; }
                 if (owns(s1x, s1y, (int32_t)x, y)) { ++n1; w1 += (unsigned)s1y; }
             }
@@ -528,6 +529,7 @@ __device__ __forceinline__ uint32_t merge_count(const int32_t *a, int32_t la, co
 
 struct Graph {
     const int32_t *rp0, *c0, *up0, *rp1, *c1;
+    const int4 *vrec;   // per vertex {rp0, |N0+|, rp1, |N1|}
 };
 
 // Elements per lane per window step, and the per-wavefront LDS scratch used
@@ -546,13 +548,9 @@ __device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t x, 
     yb = 0;
     if (p >= je) return false;
     const int32_t y = g.c0[p];
-    if (kind == 0) {
-        sy = g.up0[y];
-        yb = g.rp0[y];
-    } else {
-        yb = g.rp1[y];
-        sy = g.rp1[y + 1] - yb;
-    }
+    const int4 r = g.vrec[y];   // one 16-byte record for either kind
+    sy = kind == 0 ? r.y : r.w;
+    yb = kind == 0 ? r.x : r.z;
     return owns(sx, sy, x, y);
 }
 
@@ -967,7 +965,7 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     TC_HIP_TRY(hipMemsetAsync(L.stats, 0, sizeof(unsigned long long) * 16, s));
     const unsigned gp = (unsigned)di.cus * 8;
     if (n > 0) {
-        hipLaunchKernelGGL(k_own, dim3(gp), dim3(kThreads), 0, s, n, pb.e0x2, pb.rp0, pb.c0, pb.up0, pb.rp1, L.cnt,
+        hipLaunchKernelGGL(k_own, dim3(gp), dim3(kThreads), 0, s, n, pb.e0x2, pb.rp0, pb.c0, pb.up0, pb.rp1, pb.vrec, L.cnt,
                            L.work);
         TC_HIP_TRY(hipGetLastError());
         const unsigned gu = grid_for(2 * (int64_t)n, kItemThreads * kUnitsPerThread, (int64_t)1 << 30);
@@ -994,7 +992,7 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         if (per_cu < 1) per_cu = 1;
         if (getenv("TC_LOG")) fprintf(stderr, "libtc: k_isect %d blocks/CU, %zu B LDS\n", per_cu, lds_bytes);
         const unsigned gi = cfg.grid_blocks > 0 ? (unsigned)cfg.grid_blocks : (unsigned)(di.cus * per_cu);
-        Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1};
+        Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1, pb.vrec};
         const Batch bt{cfg.gid, cfg.batch_counts};
         if (cfg.prof && batch)
             hipLaunchKernelGGL((k_isect<true, true>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items, L.q,

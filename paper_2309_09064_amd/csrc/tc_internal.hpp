@@ -166,6 +166,7 @@ struct PartBufs {
     int32_t *d0;                          // n: |N0(x)|
     int32_t *rpu;                         // n+1: prefix of up0
     int64_t *e0x2;                        // device scalar: 2|E0|
+    int4 *vrec = nullptr;                 // n: {rp0, |N0+|, rp1, |N1|} per vertex, or NULL
 };
 size_t partition_ws_bytes(int32_t n, int64_t nnz);
 int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, const int32_t *lev,

@@ -28,15 +28,22 @@ constexpr int kBlockEntries = kThreads * kRun;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kTileRowsMax = 1024;   // rows a tile may span and still count in LDS
 
-// rank(y) > rank(x) with rank = (degree, id), dx = deg(x)
-__device__ __forceinline__ bool rank_above(const int32_t *rp, int32_t y, int32_t x, int32_t dx) {
-    int32_t dy = rp[y + 1] - rp[y];
+// rank(y) > rank(x) with rank = (degree, id)
+__device__ __forceinline__ bool rank_above(int32_t dy, int32_t y, int32_t x, int32_t dx) {
     return dy > dx || (dy == dx && y > x);
+}
+
+// {level, degree} of every vertex in one 8-byte record, so the marking pass
+// reads one record per neighbour instead of three scattered words.
+__global__ void k_part_vld(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ lev,
+                           int2 *__restrict__ vld) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        vld[v] = make_int2(lev[v], rp[v + 1] - rp[v]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
-                                                         const int32_t *__restrict__ lev,
+                                                         const int2 *__restrict__ vld,
                                                          uint8_t *__restrict__ flags, int32_t *__restrict__ d0,
                                                          int32_t *__restrict__ up0, int32_t *__restrict__ bh,
                                                          int32_t *__restrict__ bu) {
@@ -59,7 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
         const int64_t e1 = e0 + kRun < nnz ? e0 + kRun : nnz;
         int64_t x = row_of(rp, r_lo, r_hi, e0);
         int64_t xe = rp[x + 1];
-        int32_t lx = lev[x], dx = (int32_t)(xe - rp[x]);
+        int32_t lx = vld[x].x, dx = (int32_t)(xe - rp[x]);
         int32_t ch = 0, cu = 0;
         auto flush = [&]() {
             if (local) {
@@ -82,12 +89,13 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
                     flush();
                     ++x;
                     xe = rp[x + 1];
-                    lx = lev[x];
+                    lx = vld[x].x;
                     dx = (int32_t)(xe - rp[x]);
                 }
                 const int32_t y = col[e];
-                const bool hor = lev[y] == lx;
-                const bool up = hor && rank_above(rp, y, (int32_t)x, dx);
+                const int2 iy = vld[y];
+                const bool hor = iy.x == lx;
+                const bool up = hor && rank_above(iy.y, y, (int32_t)x, dx);
                 f[k] = (uint8_t)(hor | (up << 1));
                 ch += hor;
                 cu += up;
@@ -132,6 +140,14 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
         bh[blockIdx.x] = a;
         bu[blockIdx.x] = b;
     }
+}
+
+// Per-vertex record of the partition {rp0, |N0+|, rp1, |N1|}: the counting
+// kernels read one 16-byte record per partner instead of three words.
+__global__ void k_part_vrec(int32_t n, const int32_t *__restrict__ rp0, const int32_t *__restrict__ up0,
+                            const int32_t *__restrict__ rp1, int4 *__restrict__ vrec) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        vrec[x] = make_int4(rp0[x], up0[x], rp1[x], rp1[x + 1] - rp1[x]);
 }
 
 __global__ void k_part_rp1(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ rp0,
@@ -202,6 +218,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
 }
 
 struct PartLayout {
+    int2 *vld;
     uint8_t *flags;
     int32_t *bh, *bu;
     void *scan;
@@ -210,6 +227,7 @@ struct PartLayout {
 PartLayout carve_part(Carver &c, int32_t n, int64_t nnz) {
     PartLayout L;
     const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
+    L.vld = c.take<int2>(n > 0 ? n : 1);
     L.flags = c.take<uint8_t>(nnz > 0 ? nnz : 1);
     L.bh = c.take<int32_t>(nblk + 1);
     L.bu = c.take<int32_t>(nblk + 1);
@@ -242,7 +260,8 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
     TC_HIP_TRY(hipMemsetAsync(pb.up0, 0, sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
     const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_part_mark, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, lev, L.flags,
+        hipLaunchKernelGGL(k_part_vld, dim3(grid_for(n, 256)), dim3(256), 0, s, n, rp, lev, L.vld);
+        hipLaunchKernelGGL(k_part_mark, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, L.vld, L.flags,
                            pb.d0, pb.up0, L.bh, L.bu);
         TC_HIP_TRY(hipGetLastError());
     }
@@ -251,6 +270,10 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
     hipLaunchKernelGGL(k_part_rp1, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, n, rp, pb.rp0, pb.rp1,
                        pb.e0x2);
     TC_HIP_TRY(hipGetLastError());
+    if (pb.vrec) {
+        hipLaunchKernelGGL(k_part_vrec, dim3(grid_for(n, 256)), dim3(256), 0, s, n, pb.rp0, pb.up0, pb.rp1, pb.vrec);
+        TC_HIP_TRY(hipGetLastError());
+    }
     if (nnz > 0) {
         TC_TRY(scan_exclusive_i32_to_i32(L.bh, L.bh, nblk, L.scan, s));
         TC_TRY(scan_exclusive_i32_to_i32(L.bu, L.bu, nblk, L.scan, s));
