@@ -264,6 +264,21 @@ uint64_t tc_count_profile(int32_t n, int64_t nnz, const int32_t *d_row_ptr, cons
                           const int32_t *d_levels, const tc_options *opt, tc_stats *stats,
                           uint64_t *d_prof, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Per-vertex triangle counts t(v): the number of triangles containing v, the
+ * input of the local clustering coefficient (the applications named in the
+ * paper's Introduction).  Each triangle is found exactly once by Algorithm
+ * 4, through its one cover edge xy and common neighbour w, and adds 1 to
+ * t(x), t(y) and t(w), so sum_v t(v) = 3T.
+ *   d_tv   device uint64[n], output, written in full (zeroed by the call)
+ * Other arguments, the workspace size (tc_count_ws) and the return value as
+ * for tc_count; opt->schedule, force_strategy and the tile options apply.
+ * Scattered 64-bit atomics make this slower than tc_count.  Synchronises.
+ */
+uint64_t tc_vertex_triangles(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                             const int32_t *d_levels, const tc_options *opt, uint64_t *d_tv, tc_stats *stats,
+                             void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ cost network
  *
  * A small fully connected network predicts, for a bucket, the cost of each

@@ -15,6 +15,7 @@ Counting" (arXiv 2309.09064):
 * :func:`count_emd`          direction-oriented sorted-merge edge iterator
 * :func:`alg3`               cover-edge count (Alg. 3)
 * :func:`vertex_triangles`   per-vertex triangle counts
+* :func:`vertex_triangles_at`  the same for sampled vertices, by another definition
 
 :mod:`oracle.mlp` holds the float64 reference of the scheduler network.
 """
@@ -67,6 +68,8 @@ def _load():
         lib.orc_alg3.restype = ctypes.c_uint64
         lib.orc_vertex_triangles.argtypes = [ctypes.c_int64, _i64, _i32, _u64]
         lib.orc_vertex_triangles.restype = None
+        lib.orc_vertex_triangles_at.argtypes = [ctypes.c_int64, _i64, _i32, ctypes.c_int64, _i64, _u64]
+        lib.orc_vertex_triangles_at.restype = None
         _lib = lib
     return _lib
 
@@ -185,6 +188,18 @@ def vertex_triangles(g: CSR) -> np.ndarray:
     tv = np.zeros(max(g.n, 1), np.uint64)
     _load().orc_vertex_triangles(g.n, g.row_ptr, _col_or_dummy(g), tv)
     return tv[:g.n]
+
+
+def vertex_triangles_at(g: CSR, vertices) -> np.ndarray:
+    """t(v) for the given vertices only, from the edges among each one's
+    neighbours (cost about deg(v)^2 log d_max per vertex)."""
+    vs = np.ascontiguousarray(vertices, dtype=np.int64)
+    if vs.size and (vs.min() < 0 or vs.max() >= g.n):
+        raise ValueError("vertex out of range")
+    out = np.zeros(max(vs.size, 1), np.uint64)
+    _load().orc_vertex_triangles_at(g.n, g.row_ptr, _col_or_dummy(g), vs.size, vs if vs.size else np.zeros(1, np.int64),
+                                    out)
+    return out[:vs.size]
 
 
 def _floor_log2(v) -> np.ndarray:

@@ -311,3 +311,40 @@ void orc_vertex_triangles(int64_t n, const int64_t *row_ptr, const int32_t *col,
         }
     }
 }
+
+/*
+ * t(v) for a sample of vertices, one at a time, from the other plain
+ * definition: the edges among the neighbours of v, i.e. half the sum over
+ * u in N(v) of |N(u) and N(v) in common| (every such edge is seen from both
+ * ends).  Each common count binary-searches the members of N(v) in N(u), so
+ * a vertex of degree d costs about d^2 log(d_max): meant for samples of
+ * modest degree on graphs too large for the whole-graph routine.
+ */
+static int64_t in_row(const int32_t *a, int64_t len, int32_t key)
+{
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo < len && a[lo] == key;
+}
+
+void orc_vertex_triangles_at(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t k,
+                             const int64_t *vs, uint64_t *out)
+{
+    (void)n;
+    for (int64_t i = 0; i < k; ++i) {
+        int64_t v = vs[i];
+        const int32_t *nv = col + row_ptr[v];
+        int64_t dv = row_ptr[v + 1] - row_ptr[v];
+        uint64_t twice = 0;
+        for (int64_t j = 0; j < dv; ++j) {
+            int64_t u = nv[j];
+            const int32_t *nu = col + row_ptr[u];
+            int64_t du = row_ptr[u + 1] - row_ptr[u];
+            for (int64_t t = 0; t < dv; ++t) twice += (uint64_t)in_row(nu, du, nv[t]);
+        }
+        out[i] = twice / 2;
+    }
+}

@@ -18,7 +18,7 @@ from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_BUCKETS, TC_NUM_STRAT
                     TC_STRAT_WG_HASH, TC_TIMING, TC_VALIDATE)
 
 __all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count", "count_profile", "workspace",
-           "count_batched", "pack_csr", "schedule_table",
+           "count_batched", "pack_csr", "schedule_table", "vertex_triangles",
            "Counter", "CountResult", "new_profile",
            "STRATEGY_NAMES", "TC_STRAT_AUTO", "TC_STRAT_WAVE_HASH", "TC_STRAT_WG_HASH", "TC_STRAT_BSEARCH",
            "TC_STRAT_MERGE", "TC_SCHED_HEURISTIC", "TC_SCHED_TABLE", "TC_NUM_BUCKETS", "TC_NUM_STRATEGIES",
@@ -295,6 +295,29 @@ def count_batched(row_ptr: torch.Tensor, col: torch.Tensor, vtx_off, levels: tor
     if T == TC_COUNT_ERROR:
         raise TCError(lib.tc_last_error(), "tc_count_batched")
     return counts[:graphs], _result(T, st)
+
+
+def vertex_triangles(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor | None = None,
+                     options: Options | None = None, stream=None):
+    """Triangles through every vertex (tc_vertex_triangles).  Returns
+    (tv: int64 tensor of n entries viewing the uint64 counts, CountResult)."""
+    _require_i32_cuda(row_ptr, "row_ptr")
+    _require_i32_cuda(col, "col")
+    if levels is not None:
+        _require_i32_cuda(levels, "levels")
+    n, nnz = row_ptr.numel() - 1, col.numel()
+    lib = _capi.load()
+    opt = (options or Options()).to_c()
+    need = ctypes.c_size_t()
+    _check(lib.tc_count_ws(n, nnz, ctypes.byref(opt), ctypes.byref(need)), "tc_count_ws")
+    ws = workspace(need.value, row_ptr.device)
+    tv = torch.empty(max(n, 1), dtype=torch.int64, device=row_ptr.device)
+    st = _capi.tc_stats()
+    T = lib.tc_vertex_triangles(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(levels), ctypes.byref(opt), _ptr(tv),
+                                ctypes.byref(st), _ptr(ws), need.value, _stream(stream))
+    if T == TC_COUNT_ERROR:
+        raise TCError(lib.tc_last_error(), "tc_vertex_triangles")
+    return tv[:n], _result(T, st)
 
 
 def count(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor | None = None,

@@ -423,7 +423,8 @@ struct BatchArgs {
 
 static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                     const int32_t *d_levels, const tc_options *opt, tc_stats *stats, uint64_t *d_prof, void *ws,
-                    size_t ws_bytes, void *stream, const BatchArgs *batch = nullptr) {
+                    size_t ws_bytes, void *stream, const BatchArgs *batch = nullptr,
+                    uint64_t *d_tv = nullptr) {
     int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
     if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
     if (batch) {   // offsets: 0 = off[0] <= off[1] <= ... <= off[graphs] = n
@@ -441,6 +442,7 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
     if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
     if (cfg.schedule == TC_SCHED_TABLE && !cfg.table) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
     cfg.prof = reinterpret_cast<unsigned long long *>(d_prof);
+    cfg.tv = reinterpret_cast<unsigned long long *>(d_tv);
     size_t need = 0;
     {
         Carver c(nullptr, 0);
@@ -585,6 +587,14 @@ int tc_schedule_table(int32_t n, int64_t nnz, const tc_options *opt, int32_t *d_
     rc = device_info(&di);
     if (rc != TC_OK) return fail(rc);
     return fail(schedule_table_run(n, nnz, cfg, d_table, static_cast<hipStream_t>(stream)));
+}
+
+uint64_t tc_vertex_triangles(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                             const int32_t *d_levels, const tc_options *opt, uint64_t *d_tv, tc_stats *stats,
+                             void *ws, size_t ws_bytes, void *stream) {
+    if (!d_tv && n > 0) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
+    return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, nullptr,
+                      d_tv);
 }
 
 uint64_t tc_count_profile(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,

@@ -398,7 +398,9 @@ __device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
 // its probe chain, one pending key at a time per lane.  Keeping the common
 // case free of per-key predication is what bounds the instruction count:
 // the slowest of a wavefront's keys no longer sets the work of all of them.
-template <int kPer>
+// With kMask the result is the mask of keys found (bit u for key u) instead
+// of their number.
+template <int kPer, bool kMask = false>
 __device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (&v)[kPer]) {
     uint32_t b[kPer];
     int4 q[kPer];
@@ -413,7 +415,8 @@ __device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (
         const int32_t x = v[u];
         const bool m = bucket_has(q[u], x);
         const bool live = x >= 0;
-        hits += (live & m) ? 1u : 0u;
+        if constexpr (kMask) hits |= (live & m) ? (1u << u) : 0u;
+        else hits += (live & m) ? 1u : 0u;
         any_pend |= live & !m & (q[u].w != kEmpty);
     }
     if (__ballot(any_pend) == 0) return hits;
@@ -437,7 +440,8 @@ __device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (
             bb = (bb + 1) & t.bmask;
             const int4 r = *reinterpret_cast<const int4 *>(&t.tab[4 * bb]);
             if (bucket_has(r, x)) {
-                ++hits;
+                if constexpr (kMask) hits |= 1u << u;
+                else ++hits;
                 break;
             }
             if (r.w == kEmpty) break;
@@ -456,8 +460,8 @@ __device__ __forceinline__ uint32_t in_fours(const int32_t (&v)[8], Group grp) {
 }
 
 // Membership of up to kPer keys in a sorted global list by branch-free binary
-// search, the searches interleaved.
-template <int kPer>
+// search, the searches interleaved.  kMask as for hash_count.
+template <int kPer, bool kMask = false>
 __device__ __forceinline__ uint32_t search_count(const int32_t *a, int32_t len, const int32_t (&v)[kPer]) {
     int32_t base[kPer];
 #pragma unroll
@@ -476,7 +480,8 @@ __device__ __forceinline__ uint32_t search_count(const int32_t *a, int32_t len, 
     for (int u = 0; u < kPer; ++u) {
         if (v[u] < 0 || len <= 0) continue;
         const int32_t lb = base[u] + (a[base[u]] < v[u] ? 1 : 0);
-        hits += (lb < len && a[lb] == v[u]) ? 1u : 0u;
+        if constexpr (kMask) hits |= (lb < len && a[lb] == v[u]) ? (1u << u) : 0u;
+        else hits += (lb < len && a[lb] == v[u]) ? 1u : 0u;
     }
     return hits;
 }
@@ -510,7 +515,9 @@ __device__ __forceinline__ int32_t upper_idx(const int32_t *a, int32_t len, int3
 
 // Wave-parallel merge of sorted a (owner, length la) and b (partner, lb):
 // lane l merges its 1/64 slice of a with the matching value range of b.
-__device__ __forceinline__ uint32_t merge_count(const int32_t *a, int32_t la, const int32_t *b, int32_t lb) {
+// `on` sees every common value.
+template <class OnHit>
+__device__ __forceinline__ uint32_t merge_count(const int32_t *a, int32_t la, const int32_t *b, int32_t lb, OnHit on) {
     const int l = lane_id();
     const int32_t a0 = (int32_t)((int64_t)la * l / kWave), a1 = (int32_t)((int64_t)la * (l + 1) / kWave);
     if (a0 >= a1) return 0u;
@@ -522,7 +529,7 @@ __device__ __forceinline__ uint32_t merge_count(const int32_t *a, int32_t la, co
         int32_t x = a[i], y = b[j];
         if (x < y) ++i;
         else if (x > y) ++j;
-        else { ++hits; ++i; ++j; }
+        else { on(x); ++hits; ++i; ++j; }
     }
     return hits;
 }
@@ -536,18 +543,33 @@ struct Graph {
 // to flatten a batch of partner lists: 64 * kPer marker bytes (window offset
 // o lives at byte (o % 64) * kPer + o / 64, so a lane reads its kPer window
 // slots with one load) and 64 partner records {start in the batch, list
-// offset}.
+// offset}; with partner ids (per-vertex counts) 64 more ints hold the
+// partner vertex of every record.
 constexpr int kPer = 8;
 constexpr int kScratchInts = 16 * kPer + 128;
+constexpr int kScratchIdsInts = kScratchInts + 64;
+
+// What the intersection pass produces besides T0 and T1: per-graph counts of
+// a batch, or per-vertex triangle counts.
+enum { kModePlain = 0, kModeBatch = 1, kModeVertex = 2 };
+
+// Every hit is one triangle {x, y, w}: owner x, partner y, common neighbour w
+// (each triangle is found exactly once, through its one cover edge xy).
+struct Sink {
+    const int32_t *gid;            // batch: graph of every vertex
+    unsigned long long *counts;    // batch: one counter per graph
+    unsigned long long *tv;        // vertex: triangles through every vertex
+};
 
 // Partner information for the c0 position p of owner x: is the edge owned
-// for this kind, and where is the partner's list.
+// for this kind, which vertex is the partner, and where is its list.
 __device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p, int32_t je,
-                                           int32_t &sy, int32_t &yb) {
+                                           int32_t &sy, int32_t &yb, int32_t &y) {
     sy = 0;
     yb = 0;
+    y = 0;
     if (p >= je) return false;
-    const int32_t y = g.c0[p];
+    y = g.c0[p];
     const int4 r = g.vrec[y];   // one 16-byte record for either kind
     sy = kind == 0 ? r.y : r.w;
     yb = kind == 0 ? r.x : r.z;
@@ -561,15 +583,17 @@ __device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t x, 
 // found from a ballot of the marked list starts in the window and a
 // popcount, O(1) per element.
 // With `sliced`, only the part of each partner list with values in
-// [lo, hi) is streamed (two binary searches per partner).
-template <class Count>
+// [lo, hi) is streamed (two binary searches per partner).  With kIds every
+// element also carries its partner vertex: `count(v, y)` instead of
+// `count(v)`.
+template <bool kIds, class Count>
 __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p0,
                                                  int32_t je, int32_t *scr, Count count, bool sliced = false,
                                                  int32_t lo = 0, int32_t hi = 0) {
     static_assert(kPer == 8, "a lane reads its window markers as one 64-bit word");
     const int l = lane_id();
-    int32_t sy, yb;
-    bool mine = partner_at(g, kind, x, sx, p0 + l, je, sy, yb);
+    int32_t sy, yb, yid;
+    bool mine = partner_at(g, kind, x, sx, p0 + l, je, sy, yb, yid);
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     if (sliced && mine) {
         const int32_t b = lower_idx(lists + yb, sy, lo);
@@ -582,18 +606,23 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     if (m == 0) return 0u;
     uint8_t *marker = reinterpret_cast<uint8_t *>(scr);
     int2 *pinfo = reinterpret_cast<int2 *>(scr + 16 * kPer);
+    int32_t *pyid = scr + kScratchInts;   // kIds only
     const int32_t len = mine ? sy : 0;
     const int32_t incl = wave_incl_scan(len);
     const int32_t start = incl - len;
     const int32_t total = __shfl(incl, kWave - 1, kWave);
-    if (mine) pinfo[__popcll(m & ((1ull << l) - 1))] = make_int2(start, yb);
+    if (mine) {
+        const int r = __popcll(m & ((1ull << l) - 1));
+        pinfo[r] = make_int2(start, yb);
+        if constexpr (kIds) pyid[r] = yid;
+    }
     const uint64_t le = (l == kWave - 1) ? ~0ull : ((2ull << l) - 1);
     int32_t before = 0;   // lists that start before the current window
     constexpr int32_t kStep = kPer * kWave;
     // loads of the window at `base`: lane l takes elements base + 64u + l;
     // slots past the end read element 0 of the list array and are masked
     // when consumed, so the loads need no branch and stay in flight
-    auto gather = [&](int32_t base, int32_t (&v)[kPer]) {
+    auto gather = [&](int32_t base, int32_t (&v)[kPer], int32_t (&ys)[kPer]) {
         const int32_t o = start - base;
         const bool mark = mine && o >= 0 && o < kStep;
         const int mslot = (o & 63) * kPer + (o >> 6);
@@ -615,6 +644,10 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
         int2 pi[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) pi[u] = pinfo[k[u]];
+        if constexpr (kIds) {
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) ys[u] = pyid[k[u]];
+        }
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int32_t f = min(base + u * kWave + l, total - 1);
@@ -631,16 +664,21 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     // addresses) so that every iteration has the same loads in flight and the
     // wait before the lookups covers only this window's loads.
     uint32_t hits = 0;
-    int32_t va[kPer];
-    gather(0, va);
+    int32_t va[kPer], ya[kPer];
+    gather(0, va, ya);
     for (int32_t base = 0;; base += kStep) {
-        int32_t vb[kPer];
-        gather(base + kStep, vb);
+        int32_t vb[kPer], yb2[kPer];
+        gather(base + kStep, vb, yb2);
         masked(base, va);
-        hits += count(va);
+        if constexpr (kIds) hits += count(va, ya);
+        else hits += count(va);
         if (base + kStep >= total) break;
 #pragma unroll
         for (int u = 0; u < kPer; ++u) va[u] = vb[u];
+        if constexpr (kIds) {
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) ya[u] = yb2[u];
+        }
     }
     wave_lds_sync();   // pinfo is rewritten by the next batch
     return hits;
@@ -648,19 +686,25 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
 
 // Merge strategy for a small owner, one lane per item: the lane walks the
 // item's partners and merges each owned partner list (never longer than the
-// owner's) with the owner list.  Hits of this lane.
-__device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, int32_t x, int32_t jb, int32_t je) {
+// owner's) with the owner list.  Hits of this lane; in vertex mode every
+// common neighbour w and the partner get their triangles (the owner's are
+// added by the caller).
+template <int kMode>
+__device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, int32_t x, int32_t jb, int32_t je,
+                                                    const Sink &sk) {
     const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
     const int32_t sx = list_size(kind, g.up0, g.rp1, x);
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     uint32_t hits = 0;
     for (int32_t p = jb; p < je; ++p) {
-        int32_t sy, yb;
-        if (!partner_at(g, kind, x, sx, p, je, sy, yb)) continue;   // owned: sx >= sy >= 1
+        int32_t sy, yb, y;
+        if (!partner_at(g, kind, x, sx, p, je, sy, yb, y)) continue;   // owned: sx >= sy >= 1
         const int32_t *b = lists + yb;
         int32_t i = 0, j = 0, ai = a[0], bj = b[0];
+        const uint32_t h0 = hits;
         for (;;) {
             if (ai == bj) {
+                if constexpr (kMode == kModeVertex) atomicAdd(&sk.tv[ai], 1ull);
                 ++hits;
                 if (++i >= sx || ++j >= sy) break;
                 ai = a[i];
@@ -673,24 +717,85 @@ __device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, in
                 bj = b[j];
             }
         }
+        if constexpr (kMode == kModeVertex)
+            if (hits != h0) atomicAdd(&sk.tv[y], (unsigned long long)(hits - h0));
     }
     return hits;
 }
 
 // Merge strategy: partners one at a time, each merged against the owner list.
+template <int kMode>
 __device__ __forceinline__ uint32_t merge_chunk(const Graph &g, int kind, int32_t x, int32_t sx, const int32_t *a,
-                                                int32_t p0, int32_t je) {
-    int32_t sy, yb;
-    const bool mine = partner_at(g, kind, x, sx, p0 + lane_id(), je, sy, yb);
+                                                int32_t p0, int32_t je, const Sink &sk) {
+    int32_t sy, yb, yid;
+    const bool mine = partner_at(g, kind, x, sx, p0 + lane_id(), je, sy, yb, yid);
     uint64_t m = __ballot(mine);
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     uint32_t hits = 0;
     while (m) {
         const int src = __ffsll((unsigned long long)m) - 1;
         m &= m - 1;
-        hits += merge_count(a, sx, lists + __shfl(yb, src, kWave), __shfl(sy, src, kWave));
+        if constexpr (kMode == kModeVertex) {
+            const uint32_t h = merge_count(a, sx, lists + __shfl(yb, src, kWave), __shfl(sy, src, kWave),
+                                           [&](int32_t w) { atomicAdd(&sk.tv[w], 1ull); });
+            const int32_t y = __shfl(yid, src, kWave);
+            if (h) atomicAdd(&sk.tv[y], (unsigned long long)h);
+            hits += h;
+        } else {
+            hits += merge_count(a, sx, lists + __shfl(yb, src, kWave), __shfl(sy, src, kWave), [](int32_t) {});
+        }
     }
     return hits;
+}
+
+// The lookups of one window: plain modes count the keys found; vertex mode
+// takes their mask and adds the triangle to the common neighbour w and the
+// partner y of every key found.
+struct HashProbe {
+    HashTab t;
+    template <bool kMask> __device__ __forceinline__ uint32_t run(const int32_t (&q)[4]) const {
+        return hash_count<4, kMask>(t, q);
+    }
+};
+struct SearchProbe {
+    const int32_t *a;
+    int32_t len;
+    template <bool kMask> __device__ __forceinline__ uint32_t run(const int32_t (&q)[4]) const {
+        return search_count<4, kMask>(a, len, q);
+    }
+};
+template <class Probe> struct WindowCount {
+    Probe p;
+    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer]) const {
+        return in_fours(v, [&](const int32_t(&q)[4]) { return p.template run<false>(q); });
+    }
+};
+template <class Probe> struct WindowVertex {
+    Probe p;
+    unsigned long long *tv;
+    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&y)[kPer]) const {
+        const int32_t a[4] = {v[0], v[1], v[2], v[3]};
+        const int32_t b[4] = {v[4], v[5], v[6], v[7]};
+        const uint32_t mk = p.template run<true>(a) | (p.template run<true>(b) << 4);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if ((mk >> u) & 1u) {
+                atomicAdd(&tv[v[u]], 1ull);
+                atomicAdd(&tv[y[u]], 1ull);
+            }
+        return (uint32_t)__popc(mk);
+    }
+};
+
+// One chunk of owned partners through a lookup structure, in the kernel's mode.
+template <int kMode, class Probe>
+__device__ __forceinline__ uint32_t probe_chunk(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p0,
+                                                int32_t je, int32_t *scr, const Probe &pr, const Sink &sk,
+                                                bool sliced = false, int32_t lo = 0, int32_t hi = 0) {
+    if constexpr (kMode == kModeVertex)
+        return stream_chunk<true>(g, kind, x, sx, p0, je, scr, WindowVertex<Probe>{pr, sk.tv}, sliced, lo, hi);
+    else
+        return stream_chunk<false>(g, kind, x, sx, p0, je, scr, WindowCount<Probe>{pr}, sliced, lo, hi);
 }
 
 // Table size for sx keys: load at most 1/8 where the space allows (probe
@@ -702,28 +807,25 @@ __device__ __forceinline__ int table_log2(int32_t sx, int max_log2) {
     return lg;
 }
 
-// Per-graph counts of a batch: the graph of every vertex and one counter
-// per graph.
-struct Batch {
-    const int32_t *gid;
-    unsigned long long *counts;
-};
-
 // kProf adds the profile: per (bucket, strategy) the wavefront-ticks of the
 // items (elapsed constant-clock ticks times the wavefronts an item occupies)
 // and the item count, accumulated into prof[(b * 4 + s) * 3 + {0, 2}].
-// kBatch adds each item's hits to the counter of the owner's graph.
-template <bool kProf, bool kBatch>
+// kMode: kModeBatch adds each item's hits to the counter of the owner's
+// graph; kModeVertex adds every triangle to its three vertices (the owner's
+// share once per item).
+template <bool kProf, int kMode>
 __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__restrict__ items,
                                                           int32_t *__restrict__ q, int wg_log2, int wave_log2,
                                                           int table_ints, unsigned long long *__restrict__ tri,
-                                                          unsigned long long *__restrict__ prof, Batch bt) {
+                                                          unsigned long long *__restrict__ prof, Sink sk) {
     extern __shared__ int32_t lds[];
     __shared__ int32_t s_item, s_chunk;
     const int32_t n_wg = q[2], n_all = q[3];
+    constexpr bool kBatch = kMode == kModeBatch;
+    constexpr int kScr = kMode == kModeVertex ? kScratchIdsInts : kScratchInts;
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
-    int32_t *scr = lds + table_ints + w * kScratchInts;
+    int32_t *scr = lds + table_ints + w * kScr;
     reinterpret_cast<uint64_t *>(scr)[l] = 0ull;   // markers start clear
     uint64_t acc0 = 0, acc1 = 0;
 
@@ -761,15 +863,12 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             if (l == 0) c = atomicAdd(&s_chunk, 1);
             const int32_t p0 = item.jb + __shfl(c, 0, kWave) * kWave;
             if (p0 >= item.je) break;
-            h += stream_chunk(g, kind, x, sx, p0, item.je, scr,
-                              [&](const int32_t(&v)[kPer]) {
-                                  return in_fours(v, [&](const int32_t(&q)[4]) { return hash_count<4>(ht, q); });
-                              }, sliced, lo, hi);
+            h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr, HashProbe{ht}, sk, sliced, lo, hi);
         }
         if (kind == 0) acc0 += h; else acc1 += h;
-        if (kBatch) {
+        if (kMode != kModePlain) {
             const unsigned long long hs = wave_sum((unsigned long long)h);
-            if (l == 0 && hs) atomicAdd(&bt.counts[bt.gid[x]], hs);
+            if (l == 0 && hs) atomicAdd(kBatch ? &sk.counts[sk.gid[x]] : &sk.tv[x], hs);
         }
         __syncthreads();   // the table, s_item and s_chunk are reused by the next item
         if (kProf && threadIdx.x == 0) {
@@ -803,24 +902,18 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             for (int i = l; i < sx; i += kWave) hash_insert(ht, a[i]);
             wave_lds_sync();
             for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave)
-                h += stream_chunk(g, kind, x, sx, p0, item.je, scr,
-                                  [&](const int32_t(&v)[kPer]) {
-                                  return in_fours(v, [&](const int32_t(&q)[4]) { return hash_count<4>(ht, q); });
-                              });
+                h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr, HashProbe{ht}, sk);
             wave_lds_sync();   // lookups done before the next item clears the table
         } else if (strat == TC_STRAT_MERGE) {
-            for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave) h += merge_chunk(g, kind, x, sx, a, p0, item.je);
+            for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave) h += merge_chunk<kMode>(g, kind, x, sx, a, p0, item.je, sk);
         } else {
             for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave)
-                h += stream_chunk(g, kind, x, sx, p0, item.je, scr,
-                                  [&](const int32_t(&v)[kPer]) {
-                                  return in_fours(v, [&](const int32_t(&q)[4]) { return search_count<4>(a, sx, q); });
-                              });
+                h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr, SearchProbe{a, sx}, sk);
         }
         if (kind == 0) acc0 += h; else acc1 += h;
-        if (kBatch) {
+        if (kMode != kModePlain) {
             const unsigned long long hs = wave_sum((unsigned long long)h);
-            if (l == 0 && hs) atomicAdd(&bt.counts[bt.gid[x]], hs);
+            if (l == 0 && hs) atomicAdd(kBatch ? &sk.counts[sk.gid[x]] : &sk.tv[x], hs);
         }
         if (kProf && l == 0) {
             unsigned long long *pr = prof + (((item.code >> 3) & (kBuckets - 1)) * TC_NUM_STRATEGIES + strat) * 3;
@@ -838,9 +931,10 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             const Item item = items[it];
             const int kind = item.code & 1;
             code = item.code;
-            const uint32_t h = lane_merge_item(g, kind, item.owner, item.jb, item.je);
+            const uint32_t h = lane_merge_item<kMode>(g, kind, item.owner, item.jb, item.je, sk);
             if (kind == 0) acc0 += h; else acc1 += h;
-            if (kBatch && h) atomicAdd(&bt.counts[bt.gid[item.owner]], (unsigned long long)h);
+            if (kMode != kModePlain && h)
+                atomicAdd(kBatch ? &sk.counts[sk.gid[item.owner]] : &sk.tv[item.owner], (unsigned long long)h);
         }
         if (kProf) {   // the group holds the wavefront until its slowest lane ends: 1/64 of that per item
             const uint64_t t_group = wall_clock64() - t_beg;
@@ -963,6 +1057,7 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     TC_HIP_TRY(hipMemsetAsync(L.bucket_cur, 0, sizeof(int32_t) * kBuckets, s));
     TC_HIP_TRY(hipMemsetAsync(L.q, 0, sizeof(int32_t) * 64, s));
     TC_HIP_TRY(hipMemsetAsync(L.stats, 0, sizeof(unsigned long long) * 16, s));
+    if (cfg.tv && n > 0) TC_HIP_TRY(hipMemsetAsync(cfg.tv, 0, sizeof(unsigned long long) * (size_t)n, s));
     const unsigned gp = (unsigned)di.cus * 8;
     if (n > 0) {
         hipLaunchKernelGGL(k_own, dim3(gp), dim3(kThreads), 0, s, n, pb.e0x2, pb.rp0, pb.c0, pb.up0, pb.rp1, pb.vrec, L.cnt,
@@ -982,10 +1077,16 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     if (n > 0) {
         int table_ints = 1 << wg_log2;
         if ((kIsectWaves << wave_log2) > table_ints) table_ints = kIsectWaves << wave_log2;
-        const size_t lds_bytes = (size_t)(table_ints + kIsectWaves * kScratchInts) * sizeof(int32_t);
         const bool batch = cfg.gid != nullptr;
-        const void *kern = cfg.prof ? (batch ? (const void *)k_isect<true, true> : (const void *)k_isect<true, false>)
-                                    : (batch ? (const void *)k_isect<false, true> : (const void *)k_isect<false, false>);
+        const bool vertex = cfg.tv != nullptr;
+        if (vertex && (batch || cfg.prof)) return TC_ERR_ARG;
+        const size_t lds_bytes =
+            (size_t)(table_ints + kIsectWaves * (vertex ? kScratchIdsInts : kScratchInts)) * sizeof(int32_t);
+        const void *kern = cfg.prof ? (batch ? (const void *)k_isect<true, kModeBatch>
+                                             : (const void *)k_isect<true, kModePlain>)
+                                    : vertex ? (const void *)k_isect<false, kModeVertex>
+                                    : batch  ? (const void *)k_isect<false, kModeBatch>
+                                             : (const void *)k_isect<false, kModePlain>;
         TC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
         int per_cu = 1;
         TC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kIsectThreads, lds_bytes));
@@ -993,19 +1094,22 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         if (getenv("TC_LOG")) fprintf(stderr, "libtc: k_isect %d blocks/CU, %zu B LDS\n", per_cu, lds_bytes);
         const unsigned gi = cfg.grid_blocks > 0 ? (unsigned)cfg.grid_blocks : (unsigned)(di.cus * per_cu);
         Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1, pb.vrec};
-        const Batch bt{cfg.gid, cfg.batch_counts};
+        const Sink sk{cfg.gid, cfg.batch_counts, cfg.tv};
         if (cfg.prof && batch)
-            hipLaunchKernelGGL((k_isect<true, true>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items, L.q,
-                               wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof, bt);
+            hipLaunchKernelGGL((k_isect<true, kModeBatch>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
+                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof, sk);
         else if (cfg.prof)
-            hipLaunchKernelGGL((k_isect<true, false>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
-                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof, bt);
+            hipLaunchKernelGGL((k_isect<true, kModePlain>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
+                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof, sk);
+        else if (vertex)
+            hipLaunchKernelGGL((k_isect<false, kModeVertex>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
+                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
         else if (batch)
-            hipLaunchKernelGGL((k_isect<false, true>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
-                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, bt);
+            hipLaunchKernelGGL((k_isect<false, kModeBatch>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
+                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
         else
-            hipLaunchKernelGGL((k_isect<false, false>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
-                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, bt);
+            hipLaunchKernelGGL((k_isect<false, kModePlain>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
+                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
         TC_HIP_TRY(hipGetLastError());
     }
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev[2], s));

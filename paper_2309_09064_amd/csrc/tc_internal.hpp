@@ -193,6 +193,7 @@ struct CountCfg {
     unsigned long long *prof = nullptr;   // device per-(bucket, strategy) profile, or NULL
     const int32_t *gid = nullptr;         // batch: graph of every vertex, or NULL
     unsigned long long *batch_counts = nullptr;   // batch: one count per graph (zeroed by the caller)
+    unsigned long long *tv = nullptr;   // per-vertex triangle counts, n entries (zeroed by count_run), or NULL
     bool timing = false;
 };
 // Checked options -> configuration (TC_ERR_ARG for invalid options).

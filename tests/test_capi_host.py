@@ -181,3 +181,11 @@ def test_batch_needs_counts_buffer(lib):
     assert lib.tc_count_batched_ws(2, 10, 20, None, ctypes.byref(sz)) == _capi.TC_OK
     assert lib.tc_count_ws(10, 20, None, ctypes.byref(sz1)) == _capi.TC_OK
     assert sz.value > sz1.value
+
+
+def test_vertex_triangles_needs_an_output_before_device(lib):
+    fake = ctypes.c_void_p(0x1000)
+    T = lib.tc_vertex_triangles(10, 20, fake, fake, None, None, None, None, fake, 1 << 30, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_ARG
+    T = lib.tc_vertex_triangles(10, 20, fake, fake, None, None, fake, None, fake, 16, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_WORKSPACE

@@ -305,3 +305,56 @@ def test_partition_definition(kron12):
         assert p.up0[x] == above.sum()
         assert np.array_equal(p.c1[p.rp1[x]:p.rp1[x + 1]], nb[lev[nb] != lev[x]])
     assert p.rp0[-1] == 2 * oracle.alg4(g, lev).E0
+
+
+# ------------------------------------------------------------ per-vertex counts
+
+def _both_vertex(g, vs=None):
+    """Whole-graph t(v) and the sampled routine's t(v) over every vertex."""
+    tv = oracle.vertex_triangles(g)
+    at = oracle.vertex_triangles_at(g, np.arange(g.n) if vs is None else vs)
+    assert np.array_equal(at, tv if vs is None else tv[vs])
+    return tv.astype(np.int64)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 12])
+def test_vertex_triangles_complete(n):
+    assert np.all(_both_vertex(complete(n)) == choose(n - 1, 2))
+
+
+@pytest.mark.parametrize("n", [5, 9, 14])
+def test_vertex_triangles_wheel(n):
+    tv = _both_vertex(wheel(n))
+    assert tv[0] == n - 1 and np.all(tv[1:] == 2)
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_vertex_triangles_friendship_and_book(k):
+    tv = _both_vertex(friendship(k))
+    assert tv[0] == k and np.all(tv[1:] == 1)
+    tv = _both_vertex(book(k))
+    assert tv[0] == tv[1] == k and np.all(tv[2:] == 1)
+
+
+def test_vertex_triangles_bipartite_and_empty():
+    assert np.all(_both_vertex(complete_bipartite(4, 6)) == 0)
+    assert _both_vertex(csr_from_edges(3, [])).tolist() == [0, 0, 0]
+
+
+@pytest.mark.parametrize("n,p,seed", [(80, 0.2, 1), (150, 0.1, 2), (60, 0.6, 3)])
+def test_vertex_triangles_diag_a_cubed(n, p, seed):
+    # (A^3)[v, v] counts closed walks of length 3 through v: 2 t(v)
+    g = gnp(n, p, seed)
+    A = dense(g).astype(np.int64)
+    tv = _both_vertex(g)
+    assert np.array_equal(2 * tv, np.diag(A @ A @ A))
+
+
+def test_vertex_triangles_sampled_kronecker():
+    n, s, d = graphgen.kronecker(12, seed=5)
+    g = oracle.build_csr(n, s, d)
+    vs = np.random.default_rng(1).choice(n, 300, replace=False)
+    tv = _both_vertex(g, vs)
+    assert int(oracle.vertex_triangles(g).sum()) == 3 * oracle.count_emd(g)
+    with pytest.raises(ValueError):
+        oracle.vertex_triangles_at(g, [n])
