@@ -179,6 +179,23 @@ def main():
     forward_hashed = {"value": m / fstep_s, "ms_per_step": fstep_s * 1e3, "phase_ms": phase_means(fres)}
     print(f"# forward-hashed (L = 0): {fstep_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # context: the per-vertex and per-edge modes of the same pass (triangles
+    # through every vertex / every edge; whole pipeline, output allocation
+    # included)
+    local = {}
+    for name, fn in (("vertex_triangles", tc.vertex_triangles), ("edge_support", tc.edge_support)):
+        for _ in range(max(args.warmup, 1)):
+            fn(rp, col)
+        torch.cuda.synchronize()
+        t_x0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, rx = fn(rp, col)
+        torch.cuda.synchronize()
+        x_s = (time.perf_counter() - t_x0) / args.steps
+        assert rx.T == T, f"{name} count differs"
+        local[name] = {"value": m / x_s, "ms_per_step": x_s * 1e3}
+        print(f"# {name}: {x_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+
     learned = None
     if not args.no_learned:
         # learned schedule: profile this graph under each forced strategy,
@@ -239,7 +256,8 @@ def main():
                    "n": n, "m": m, "triangles": T, "T0": r.T0, "T1": r.T1, "e0": r.e0,
                    "k_percent": round(100.0 * r.e0 / m, 2), "levels": r.levels, "counts_bit_exact": exact,
                    "phase_ms": ms, "items": r.items, "strategy_items": r.strategy_items,
-                   "learned_schedule": learned, "forward_hashed_same_kernels": forward_hashed},
+                   "learned_schedule": learned, "forward_hashed_same_kernels": forward_hashed,
+                   "per_vertex_and_edge": local},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_isect",
                      "bytes_per_launch": balg, "ms_per_launch": ms["isect"]},

@@ -279,6 +279,58 @@ uint64_t tc_vertex_triangles(int32_t n, int64_t nnz, const int32_t *d_row_ptr, c
                              const int32_t *d_levels, const tc_options *opt, uint64_t *d_tv, tc_stats *stats,
                              void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Per-edge triangle counts (support): for every input entry e = (u, v),
+ * d_sup[e] = the number of triangles containing the edge {u, v}, the same at
+ * both entries of an edge (the k-truss input; applications named in the
+ * paper's Introduction).  Each triangle, found once by Algorithm 4, adds 1 to
+ * its three edges, so the entries sum to 6T.
+ *   d_sup  device uint32[nnz], output, written in full (zeroed by the call);
+ *          indexed like d_col_idx
+ * The workspace is larger than tc_count's (two int32 maps of nnz entries from
+ * the partitioned lists back to input entries): size it with
+ * tc_edge_support_ws.  The hash tables carry the input entry of each key
+ * beside it, so wave_slots and wg_slots are capped at 1024 and 16384 here.
+ * The rows must be symmetric (every (u, v) has its (v, u)); TC_VALIDATE
+ * checks this.  Returns T or TC_COUNT_ERROR.  Synchronises.
+ */
+int tc_edge_support_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_bytes);
+uint64_t tc_edge_support(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                         const int32_t *d_levels, const tc_options *opt, uint32_t *d_sup, tc_stats *stats,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Cover-edge count (Algorithm 3, CE; after tc_relabel_degree, CED): for every
+ * horizontal edge uv, u < v, every common neighbour w of the full rows N(u)
+ * and N(v) counts when L(w) != L(u), or L(w) = L(u) and w > v.  The same
+ * kernels as tc_count, run over full rows instead of the N0+ / N1 split: the
+ * single-pass form of the method that Algorithm 4 refines.  Arguments,
+ * workspace (tc_count_ws) and return value as for tc_count; stats->T0 is 0
+ * and stats->T1 = T.  Synchronises.
+ */
+uint64_t tc_count_cover_edge(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                             const int32_t *d_levels, const tc_options *opt, tc_stats *stats, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ degree relabel */
+
+/*
+ * Degree ordering of the vertices (Section III, last paragraph; the BaderD
+ * and CED variants of the experiments): new id i is the vertex with the i-th
+ * largest degree, ties by increasing old id.  Writes the relabelled CSR
+ * (sorted rows) and the permutation.
+ *   d_out_row_ptr  int32[n+1] device, output
+ *   d_out_col_idx  int32[nnz] device, output (must not alias d_col_idx)
+ *   d_perm         int32[n] device, output: d_perm[new id] = old id
+ * Needs tc_relabel_degree_ws bytes of workspace.  Asynchronous on `stream`
+ * (argument errors are reported before any work is queued).  T is unchanged
+ * by a relabel; BFS roots, levels and the horizontal share k are not.
+ */
+int tc_relabel_degree_ws(int32_t n, int64_t nnz, size_t *h_ws_bytes);
+int tc_relabel_degree(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                      int32_t *d_out_row_ptr, int32_t *d_out_col_idx, int32_t *d_perm, void *ws, size_t ws_bytes,
+                      void *stream);
+
 /* ------------------------------------------------------------ cost network
  *
  * A small fully connected network predicts, for a bucket, the cost of each

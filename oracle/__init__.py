@@ -16,6 +16,9 @@ Counting" (arXiv 2309.09064):
 * :func:`alg3`               cover-edge count (Alg. 3)
 * :func:`vertex_triangles`   per-vertex triangle counts
 * :func:`vertex_triangles_at`  the same for sampled vertices, by another definition
+* :func:`edge_support`       per-edge triangle counts (k-truss support)
+* :func:`edge_support_at`    the same for sampled entries
+* :func:`relabel_degree`     degree ordering of the vertices (BaderD / CED)
 
 :mod:`oracle.mlp` holds the float64 reference of the scheduler network.
 """
@@ -36,6 +39,7 @@ _lib = None
 _i32 = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
 _i64 = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
 _u64 = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+_u32 = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
 
 
 def build(force: bool = True, opt: str = "-O2") -> str:
@@ -70,6 +74,12 @@ def _load():
         lib.orc_vertex_triangles.restype = None
         lib.orc_vertex_triangles_at.argtypes = [ctypes.c_int64, _i64, _i32, ctypes.c_int64, _i64, _u64]
         lib.orc_vertex_triangles_at.restype = None
+        lib.orc_edge_support.argtypes = [ctypes.c_int64, _i64, _i32, _u32]
+        lib.orc_edge_support.restype = None
+        lib.orc_edge_support_at.argtypes = [ctypes.c_int64, _i64, _i32, ctypes.c_int64, _i64, _u32]
+        lib.orc_edge_support_at.restype = None
+        lib.orc_relabel_degree.argtypes = [ctypes.c_int64, _i64, _i32, _i64, _i32, _i32]
+        lib.orc_relabel_degree.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -200,6 +210,36 @@ def vertex_triangles_at(g: CSR, vertices) -> np.ndarray:
     _load().orc_vertex_triangles_at(g.n, g.row_ptr, _col_or_dummy(g), vs.size, vs if vs.size else np.zeros(1, np.int64),
                                     out)
     return out[:vs.size]
+
+
+def edge_support(g: CSR) -> np.ndarray:
+    """Triangles through the edge of every CSR entry (uint32, nnz entries)."""
+    sup = np.zeros(max(g.nnz, 1), np.uint32)
+    _load().orc_edge_support(g.n, g.row_ptr, _col_or_dummy(g), sup)
+    return sup[:g.nnz]
+
+
+def edge_support_at(g: CSR, entries) -> np.ndarray:
+    """edge_support for the given CSR entries only, one at a time."""
+    es = np.ascontiguousarray(entries, dtype=np.int64)
+    if es.size and (es.min() < 0 or es.max() >= g.nnz):
+        raise ValueError("entry out of range")
+    out = np.zeros(max(es.size, 1), np.uint32)
+    _load().orc_edge_support_at(g.n, g.row_ptr, _col_or_dummy(g), es.size, es if es.size else np.zeros(1, np.int64),
+                                out)
+    return out[:es.size]
+
+
+def relabel_degree(g: CSR):
+    """Degree ordering: returns (relabelled CSR, perm) with perm[new] = old,
+    new ids by decreasing degree, ties by increasing old id."""
+    rp = np.zeros(g.n + 1, np.int64)
+    col = np.zeros(max(g.nnz, 1), np.int32)
+    perm = np.zeros(max(g.n, 1), np.int32)
+    rc = _load().orc_relabel_degree(g.n, g.row_ptr, _col_or_dummy(g), rp, col, perm)
+    if rc != 0:
+        raise MemoryError("oracle relabel")
+    return as_csr(g.n, rp, col[:g.nnz]), perm[:g.n]
 
 
 def _floor_log2(v) -> np.ndarray:

@@ -348,3 +348,96 @@ void orc_vertex_triangles_at(int64_t n, const int64_t *row_ptr, const int32_t *c
         out[i] = twice / 2;
     }
 }
+
+/* ------------------------------------------------ per-edge triangle counts */
+
+/*
+ * Support of every edge (the k-truss input the paper's introduction
+ * motivates): for each input entry e = (u, v), sup[e] = the number of
+ * triangles containing {u, v}, i.e. the common neighbours of u and v,
+ * counted by a sorted merge of the two rows.
+ */
+void orc_edge_support(int64_t n, const int64_t *row_ptr, const int32_t *col, uint32_t *sup)
+{
+    for (int64_t u = 0; u < n; ++u) {
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int64_t v = col[e];
+            int64_t a = row_ptr[u], ae = row_ptr[u + 1], b = row_ptr[v], be = row_ptr[v + 1];
+            uint32_t c = 0;
+            while (a < ae && b < be) {
+                if (col[a] < col[b]) ++a;
+                else if (col[a] > col[b]) ++b;
+                else { ++c; ++a; ++b; }
+            }
+            sup[e] = c;
+        }
+    }
+}
+
+/*
+ * The same for a sample of entries, one at a time: the row u of each entry is
+ * found by binary search in row_ptr, and every member of N(u) is looked up in
+ * N(v) by binary search (cost about deg(u) log deg(v) per entry).
+ */
+void orc_edge_support_at(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t k,
+                         const int64_t *entries, uint32_t *out)
+{
+    for (int64_t i = 0; i < k; ++i) {
+        int64_t e = entries[i];
+        int64_t lo = 0, hi = n - 1;           /* last row u with row_ptr[u] <= e */
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo + 1) / 2;
+            if (row_ptr[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        int64_t u = lo, v = col[e];
+        const int32_t *nv = col + row_ptr[v];
+        int64_t dv = row_ptr[v + 1] - row_ptr[v];
+        uint32_t c = 0;
+        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) c += (uint32_t)in_row(nv, dv, col[j]);
+        out[i] = c;
+    }
+}
+
+/* ------------------------------------------------ degree relabel */
+
+static const int64_t *g_rl_deg;
+
+static int cmp_deg_desc(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    if (g_rl_deg[x] != g_rl_deg[y]) return g_rl_deg[x] > g_rl_deg[y] ? -1 : 1;
+    return (x > y) - (x < y);
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Degree ordering (Section III, last paragraph; BaderD / CED): vertices
+ * sorted by decreasing degree, ties by increasing id; perm[new] = old.  The
+ * relabelled rows are sorted.  Returns 0, or -3 on allocation failure.
+ */
+int orc_relabel_degree(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t *out_rp, int32_t *out_col,
+                       int32_t *perm)
+{
+    int64_t *deg = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *inv = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!deg || !inv) { free(deg); free(inv); return -3; }
+    for (int64_t v = 0; v < n; ++v) { deg[v] = row_ptr[v + 1] - row_ptr[v]; perm[v] = (int32_t)v; }
+    g_rl_deg = deg;
+    qsort(perm, (size_t)n, sizeof(int32_t), cmp_deg_desc);
+    for (int64_t i = 0; i < n; ++i) inv[perm[i]] = (int32_t)i;
+    out_rp[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t v = perm[i], o = out_rp[i];
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) out_col[o + e - row_ptr[v]] = inv[col[e]];
+        qsort(out_col + o, (size_t)deg[v], sizeof(int32_t), cmp_i32);
+        out_rp[i + 1] = o + deg[v];
+    }
+    free(deg);
+    free(inv);
+    return 0;
+}

@@ -18,7 +18,8 @@ from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_BUCKETS, TC_NUM_STRAT
                     TC_STRAT_WG_HASH, TC_TIMING, TC_VALIDATE)
 
 __all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count", "count_profile", "workspace",
-           "count_batched", "pack_csr", "schedule_table", "vertex_triangles",
+           "count_batched", "pack_csr", "schedule_table", "vertex_triangles", "edge_support",
+           "relabel_by_degree", "count_cover_edge",
            "Counter", "CountResult", "new_profile",
            "STRATEGY_NAMES", "TC_STRAT_AUTO", "TC_STRAT_WAVE_HASH", "TC_STRAT_WG_HASH", "TC_STRAT_BSEARCH",
            "TC_STRAT_MERGE", "TC_SCHED_HEURISTIC", "TC_SCHED_TABLE", "TC_NUM_BUCKETS", "TC_NUM_STRATEGIES",
@@ -318,6 +319,71 @@ def vertex_triangles(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Ten
     if T == TC_COUNT_ERROR:
         raise TCError(lib.tc_last_error(), "tc_vertex_triangles")
     return tv[:n], _result(T, st)
+
+
+def edge_support(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor | None = None,
+                 options: Options | None = None, stream=None):
+    """Triangles through every edge, per input entry (tc_edge_support).
+    Returns (sup: int32 tensor of nnz entries viewing the uint32 supports,
+    CountResult)."""
+    _require_i32_cuda(row_ptr, "row_ptr")
+    _require_i32_cuda(col, "col")
+    if levels is not None:
+        _require_i32_cuda(levels, "levels")
+    n, nnz = row_ptr.numel() - 1, col.numel()
+    lib = _capi.load()
+    opt = (options or Options()).to_c()
+    need = ctypes.c_size_t()
+    _check(lib.tc_edge_support_ws(n, nnz, ctypes.byref(opt), ctypes.byref(need)), "tc_edge_support_ws")
+    ws = workspace(need.value, row_ptr.device)
+    sup = torch.empty(max(nnz, 1), dtype=torch.int32, device=row_ptr.device)
+    st = _capi.tc_stats()
+    T = lib.tc_edge_support(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(levels), ctypes.byref(opt), _ptr(sup),
+                            ctypes.byref(st), _ptr(ws), need.value, _stream(stream))
+    if T == TC_COUNT_ERROR:
+        raise TCError(lib.tc_last_error(), "tc_edge_support")
+    return sup[:nnz], _result(T, st)
+
+
+def relabel_by_degree(row_ptr: torch.Tensor, col: torch.Tensor, stream=None):
+    """Degree relabel (tc_relabel_degree).  Returns (row_ptr', col', perm)
+    with perm[new id] = old id; new ids follow decreasing degree, ties by
+    increasing old id."""
+    _require_i32_cuda(row_ptr, "row_ptr")
+    _require_i32_cuda(col, "col")
+    n, nnz = row_ptr.numel() - 1, col.numel()
+    lib = _capi.load()
+    need = ctypes.c_size_t()
+    _check(lib.tc_relabel_degree_ws(n, nnz, ctypes.byref(need)), "tc_relabel_degree_ws")
+    ws = workspace(need.value, row_ptr.device)
+    rp2 = torch.empty(n + 1, dtype=torch.int32, device=row_ptr.device)
+    col2 = torch.empty(max(nnz, 1), dtype=torch.int32, device=row_ptr.device)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=row_ptr.device)
+    _check(lib.tc_relabel_degree(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(rp2), _ptr(col2), _ptr(perm), _ptr(ws),
+                                 need.value, _stream(stream)), "tc_relabel_degree")
+    return rp2, col2[:nnz], perm[:n]
+
+
+def count_cover_edge(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor | None = None,
+                     options: Options | None = None, stream=None) -> CountResult:
+    """Cover-edge count (Algorithm 3) on the same kernels over full rows
+    (tc_count_cover_edge); T0 is 0 and T1 = T in the result."""
+    _require_i32_cuda(row_ptr, "row_ptr")
+    _require_i32_cuda(col, "col")
+    if levels is not None:
+        _require_i32_cuda(levels, "levels")
+    n, nnz = row_ptr.numel() - 1, col.numel()
+    lib = _capi.load()
+    opt = (options or Options()).to_c()
+    need = ctypes.c_size_t()
+    _check(lib.tc_count_ws(n, nnz, ctypes.byref(opt), ctypes.byref(need)), "tc_count_ws")
+    ws = workspace(need.value, row_ptr.device)
+    st = _capi.tc_stats()
+    T = lib.tc_count_cover_edge(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(levels), ctypes.byref(opt),
+                                ctypes.byref(st), _ptr(ws), need.value, _stream(stream))
+    if T == TC_COUNT_ERROR:
+        raise TCError(lib.tc_last_error(), "tc_count_cover_edge")
+    return _result(T, st)
 
 
 def count(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor | None = None,

@@ -97,6 +97,13 @@ _SIGNATURES = {
                                            _vp]),
     "tc_vertex_triangles": (ctypes.c_uint64, [_i32, _i64, _vp, _vp, _vp, _P(tc_options), _vp, _P(tc_stats), _vp,
                                               _sz, _vp]),
+    "tc_edge_support_ws": (ctypes.c_int, [_i32, _i64, _P(tc_options), _P(_sz)]),
+    "tc_edge_support": (ctypes.c_uint64, [_i32, _i64, _vp, _vp, _vp, _P(tc_options), _vp, _P(tc_stats), _vp, _sz,
+                                          _vp]),
+    "tc_relabel_degree_ws": (ctypes.c_int, [_i32, _i64, _P(_sz)]),
+    "tc_relabel_degree": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "tc_count_cover_edge": (ctypes.c_uint64, [_i32, _i64, _vp, _vp, _vp, _P(tc_options), _P(tc_stats), _vp, _sz,
+                                              _vp]),
     "tc_count_batched_ws": (ctypes.c_int, [_i32, _i32, _i64, _P(tc_options), _P(_sz)]),
     "tc_count_batched": (ctypes.c_uint64, [_i32, _vp, _i32, _i64, _vp, _vp, _vp, _P(tc_options), _vp, _P(tc_stats),
                                            _vp, _sz, _vp]),

@@ -235,7 +235,7 @@ struct CountPlan {
     int32_t *flag;
 };
 
-CountPlan carve_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels) {
+CountPlan carve_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels, bool edge_pos = false) {
     CountPlan P;
     const int64_t nn = n > 0 ? n : 1;
     const int64_t nz = nnz > 0 ? nnz : 1;
@@ -252,6 +252,10 @@ CountPlan carve_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels) {
     P.pb.rpu = c.take<int32_t>(nn + 1);
     P.pb.e0x2 = c.take<int64_t>(1);
     P.pb.vrec = c.take<int4>(nn);
+    if (edge_pos) {   // per-edge support: input entry of every c0 / c1 entry
+        P.pb.pos0 = c.take<int32_t>(nz);
+        P.pb.pos1 = c.take<int32_t>(nz);
+    }
     P.flag = c.take<int32_t>(64);
     size_t sb = bfs_ws_bytes(n, nnz);
     size_t t = partition_ws_bytes(n, nnz);
@@ -424,7 +428,7 @@ struct BatchArgs {
 static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                     const int32_t *d_levels, const tc_options *opt, tc_stats *stats, uint64_t *d_prof, void *ws,
                     size_t ws_bytes, void *stream, const BatchArgs *batch = nullptr,
-                    uint64_t *d_tv = nullptr) {
+                    uint64_t *d_tv = nullptr, bool edge = false, uint32_t *d_sup = nullptr, bool cover = false) {
     int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
     if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
     if (batch) {   // offsets: 0 = off[0] <= off[1] <= ... <= off[graphs] = n
@@ -443,10 +447,18 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
     if (cfg.schedule == TC_SCHED_TABLE && !cfg.table) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
     cfg.prof = reinterpret_cast<unsigned long long *>(d_prof);
     cfg.tv = reinterpret_cast<unsigned long long *>(d_tv);
+    if (edge) {
+        // the payload array beside every hash table halves the LDS per table
+        if (cfg.wg_slots > kEdgeMaxWgSlots) cfg.wg_slots = kEdgeMaxWgSlots;
+        if (cfg.wave_slots > kEdgeMaxWaveSlots) cfg.wave_slots = kEdgeMaxWaveSlots;
+        cfg.sup = nnz > 0 ? d_sup : nullptr;   // no entries: nothing to count or write
+        cfg.rp = d_row_ptr;
+        cfg.col = d_col_idx;
+    }
     size_t need = 0;
     {
         Carver c(nullptr, 0);
-        carve_plan(c, n, nnz, true);
+        carve_plan(c, n, nnz, true, edge);
         if (batch) carve_batch(c, batch->graphs, n);
         need = c.used();
     }
@@ -467,7 +479,7 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
         return 0;
     }
     Carver c(ws, ws_bytes);
-    CountPlan P = carve_plan(c, n, nnz, true);
+    CountPlan P = carve_plan(c, n, nnz, true, edge);
     if (flags & TC_VALIDATE) {
         rc = validate_device(n, nnz, d_row_ptr, d_col_idx, d_levels, P.flag, s);
         if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
@@ -519,9 +531,15 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
     if (timing && hipEventRecord(ev[1], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
     rc = partition_run(n, nnz, d_row_ptr, d_col_idx, lev, P.pb, P.scratch, P.scratch_bytes, s);
     if (rc != TC_OK) return fail_ev(rc);
+    PartBufs pb = P.pb;
+    if (cover) {   // Algorithm 3 runs on full rows; the partition only supplies the horizontal edges
+        rc = cover_view_run(n, d_row_ptr, d_col_idx, &pb, s);
+        if (rc != TC_OK) return fail_ev(rc);
+        cfg.cover_lev = lev;
+    }
     if (timing && hipEventRecord(ev[2], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
     CountOut co;
-    rc = count_run(n, nnz, P.pb, cfg, &co, P.scratch, P.scratch_bytes, s);
+    rc = count_run(n, nnz, pb, cfg, &co, P.scratch, P.scratch_bytes, s);
     if (rc != TC_OK) return fail_ev(rc);
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -595,6 +613,58 @@ uint64_t tc_vertex_triangles(int32_t n, int64_t nnz, const int32_t *d_row_ptr, c
     if (!d_tv && n > 0) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
     return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, nullptr,
                       d_tv);
+}
+
+int tc_edge_support_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_bytes) {
+    if (!h_ws_bytes) return fail(TC_ERR_ARG);
+    int rc = check_graph_args(n, nnz, (const void *)1, (const void *)1);
+    if (rc != TC_OK) return fail(rc);
+    CountCfg cfg;
+    int flags;
+    rc = make_cfg(opt, &cfg, &flags);
+    if (rc != TC_OK) return fail(rc);
+    Carver c(nullptr, 0);
+    carve_plan(c, n, nnz, true, true);
+    *h_ws_bytes = c.used();
+    return fail(TC_OK);
+}
+
+uint64_t tc_edge_support(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                         const int32_t *d_levels, const tc_options *opt, uint32_t *d_sup, tc_stats *stats, void *ws,
+                         size_t ws_bytes, void *stream) {
+    if (!d_sup && nnz > 0) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
+    return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, nullptr,
+                      nullptr, true, d_sup);
+}
+
+uint64_t tc_count_cover_edge(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                             const int32_t *d_levels, const tc_options *opt, tc_stats *stats, void *ws,
+                             size_t ws_bytes, void *stream) {
+    return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, nullptr,
+                      nullptr, false, nullptr, true);
+}
+
+int tc_relabel_degree_ws(int32_t n, int64_t nnz, size_t *h_ws_bytes) {
+    if (!h_ws_bytes) return fail(TC_ERR_ARG);
+    int rc = check_graph_args(n, nnz, (const void *)1, (const void *)1);
+    if (rc != TC_OK) return fail(rc);
+    *h_ws_bytes = relabel_ws_bytes(n, nnz);
+    return fail(TC_OK);
+}
+
+int tc_relabel_degree(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                      int32_t *d_out_row_ptr, int32_t *d_out_col_idx, int32_t *d_perm, void *ws, size_t ws_bytes,
+                      void *stream) {
+    int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
+    if (rc != TC_OK) return fail(rc);
+    if (!d_out_row_ptr || (nnz > 0 && !d_out_col_idx) || (n > 0 && !d_perm)) return fail(TC_ERR_ARG);
+    rc = check_ws(ws, ws_bytes, relabel_ws_bytes(n, nnz));
+    if (rc != TC_OK) return fail(rc);
+    DeviceInfo di;
+    rc = device_info(&di);
+    if (rc != TC_OK) return fail(rc);
+    return fail(relabel_run(n, nnz, d_row_ptr, d_col_idx, d_out_row_ptr, d_out_col_idx, d_perm, ws, ws_bytes,
+                            static_cast<hipStream_t>(stream)));
 }
 
 uint64_t tc_count_profile(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,

@@ -358,11 +358,13 @@ struct HashTab {
     int32_t *tab;
     uint32_t bmask;   // buckets - 1
     int shift;        // 32 - log2(buckets)
+    int32_t *pos;     // per-edge counts: a payload per slot (the key's input entry), else unused
 };
 
-__device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots) {
+__device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots, int32_t *pos = nullptr) {
     HashTab t;
     t.tab = tab;
+    t.pos = pos;
     t.bmask = (1u << (lg_slots - 2)) - 1;
     t.shift = 32 - (lg_slots - 2);
     return t;
@@ -390,6 +392,46 @@ __device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
             if (atomicCAS(&t.tab[4 * b + j], kEmpty, v) == kEmpty) return;
         b = (b + 1) & t.bmask;
     }
+}
+
+// Insert with a payload stored beside the key's slot.
+__device__ __forceinline__ void hash_insert_pos(const HashTab &t, int32_t v, int32_t payload) {
+    uint32_t b = home_bucket(t, v);
+    for (;;) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (atomicCAS(&t.tab[4 * b + j], kEmpty, v) == kEmpty) {
+                t.pos[4 * b + j] = payload;
+                return;
+            }
+        b = (b + 1) & t.bmask;
+    }
+}
+
+// Lookup of up to kPer keys returning the mask of keys found and, for each
+// found key, the payload of its slot (per-edge counts only).
+template <int kPer>
+__device__ __forceinline__ uint32_t hash_find(const HashTab &t, const int32_t (&v)[kPer], int32_t (&e)[kPer]) {
+    uint32_t mask = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        e[u] = 0;
+        const int32_t x = v[u];
+        if (x < 0) continue;
+        uint32_t b = home_bucket(t, x);
+        for (;;) {
+            const int4 r = *reinterpret_cast<const int4 *>(&t.tab[4 * b]);
+            const int slot = r.x == x ? 0 : r.y == x ? 1 : r.z == x ? 2 : r.w == x ? 3 : -1;
+            if (slot >= 0) {
+                mask |= 1u << u;
+                e[u] = t.pos[4 * b + slot];
+                break;
+            }
+            if (r.w == kEmpty) break;
+            b = (b + 1) & t.bmask;
+        }
+    }
+    return mask;
 }
 
 // Membership of up to kPer keys (negative = absent slot).  Every key's home
@@ -513,9 +555,28 @@ __device__ __forceinline__ int32_t upper_idx(const int32_t *a, int32_t len, int3
     return lo;
 }
 
+// search_count that also returns, for each key found, apos[index of the key
+// in a] (per-edge counts: the input entry of the owner's edge to the key).
+template <int kPer>
+__device__ __forceinline__ uint32_t search_find(const int32_t *a, const int32_t *apos, int32_t len,
+                                                const int32_t (&v)[kPer], int32_t (&e)[kPer]) {
+    uint32_t mask = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        e[u] = 0;
+        if (v[u] < 0 || len <= 0) continue;
+        const int32_t lb = lower_idx(a, len, v[u]);
+        if (lb < len && a[lb] == v[u]) {
+            mask |= 1u << u;
+            e[u] = apos[lb];
+        }
+    }
+    return mask;
+}
+
 // Wave-parallel merge of sorted a (owner, length la) and b (partner, lb):
 // lane l merges its 1/64 slice of a with the matching value range of b.
-// `on` sees every common value.
+// `on(value, i, j)` sees every common value with its indices in a and b.
 template <class OnHit>
 __device__ __forceinline__ uint32_t merge_count(const int32_t *a, int32_t la, const int32_t *b, int32_t lb, OnHit on) {
     const int l = lane_id();
@@ -529,7 +590,7 @@ __device__ __forceinline__ uint32_t merge_count(const int32_t *a, int32_t la, co
         int32_t x = a[i], y = b[j];
         if (x < y) ++i;
         else if (x > y) ++j;
-        else { on(x); ++hits; ++i; ++j; }
+        else { on(x, i, j); ++hits; ++i; ++j; }
     }
     return hits;
 }
@@ -537,21 +598,25 @@ __device__ __forceinline__ uint32_t merge_count(const int32_t *a, int32_t la, co
 struct Graph {
     const int32_t *rp0, *c0, *up0, *rp1, *c1;
     const int4 *vrec;   // per vertex {rp0, |N0+|, rp1, |N1|}
+    const int32_t *pos0, *pos1;   // per-edge counts: input entry of every c0 / c1 entry
 };
 
 // Elements per lane per window step, and the per-wavefront LDS scratch used
 // to flatten a batch of partner lists: 64 * kPer marker bytes (window offset
 // o lives at byte (o % 64) * kPer + o / 64, so a lane reads its kPer window
 // slots with one load) and 64 partner records {start in the batch, list
-// offset}; with partner ids (per-vertex counts) 64 more ints hold the
-// partner vertex of every record.
+// offset}; with record tags (per-vertex and per-edge counts) 64 more ints
+// hold a tag per record: the partner vertex, or the input entry of the edge
+// owner-partner.
 constexpr int kPer = 8;
 constexpr int kScratchInts = 16 * kPer + 128;
 constexpr int kScratchIdsInts = kScratchInts + 64;
 
 // What the intersection pass produces besides T0 and T1: per-graph counts of
-// a batch, or per-vertex triangle counts.
-enum { kModePlain = 0, kModeBatch = 1, kModeVertex = 2 };
+// a batch, per-vertex triangle counts, or per-edge supports.  kModeCover is
+// the cover-edge count (Algorithm 3) over the full-row view: every common
+// neighbour w of a horizontal edge xy is tested by its level.
+enum { kModePlain = 0, kModeBatch = 1, kModeVertex = 2, kModeEdge = 3, kModeCover = 4 };
 
 // Every hit is one triangle {x, y, w}: owner x, partner y, common neighbour w
 // (each triangle is found exactly once, through its one cover edge xy).
@@ -559,7 +624,18 @@ struct Sink {
     const int32_t *gid;            // batch: graph of every vertex
     unsigned long long *counts;    // batch: one counter per graph
     unsigned long long *tv;        // vertex: triangles through every vertex
+    uint32_t *sup;                 // edge: triangles through every edge, added at one of its two entries
+    const int32_t *lev;            // cover: the BFS levels
 };
+
+// Algorithm 3's test for a common neighbour w of the horizontal edge xy (x
+// at level lx): a triangle is counted from this edge when w is on another
+// level, or on the same level with the larger id of the three (so that a
+// triangle with three horizontal edges is counted from the edge of its two
+// smaller ids only).
+__device__ __forceinline__ bool cover_counts(int32_t lw, int32_t lx, int32_t w, int32_t hi_xy) {
+    return lw != lx || w > hi_xy;
+}
 
 // Partner information for the c0 position p of owner x: is the edge owned
 // for this kind, which vertex is the partner, and where is its list.
@@ -583,10 +659,12 @@ __device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t x, 
 // found from a ballot of the marked list starts in the window and a
 // popcount, O(1) per element.
 // With `sliced`, only the part of each partner list with values in
-// [lo, hi) is streamed (two binary searches per partner).  With kIds every
-// element also carries its partner vertex: `count(v, y)` instead of
-// `count(v)`.
-template <bool kIds, class Count>
+// [lo, hi) is streamed (two binary searches per partner).  kRec selects what
+// else travels with each element: nothing (`count(v)`), the partner vertex
+// (`count(v, y)`), or the input entry of the edge owner-partner and the
+// element's own index in the list array (`count(v, exy, idx)`).
+enum { kRecNone = 0, kRecVertex = 1, kRecEdge = 2 };
+template <int kRec, class Count>
 __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p0,
                                                  int32_t je, int32_t *scr, Count count, bool sliced = false,
                                                  int32_t lo = 0, int32_t hi = 0) {
@@ -606,7 +684,7 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     if (m == 0) return 0u;
     uint8_t *marker = reinterpret_cast<uint8_t *>(scr);
     int2 *pinfo = reinterpret_cast<int2 *>(scr + 16 * kPer);
-    int32_t *pyid = scr + kScratchInts;   // kIds only
+    int32_t *ptag = scr + kScratchInts;   // kRec != kRecNone only
     const int32_t len = mine ? sy : 0;
     const int32_t incl = wave_incl_scan(len);
     const int32_t start = incl - len;
@@ -614,7 +692,8 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     if (mine) {
         const int r = __popcll(m & ((1ull << l) - 1));
         pinfo[r] = make_int2(start, yb);
-        if constexpr (kIds) pyid[r] = yid;
+        if constexpr (kRec == kRecVertex) ptag[r] = yid;
+        if constexpr (kRec == kRecEdge) ptag[r] = g.pos0[p0 + l];   // owned partners sit at c0[p0 + l]
     }
     const uint64_t le = (l == kWave - 1) ? ~0ull : ((2ull << l) - 1);
     int32_t before = 0;   // lists that start before the current window
@@ -622,7 +701,7 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     // loads of the window at `base`: lane l takes elements base + 64u + l;
     // slots past the end read element 0 of the list array and are masked
     // when consumed, so the loads need no branch and stay in flight
-    auto gather = [&](int32_t base, int32_t (&v)[kPer], int32_t (&ys)[kPer]) {
+    auto gather = [&](int32_t base, int32_t (&v)[kPer], int32_t (&ys)[kPer], int32_t (&ix)[kPer]) {
         const int32_t o = start - base;
         const bool mark = mine && o >= 0 && o < kStep;
         const int mslot = (o & 63) * kPer + (o >> 6);
@@ -644,14 +723,16 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
         int2 pi[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) pi[u] = pinfo[k[u]];
-        if constexpr (kIds) {
+        if constexpr (kRec != kRecNone) {
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) ys[u] = pyid[k[u]];
+            for (int u = 0; u < kPer; ++u) ys[u] = ptag[k[u]];
         }
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int32_t f = min(base + u * kWave + l, total - 1);
-            v[u] = lists[pi[u].y + f - pi[u].x];
+            const int32_t at = pi[u].y + f - pi[u].x;
+            v[u] = lists[at];
+            if constexpr (kRec == kRecEdge) ix[u] = at;
         }
     };
     auto masked = [&](int32_t base, int32_t (&v)[kPer]) {
@@ -664,20 +745,25 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     // addresses) so that every iteration has the same loads in flight and the
     // wait before the lookups covers only this window's loads.
     uint32_t hits = 0;
-    int32_t va[kPer], ya[kPer];
-    gather(0, va, ya);
+    int32_t va[kPer], ya[kPer], ia[kPer];
+    gather(0, va, ya, ia);
     for (int32_t base = 0;; base += kStep) {
-        int32_t vb[kPer], yb2[kPer];
-        gather(base + kStep, vb, yb2);
+        int32_t vb[kPer], yb2[kPer], ib[kPer];
+        gather(base + kStep, vb, yb2, ib);
         masked(base, va);
-        if constexpr (kIds) hits += count(va, ya);
+        if constexpr (kRec == kRecEdge) hits += count(va, ya, ia);
+        else if constexpr (kRec == kRecVertex) hits += count(va, ya);
         else hits += count(va);
         if (base + kStep >= total) break;
 #pragma unroll
         for (int u = 0; u < kPer; ++u) va[u] = vb[u];
-        if constexpr (kIds) {
+        if constexpr (kRec != kRecNone) {
 #pragma unroll
             for (int u = 0; u < kPer; ++u) ya[u] = yb2[u];
+        }
+        if constexpr (kRec == kRecEdge) {
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) ia[u] = ib[u];
         }
     }
     wave_lds_sync();   // pinfo is rewritten by the next batch
@@ -688,13 +774,16 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
 // item's partners and merges each owned partner list (never longer than the
 // owner's) with the owner list.  Hits of this lane; in vertex mode every
 // common neighbour w and the partner get their triangles (the owner's are
-// added by the caller).
+// added by the caller), in edge mode the three edges of every triangle.
 template <int kMode>
 __device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, int32_t x, int32_t jb, int32_t je,
                                                     const Sink &sk) {
     const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
     const int32_t sx = list_size(kind, g.up0, g.rp1, x);
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
+    const int32_t *lpos = kind == 0 ? g.pos0 : g.pos1;   // edge mode only
+    const int32_t xb = (int32_t)(a - lists);
+    const int32_t lx = kMode == kModeCover ? sk.lev[x] : 0;
     uint32_t hits = 0;
     for (int32_t p = jb; p < je; ++p) {
         int32_t sy, yb, y;
@@ -702,10 +791,16 @@ __device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, in
         const int32_t *b = lists + yb;
         int32_t i = 0, j = 0, ai = a[0], bj = b[0];
         const uint32_t h0 = hits;
+        const int32_t hi_xy = max(x, y);
         for (;;) {
             if (ai == bj) {
                 if constexpr (kMode == kModeVertex) atomicAdd(&sk.tv[ai], 1ull);
-                ++hits;
+                if constexpr (kMode == kModeEdge) {
+                    atomicAdd(&sk.sup[lpos[xb + i]], 1u);
+                    atomicAdd(&sk.sup[lpos[yb + j]], 1u);
+                }
+                if constexpr (kMode == kModeCover) hits += cover_counts(sk.lev[ai], lx, ai, hi_xy) ? 1u : 0u;
+                else ++hits;
                 if (++i >= sx || ++j >= sy) break;
                 ai = a[i];
                 bj = b[j];
@@ -719,6 +814,8 @@ __device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, in
         }
         if constexpr (kMode == kModeVertex)
             if (hits != h0) atomicAdd(&sk.tv[y], (unsigned long long)(hits - h0));
+        if constexpr (kMode == kModeEdge)
+            if (hits != h0) atomicAdd(&sk.sup[g.pos0[p]], hits - h0);
     }
     return hits;
 }
@@ -737,12 +834,29 @@ __device__ __forceinline__ uint32_t merge_chunk(const Graph &g, int kind, int32_
         m &= m - 1;
         if constexpr (kMode == kModeVertex) {
             const uint32_t h = merge_count(a, sx, lists + __shfl(yb, src, kWave), __shfl(sy, src, kWave),
-                                           [&](int32_t w) { atomicAdd(&sk.tv[w], 1ull); });
+                                           [&](int32_t w, int32_t, int32_t) { atomicAdd(&sk.tv[w], 1ull); });
             const int32_t y = __shfl(yid, src, kWave);
             if (h) atomicAdd(&sk.tv[y], (unsigned long long)h);
             hits += h;
+        } else if constexpr (kMode == kModeEdge) {
+            const int32_t *lpos = kind == 0 ? g.pos0 : g.pos1;
+            const int32_t xb = (int32_t)(a - lists), ybs = __shfl(yb, src, kWave);
+            const uint32_t h = merge_count(a, sx, lists + ybs, __shfl(sy, src, kWave), [&](int32_t, int32_t i, int32_t j) {
+                atomicAdd(&sk.sup[lpos[xb + i]], 1u);
+                atomicAdd(&sk.sup[lpos[ybs + j]], 1u);
+            });
+            if (h) atomicAdd(&sk.sup[g.pos0[p0 + src]], h);
+            hits += h;
+        } else if constexpr (kMode == kModeCover) {
+            const int32_t hi_xy = max(x, __shfl(yid, src, kWave));
+            const int32_t lx = sk.lev[x];
+            uint32_t c = 0;
+            merge_count(a, sx, lists + __shfl(yb, src, kWave), __shfl(sy, src, kWave),
+                        [&](int32_t w, int32_t, int32_t) { c += cover_counts(sk.lev[w], lx, w, hi_xy) ? 1u : 0u; });
+            hits += c;
         } else {
-            hits += merge_count(a, sx, lists + __shfl(yb, src, kWave), __shfl(sy, src, kWave), [](int32_t) {});
+            hits += merge_count(a, sx, lists + __shfl(yb, src, kWave), __shfl(sy, src, kWave),
+                                [](int32_t, int32_t, int32_t) {});
         }
     }
     return hits;
@@ -751,17 +865,26 @@ __device__ __forceinline__ uint32_t merge_chunk(const Graph &g, int kind, int32_
 // The lookups of one window: plain modes count the keys found; vertex mode
 // takes their mask and adds the triangle to the common neighbour w and the
 // partner y of every key found.
+// Edge mode asks `find` for the mask and, per key found, the input entry of
+// the edge owner-key.
 struct HashProbe {
     HashTab t;
     template <bool kMask> __device__ __forceinline__ uint32_t run(const int32_t (&q)[4]) const {
         return hash_count<4, kMask>(t, q);
     }
+    __device__ __forceinline__ uint32_t find(const int32_t (&q)[4], int32_t (&e)[4]) const {
+        return hash_find<4>(t, q, e);
+    }
 };
 struct SearchProbe {
     const int32_t *a;
     int32_t len;
+    const int32_t *apos;   // edge mode: input entry of every owner-list element
     template <bool kMask> __device__ __forceinline__ uint32_t run(const int32_t (&q)[4]) const {
         return search_count<4, kMask>(a, len, q);
+    }
+    __device__ __forceinline__ uint32_t find(const int32_t (&q)[4], int32_t (&e)[4]) const {
+        return search_find<4>(a, apos, len, q, e);
     }
 };
 template <class Probe> struct WindowCount {
@@ -787,15 +910,58 @@ template <class Probe> struct WindowVertex {
     }
 };
 
+template <class Probe> struct WindowEdge {
+    Probe p;
+    uint32_t *sup;
+    const int32_t *lpos;   // input entry of every element of the list array streamed
+    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&exy)[kPer],
+                                                   const int32_t (&idx)[kPer]) const {
+        const int32_t a[4] = {v[0], v[1], v[2], v[3]};
+        const int32_t b[4] = {v[4], v[5], v[6], v[7]};
+        int32_t ea[4], eb[4];
+        const uint32_t mk = p.find(a, ea) | (p.find(b, eb) << 4);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if ((mk >> u) & 1u) {
+                atomicAdd(&sup[u < 4 ? ea[u & 3] : eb[u & 3]], 1u);   // owner - w
+                atomicAdd(&sup[lpos[idx[u]]], 1u);                    // partner - w
+                atomicAdd(&sup[exy[u]], 1u);                          // owner - partner
+            }
+        return (uint32_t)__popc(mk);
+    }
+};
+
+template <class Probe> struct WindowCover {
+    Probe p;
+    const int32_t *lev;
+    int32_t x, lx;
+    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&y)[kPer]) const {
+        const int32_t a[4] = {v[0], v[1], v[2], v[3]};
+        const int32_t b[4] = {v[4], v[5], v[6], v[7]};
+        const uint32_t mk = p.template run<true>(a) | (p.template run<true>(b) << 4);
+        uint32_t c = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if ((mk >> u) & 1u) c += cover_counts(lev[v[u]], lx, v[u], max(x, y[u])) ? 1u : 0u;
+        return c;
+    }
+};
+
 // One chunk of owned partners through a lookup structure, in the kernel's mode.
 template <int kMode, class Probe>
 __device__ __forceinline__ uint32_t probe_chunk(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p0,
                                                 int32_t je, int32_t *scr, const Probe &pr, const Sink &sk,
                                                 bool sliced = false, int32_t lo = 0, int32_t hi = 0) {
     if constexpr (kMode == kModeVertex)
-        return stream_chunk<true>(g, kind, x, sx, p0, je, scr, WindowVertex<Probe>{pr, sk.tv}, sliced, lo, hi);
+        return stream_chunk<kRecVertex>(g, kind, x, sx, p0, je, scr, WindowVertex<Probe>{pr, sk.tv}, sliced, lo, hi);
+    else if constexpr (kMode == kModeCover)
+        return stream_chunk<kRecVertex>(g, kind, x, sx, p0, je, scr, WindowCover<Probe>{pr, sk.lev, x, sk.lev[x]},
+                                        sliced, lo, hi);
+    else if constexpr (kMode == kModeEdge)
+        return stream_chunk<kRecEdge>(g, kind, x, sx, p0, je, scr,
+                                      WindowEdge<Probe>{pr, sk.sup, kind == 0 ? g.pos0 : g.pos1}, sliced, lo, hi);
     else
-        return stream_chunk<false>(g, kind, x, sx, p0, je, scr, WindowCount<Probe>{pr}, sliced, lo, hi);
+        return stream_chunk<kRecNone>(g, kind, x, sx, p0, je, scr, WindowCount<Probe>{pr}, sliced, lo, hi);
 }
 
 // Table size for sx keys: load at most 1/8 where the space allows (probe
@@ -812,7 +978,10 @@ __device__ __forceinline__ int table_log2(int32_t sx, int max_log2) {
 // and the item count, accumulated into prof[(b * 4 + s) * 3 + {0, 2}].
 // kMode: kModeBatch adds each item's hits to the counter of the owner's
 // graph; kModeVertex adds every triangle to its three vertices (the owner's
-// share once per item).
+// share once per item); kModeEdge adds every triangle to its three edges,
+// each at one of the edge's two input entries, and keeps a payload array
+// (the owner-key edge's input entry) beside every hash table, so its LDS
+// holds two table regions.
 template <bool kProf, int kMode>
 __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__restrict__ items,
                                                           int32_t *__restrict__ q, int wg_log2, int wave_log2,
@@ -822,10 +991,12 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
     __shared__ int32_t s_item, s_chunk;
     const int32_t n_wg = q[2], n_all = q[3];
     constexpr bool kBatch = kMode == kModeBatch;
-    constexpr int kScr = kMode == kModeVertex ? kScratchIdsInts : kScratchInts;
+    constexpr bool kEdge = kMode == kModeEdge;
+    constexpr bool kOwnerSink = kMode == kModeBatch || kMode == kModeVertex;
+    constexpr int kScr = kMode == kModeVertex || kMode == kModeCover || kEdge ? kScratchIdsInts : kScratchInts;
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
-    int32_t *scr = lds + table_ints + w * kScr;
+    int32_t *scr = lds + (kEdge ? 2 : 1) * table_ints + w * kScr;
     reinterpret_cast<uint64_t *>(scr)[l] = 0ull;   // markers start clear
     uint64_t acc0 = 0, acc1 = 0;
 
@@ -850,12 +1021,17 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const int32_t lo = sliced ? a[a_lo] : 0;
         const int32_t hi = sliced && a_hi < sx ? a[a_hi] : INT32_MAX;
         const int lg = table_log2(a_hi - a_lo, wg_log2);
-        const HashTab ht = make_tab(lds, lg);
+        const HashTab ht = make_tab(lds, lg, kEdge ? lds + table_ints : nullptr);
         if (threadIdx.x == 0) s_chunk = 0;
         for (int i = threadIdx.x; i < (1 << lg) / 4; i += kIsectThreads)
             reinterpret_cast<int4 *>(lds)[i] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
         __syncthreads();
-        for (int i = a_lo + (int)threadIdx.x; i < a_hi; i += kIsectThreads) hash_insert(ht, a[i]);
+        if constexpr (kEdge) {
+            const int32_t *apos = (kind == 0 ? g.pos0 + g.rp0[x] : g.pos1 + g.rp1[x]);
+            for (int i = a_lo + (int)threadIdx.x; i < a_hi; i += kIsectThreads) hash_insert_pos(ht, a[i], apos[i]);
+        } else {
+            for (int i = a_lo + (int)threadIdx.x; i < a_hi; i += kIsectThreads) hash_insert(ht, a[i]);
+        }
         __syncthreads();
         uint32_t h = 0;
         for (;;) {
@@ -866,7 +1042,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr, HashProbe{ht}, sk, sliced, lo, hi);
         }
         if (kind == 0) acc0 += h; else acc1 += h;
-        if (kMode != kModePlain) {
+        if (kOwnerSink) {
             const unsigned long long hs = wave_sum((unsigned long long)h);
             if (l == 0 && hs) atomicAdd(kBatch ? &sk.counts[sk.gid[x]] : &sk.tv[x], hs);
         }
@@ -895,11 +1071,16 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         uint32_t h = 0;
         if (strat == TC_STRAT_WAVE_HASH) {
             const int lg = table_log2(sx, wave_log2);
-            const HashTab ht = make_tab(tab, lg);
+            const HashTab ht = make_tab(tab, lg, kEdge ? tab + table_ints : nullptr);
             for (int i = l; i < (1 << lg) / 4; i += kWave)
                 reinterpret_cast<int4 *>(tab)[i] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
             wave_lds_sync();
-            for (int i = l; i < sx; i += kWave) hash_insert(ht, a[i]);
+            if constexpr (kEdge) {
+                const int32_t *apos = (kind == 0 ? g.pos0 + g.rp0[x] : g.pos1 + g.rp1[x]);
+                for (int i = l; i < sx; i += kWave) hash_insert_pos(ht, a[i], apos[i]);
+            } else {
+                for (int i = l; i < sx; i += kWave) hash_insert(ht, a[i]);
+            }
             wave_lds_sync();
             for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave)
                 h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr, HashProbe{ht}, sk);
@@ -908,10 +1089,13 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave) h += merge_chunk<kMode>(g, kind, x, sx, a, p0, item.je, sk);
         } else {
             for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave)
-                h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr, SearchProbe{a, sx}, sk);
+                h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr,
+                                        SearchProbe{a, sx, kEdge ? (kind == 0 ? g.pos0 + g.rp0[x] : g.pos1 + g.rp1[x])
+                                                                 : nullptr},
+                                        sk);
         }
         if (kind == 0) acc0 += h; else acc1 += h;
-        if (kMode != kModePlain) {
+        if (kOwnerSink) {
             const unsigned long long hs = wave_sum((unsigned long long)h);
             if (l == 0 && hs) atomicAdd(kBatch ? &sk.counts[sk.gid[x]] : &sk.tv[x], hs);
         }
@@ -933,7 +1117,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             code = item.code;
             const uint32_t h = lane_merge_item<kMode>(g, kind, item.owner, item.jb, item.je, sk);
             if (kind == 0) acc0 += h; else acc1 += h;
-            if (kMode != kModePlain && h)
+            if (kOwnerSink && h)
                 atomicAdd(kBatch ? &sk.counts[sk.gid[item.owner]] : &sk.tv[item.owner], (unsigned long long)h);
         }
         if (kProf) {   // the group holds the wavefront until its slowest lane ends: 1/64 of that per item
@@ -952,6 +1136,50 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
     if (l == 0) {
         if (t0) atomicAdd(&tri[0], (unsigned long long)t0);
         if (t1) atomicAdd(&tri[1], (unsigned long long)t1);
+    }
+}
+
+// Per-edge counts land at either of an edge's two input entries; this pass
+// adds the two and writes the sum to both.  The entry (u, v) with u < v finds
+// its reverse (v, u) by binary search in row v, so each edge is handled by
+// exactly one thread.
+__global__ __launch_bounds__(kThreads) void k_edge_mirror(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ col, uint32_t *__restrict__ sup) {
+    __shared__ int64_t rows[2];
+    constexpr int64_t kTile = (int64_t)kThreads * kRun;
+    for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < nnz; t0 += (int64_t)gridDim.x * kTile) {
+        tile_rows(rp, n, t0, t0 + kTile < nnz ? t0 + kTile : nnz, rows);
+        const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
+        if (e0 < nnz) {
+            const int64_t e1 = e0 + kRun < nnz ? e0 + kRun : nnz;
+            int64_t u = row_of(rp, rows[0], rows[1], e0);
+            int64_t ue = rp[u + 1];
+            for (int64_t e = e0; e < e1; ++e) {
+                while (e >= ue) { ++u; ue = rp[u + 1]; }
+                const int32_t v = col[e];
+                if (v <= u) continue;
+                const int32_t b = rp[v], len = rp[v + 1] - b;
+                const int32_t r = b + lower_idx(col + b, len, (int32_t)u);
+                if (r < b + len && col[r] == (int32_t)u) {
+                    const uint32_t t = sup[e] + sup[r];
+                    sup[e] = t;
+                    sup[r] = t;
+                }
+            }
+        }
+        __syncthreads();   // rows is rewritten by the next tile
+    }
+}
+
+// Full-row view of a partition for the cover-edge count: no N0+ lists (so no
+// kind-0 units) and kind-1 lists that are the whole input rows; the partner
+// rows stay the N0 rows, so every horizontal edge is still offered to the
+// endpoint with the longer list.
+__global__ void k_cover_view(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ rp0,
+                             int32_t *__restrict__ up0, int4 *__restrict__ vrec) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        up0[v] = 0;
+        vrec[v] = make_int4(rp0[v], 0, rp[v], rp[v + 1] - rp[v]);
     }
 }
 
@@ -990,6 +1218,17 @@ CountLayout carve_count(Carver &c, int32_t n, int64_t nnz) {
 }
 
 }  // namespace
+
+int cover_view_run(int32_t n, const int32_t *rp, const int32_t *col, PartBufs *pb, hipStream_t s) {
+    if (n > 0) {
+        hipLaunchKernelGGL(k_cover_view, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, rp, pb->rp0, pb->up0,
+                           pb->vrec);
+        TC_HIP_TRY(hipGetLastError());
+    }
+    pb->rp1 = const_cast<int32_t *>(rp);    // read only from here on
+    pb->c1 = const_cast<int32_t *>(col);
+    return TC_OK;
+}
 
 size_t count_ws_bytes(int32_t n, int64_t nnz) {
     Carver c(nullptr, 0);
@@ -1058,6 +1297,7 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     TC_HIP_TRY(hipMemsetAsync(L.q, 0, sizeof(int32_t) * 64, s));
     TC_HIP_TRY(hipMemsetAsync(L.stats, 0, sizeof(unsigned long long) * 16, s));
     if (cfg.tv && n > 0) TC_HIP_TRY(hipMemsetAsync(cfg.tv, 0, sizeof(unsigned long long) * (size_t)n, s));
+    if (cfg.sup && nnz > 0) TC_HIP_TRY(hipMemsetAsync(cfg.sup, 0, sizeof(uint32_t) * (size_t)nnz, s));
     const unsigned gp = (unsigned)di.cus * 8;
     if (n > 0) {
         hipLaunchKernelGGL(k_own, dim3(gp), dim3(kThreads), 0, s, n, pb.e0x2, pb.rp0, pb.c0, pb.up0, pb.rp1, pb.vrec, L.cnt,
@@ -1079,12 +1319,19 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         if ((kIsectWaves << wave_log2) > table_ints) table_ints = kIsectWaves << wave_log2;
         const bool batch = cfg.gid != nullptr;
         const bool vertex = cfg.tv != nullptr;
-        if (vertex && (batch || cfg.prof)) return TC_ERR_ARG;
-        const size_t lds_bytes =
-            (size_t)(table_ints + kIsectWaves * (vertex ? kScratchIdsInts : kScratchInts)) * sizeof(int32_t);
+        const bool edge = cfg.sup != nullptr;
+        const bool cover = cfg.cover_lev != nullptr;
+        if ((vertex || edge || cover) && (batch || cfg.prof)) return TC_ERR_ARG;
+        if ((int)vertex + (int)edge + (int)cover > 1) return TC_ERR_ARG;
+        if (edge && (!pb.pos0 || !pb.pos1 || !cfg.rp || !cfg.col)) return TC_ERR_ARG;
+        const size_t lds_bytes = (size_t)((edge ? 2 : 1) * table_ints +
+                                          kIsectWaves * (vertex || edge || cover ? kScratchIdsInts : kScratchInts)) *
+                                 sizeof(int32_t);
         const void *kern = cfg.prof ? (batch ? (const void *)k_isect<true, kModeBatch>
                                              : (const void *)k_isect<true, kModePlain>)
                                     : vertex ? (const void *)k_isect<false, kModeVertex>
+                                    : edge   ? (const void *)k_isect<false, kModeEdge>
+                                    : cover  ? (const void *)k_isect<false, kModeCover>
                                     : batch  ? (const void *)k_isect<false, kModeBatch>
                                              : (const void *)k_isect<false, kModePlain>;
         TC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
@@ -1093,8 +1340,8 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         if (per_cu < 1) per_cu = 1;
         if (getenv("TC_LOG")) fprintf(stderr, "libtc: k_isect %d blocks/CU, %zu B LDS\n", per_cu, lds_bytes);
         const unsigned gi = cfg.grid_blocks > 0 ? (unsigned)cfg.grid_blocks : (unsigned)(di.cus * per_cu);
-        Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1, pb.vrec};
-        const Sink sk{cfg.gid, cfg.batch_counts, cfg.tv};
+        Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1, pb.vrec, pb.pos0, pb.pos1};
+        const Sink sk{cfg.gid, cfg.batch_counts, cfg.tv, cfg.sup, cfg.cover_lev};
         if (cfg.prof && batch)
             hipLaunchKernelGGL((k_isect<true, kModeBatch>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
                                L.q, wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof, sk);
@@ -1104,12 +1351,22 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         else if (vertex)
             hipLaunchKernelGGL((k_isect<false, kModeVertex>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
                                L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
+        else if (edge)
+            hipLaunchKernelGGL((k_isect<false, kModeEdge>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
+                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
+        else if (cover)
+            hipLaunchKernelGGL((k_isect<false, kModeCover>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
+                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
         else if (batch)
             hipLaunchKernelGGL((k_isect<false, kModeBatch>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
                                L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
         else
             hipLaunchKernelGGL((k_isect<false, kModePlain>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
                                L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
+        TC_HIP_TRY(hipGetLastError());
+    }
+    if (cfg.sup && nnz > 0) {
+        hipLaunchKernelGGL(k_edge_mirror, dim3(gp), dim3(kThreads), 0, s, n, nnz, cfg.rp, cfg.col, cfg.sup);
         TC_HIP_TRY(hipGetLastError());
     }
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev[2], s));

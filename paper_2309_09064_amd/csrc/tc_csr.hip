@@ -133,29 +133,70 @@ unsigned grid_for(int64_t work, int threads) {
 
 struct CsrLayout {
     uint64_t *ka, *kb;
-    int32_t *hist, *flag, *pos, *deg, *err;
-    void *scan;
+    int32_t *flag, *pos, *deg, *err;
+    void *sort;   // radix sort scratch, also the scans' scratch
+    size_t sort_bytes;
 };
 
 CsrLayout carve_csr(Carver &c, int32_t n, int64_t m) {
     const int64_t nk = 2 * m;
-    const int64_t nblk = (nk + kTileKeys - 1) / kTileKeys;
     CsrLayout L;
     L.ka = c.take<uint64_t>(nk > 0 ? nk : 1);
     L.kb = c.take<uint64_t>(nk > 0 ? nk : 1);
-    L.hist = c.take<int32_t>(256 * nblk + 1);
     L.flag = c.take<int32_t>(nk + 1);
     L.pos = c.take<int32_t>(nk + 1);
     L.deg = c.take<int32_t>((int64_t)n + 1);
     L.err = c.take<int32_t>(64);
-    int64_t biggest = 256 * nblk;
-    if (nk > biggest) biggest = nk;
-    if ((int64_t)n > biggest) biggest = n;
-    L.scan = c.take<char>(scan_ws_bytes(biggest));
+    int64_t biggest = nk > (int64_t)n ? nk : (int64_t)n;
+    L.sort_bytes = radix_sort_ws_bytes(biggest);
+    L.sort = c.take<char>(L.sort_bytes);
+    return L;
+}
+
+struct SortLayout {
+    int32_t *hist;
+    void *scan;
+};
+
+SortLayout carve_sort(Carver &c, int64_t nk) {
+    const int64_t nblk = (nk + kTileKeys - 1) / kTileKeys;
+    SortLayout L;
+    L.hist = c.take<int32_t>(256 * nblk + 1);
+    L.scan = c.take<char>(scan_ws_bytes(256 * nblk > nk ? 256 * nblk : nk));
     return L;
 }
 
 }  // namespace
+
+int bits_for_ids(int64_t n) { return bits_for(n); }
+
+size_t radix_sort_ws_bytes(int64_t nk) {
+    Carver c(nullptr, 0);
+    carve_sort(c, nk);
+    return c.used();
+}
+
+int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t nk, int bits, void *ws, size_t ws_bytes, hipStream_t s,
+                   uint64_t **sorted) {
+    Carver c(ws, ws_bytes);
+    SortLayout L = carve_sort(c, nk);
+    if (!c.fits()) return TC_ERR_WORKSPACE;
+    *sorted = a;
+    if (nk <= 0) return TC_OK;
+    const int64_t nblk = (nk + kTileKeys - 1) / kTileKeys;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, a, nk, shift, L.hist);
+        TC_HIP_TRY(hipGetLastError());
+        TC_TRY(scan_exclusive_i32_to_i32(L.hist, L.hist, 256 * nblk, L.scan, s));
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, a, b, nk, shift, L.hist);
+        TC_HIP_TRY(hipGetLastError());
+        uint64_t *t = a;
+        a = b;
+        b = t;
+    }
+    *sorted = a;
+    return TC_OK;
+}
 
 size_t build_csr_ws_bytes(int32_t n, int64_t m) {
     Carver c(nullptr, 0);
@@ -178,21 +219,11 @@ int build_csr_run(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, 
                            bits_for(n), L.ka, L.err);
         TC_HIP_TRY(hipGetLastError());
         const int bv = bits_for(n);
-        const int bits = 2 * bv;
-        const int64_t nblk = (nk + kTileKeys - 1) / kTileKeys;
-        uint64_t *a = L.ka, *b = L.kb;
-        for (int shift = 0; shift < bits; shift += 8) {
-            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, a, nk, shift, L.hist);
-            TC_HIP_TRY(hipGetLastError());
-            TC_TRY(scan_exclusive_i32_to_i32(L.hist, L.hist, 256 * nblk, L.scan, s));
-            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, a, b, nk, shift,
-                               L.hist);
-            TC_HIP_TRY(hipGetLastError());
-            uint64_t *t = a; a = b; b = t;
-        }
+        uint64_t *a = nullptr;
+        TC_TRY(radix_sort_u64(L.ka, L.kb, nk, 2 * bv, L.sort, L.sort_bytes, s, &a));
         hipLaunchKernelGGL(k_uniq_flags, dim3(grid_for(nk, 256)), dim3(256), 0, s, a, nk, L.flag);
         TC_HIP_TRY(hipGetLastError());
-        TC_TRY(scan_exclusive_i32_to_i32(L.flag, L.pos, nk, L.scan, s));
+        TC_TRY(scan_exclusive_i32_to_i32(L.flag, L.pos, nk, L.sort, s));
         int32_t hv[2] = {0, 0};
         TC_HIP_TRY(hipMemcpyAsync(&hv[0], L.pos + nk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         TC_HIP_TRY(hipMemcpyAsync(&hv[1], L.err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -207,7 +238,7 @@ int build_csr_run(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, 
     } else if (h_nnz) {
         *h_nnz = 0;
     }
-    TC_TRY(scan_exclusive_i32_to_i32(L.deg, row_ptr, n, L.scan, s));
+    TC_TRY(scan_exclusive_i32_to_i32(L.deg, row_ptr, n, L.sort, s));
     TC_HIP_TRY(hipStreamSynchronize(s));
     if (h_nnz) *h_nnz = nnz;
     return TC_OK;

@@ -141,6 +141,20 @@ int scan_exclusive_i64_to_i64(const int64_t *in, int64_t *out, int64_t n, void *
 
 // ------------------------------------------------------------------ phases
 
+// Stable LSD radix sort of nk 64-bit keys on their low `bits` bits, 8 bits a
+// pass, ping-ponging between a and b; *sorted is whichever holds the result.
+// Its scratch (radix_sort_ws_bytes(nk)) also serves any scan of up to nk
+// values.
+size_t radix_sort_ws_bytes(int64_t nk);
+int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t nk, int bits, void *ws, size_t ws_bytes, hipStream_t s,
+                   uint64_t **sorted);
+int bits_for_ids(int64_t n);   // bits for ids 0 .. n-1 (at least 1)
+
+// Degree relabel (decreasing degree, ties by increasing id)
+size_t relabel_ws_bytes(int32_t n, int64_t nnz);
+int relabel_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32_t *out_rp, int32_t *out_col,
+                int32_t *perm, void *ws, size_t ws_bytes, hipStream_t s);
+
 // CSR build
 size_t build_csr_ws_bytes(int32_t n, int64_t m);
 int build_csr_run(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t *row_ptr,
@@ -167,8 +181,12 @@ struct PartBufs {
     int32_t *rpu;                         // n+1: prefix of up0
     int64_t *e0x2;                        // device scalar: 2|E0|
     int4 *vrec = nullptr;                 // n: {rp0, |N0+|, rp1, |N1|} per vertex, or NULL
+    int32_t *pos0 = nullptr, *pos1 = nullptr;   // input entry of every c0 / c1 entry (nnz each), or NULL
 };
 size_t partition_ws_bytes(int32_t n, int64_t nnz);
+// Turns a partition into the full-row view the cover-edge count runs on
+// (up0 zeroed, vrec rewritten, rp1/c1 pointing at the input CSR).
+int cover_view_run(int32_t n, const int32_t *rp, const int32_t *col, PartBufs *pb, hipStream_t s);
 int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, const int32_t *lev,
                   const PartBufs &pb, void *ws, size_t ws_bytes, hipStream_t s);
 
@@ -180,6 +198,11 @@ struct CountOut {
     int32_t strategy_items[TC_NUM_STRATEGIES] = {0, 0, 0, 0};
     float ms_bucket = 0.f, ms_isect = 0.f;
 };
+// Per-edge support keeps a payload array beside every hash table, so its
+// tables get half the LDS: at most these many slots.
+constexpr int kEdgeMaxWgSlots = 16384;
+constexpr int kEdgeMaxWaveSlots = 1024;
+
 struct CountCfg {
     int schedule = TC_SCHED_HEURISTIC;
     int force = TC_STRAT_AUTO;
@@ -194,6 +217,9 @@ struct CountCfg {
     const int32_t *gid = nullptr;         // batch: graph of every vertex, or NULL
     unsigned long long *batch_counts = nullptr;   // batch: one count per graph (zeroed by the caller)
     unsigned long long *tv = nullptr;   // per-vertex triangle counts, n entries (zeroed by count_run), or NULL
+    uint32_t *sup = nullptr;   // per-edge support, one per input entry (zeroed by count_run), or NULL; needs pos0/1
+    const int32_t *rp = nullptr, *col = nullptr;   // the input CSR (per-edge support only)
+    const int32_t *cover_lev = nullptr;   // cover-edge count (over a cover_view_run view): the levels, or NULL
     bool timing = false;
 };
 // Checked options -> configuration (TC_ERR_ARG for invalid options).

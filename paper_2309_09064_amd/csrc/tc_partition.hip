@@ -157,6 +157,9 @@ __global__ void k_part_rp1(int32_t n, const int32_t *__restrict__ rp, const int3
     if (e0x2 && blockIdx.x == 0 && threadIdx.x == 0) *e0x2 = rp0[n];
 }
 
+// kPos also records, for every c0 / c1 entry, the input entry it came from
+// (per-edge counts add to input entries).
+template <bool kPos>
 __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ col,
                                                             const uint8_t *__restrict__ flags,
@@ -164,7 +167,8 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
                                                             const int32_t *__restrict__ bu_off,
                                                             const int32_t *__restrict__ rp0,
                                                             const int32_t *__restrict__ rpu,
-                                                            int32_t *__restrict__ c0, int32_t *__restrict__ c1) {
+                                                            int32_t *__restrict__ c0, int32_t *__restrict__ c1,
+                                                            int32_t *__restrict__ pos0, int32_t *__restrict__ pos1) {
     __shared__ int64_t wsum[kWaves];
     __shared__ int64_t rows[2];
     const int64_t t0 = (int64_t)blockIdx.x * kBlockEntries;
@@ -206,10 +210,12 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
             const uint8_t fe = f[k];
             const int32_t y = col[e];
             if (fe & 1) {
-                if (fe & 2) c0[(int64_t)rp0[x] + U - rpu[x]] = y;
-                else c0[H - U + rpu[x + 1]] = y;
+                const int64_t d = (fe & 2) ? (int64_t)rp0[x] + U - rpu[x] : H - U + rpu[x + 1];
+                c0[d] = y;
+                if (kPos) pos0[d] = (int32_t)e;
             } else {
                 c1[e - H] = y;
+                if (kPos) pos1[e - H] = (int32_t)e;
             }
             H += fe & 1;
             U += fe >> 1;
@@ -277,8 +283,12 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
     if (nnz > 0) {
         TC_TRY(scan_exclusive_i32_to_i32(L.bh, L.bh, nblk, L.scan, s));
         TC_TRY(scan_exclusive_i32_to_i32(L.bu, L.bu, nblk, L.scan, s));
-        hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, L.flags,
-                           L.bh, L.bu, pb.rp0, pb.rpu, pb.c0, pb.c1);
+        if (pb.pos0)
+            hipLaunchKernelGGL(k_part_scatter<true>, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col,
+                               L.flags, L.bh, L.bu, pb.rp0, pb.rpu, pb.c0, pb.c1, pb.pos0, pb.pos1);
+        else
+            hipLaunchKernelGGL(k_part_scatter<false>, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col,
+                               L.flags, L.bh, L.bu, pb.rp0, pb.rpu, pb.c0, pb.c1, nullptr, nullptr);
         TC_HIP_TRY(hipGetLastError());
     }
     return TC_OK;

@@ -189,3 +189,14 @@ def test_vertex_triangles_needs_an_output_before_device(lib):
     assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_ARG
     T = lib.tc_vertex_triangles(10, 20, fake, fake, None, None, fake, None, fake, 16, None)
     assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_WORKSPACE
+
+
+def test_edge_support_needs_an_output_and_its_workspace(lib):
+    fake = ctypes.c_void_p(0x1000)
+    T = lib.tc_edge_support(10, 20, fake, fake, None, None, None, None, fake, 1 << 30, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_ARG
+    rc, plain = size_q(lib.tc_count_ws, 1000, 20000, None)
+    rc2, edge = size_q(lib.tc_edge_support_ws, 1000, 20000, None)
+    assert rc == 0 and rc2 == 0 and edge >= plain + 2 * 4 * 20000
+    T = lib.tc_edge_support(1000, 20000, fake, fake, None, None, fake, None, fake, plain, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_WORKSPACE

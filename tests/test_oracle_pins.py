@@ -358,3 +358,109 @@ def test_vertex_triangles_sampled_kronecker():
     assert int(oracle.vertex_triangles(g).sum()) == 3 * oracle.count_emd(g)
     with pytest.raises(ValueError):
         oracle.vertex_triangles_at(g, [n])
+
+
+# ------------------------------------------------------------ per-edge support
+
+def _both_edge(g):
+    """Whole-graph support and the one-at-a-time routine over every entry."""
+    sup = oracle.edge_support(g)
+    assert np.array_equal(oracle.edge_support_at(g, np.arange(g.nnz)), sup)
+    return sup.astype(np.int64)
+
+
+def _entries(g):
+    return np.repeat(np.arange(g.n), np.diff(g.row_ptr)), g.col.astype(np.int64)
+
+
+@pytest.mark.parametrize("n,p,seed", [(70, 0.2, 4), (120, 0.1, 5), (50, 0.7, 6)])
+def test_edge_support_a_squared(n, p, seed):
+    # (A^2)[u, v] counts the paths u - w - v: the common neighbours
+    g = gnp(n, p, seed)
+    A = dense(g).astype(np.int64)
+    u, v = _entries(g)
+    assert np.array_equal(_both_edge(g), (A @ A)[u, v])
+
+
+@pytest.mark.parametrize("n", [2, 3, 6, 11])
+def test_edge_support_complete(n):
+    assert np.all(_both_edge(complete(n)) == n - 2)
+
+
+@pytest.mark.parametrize("n", [5, 8, 13])
+def test_edge_support_wheel(n):
+    g = wheel(n)
+    sup = _both_edge(g)
+    u, v = _entries(g)
+    spoke = (u == 0) | (v == 0)
+    assert np.all(sup[spoke] == 2) and np.all(sup[~spoke] == 1)
+
+
+@pytest.mark.parametrize("k", [1, 4, 9])
+def test_edge_support_book_and_friendship(k):
+    g = book(k)
+    sup = _both_edge(g)
+    u, v = _entries(g)
+    spine = ((u == 0) & (v == 1)) | ((u == 1) & (v == 0))
+    assert np.all(sup[spine] == k) and np.all(sup[~spine] == 1)
+    assert np.all(_both_edge(friendship(k)) == 1)
+
+
+def test_edge_support_bipartite_is_zero():
+    assert np.all(_both_edge(complete_bipartite(3, 5)) == 0)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_edge_support_sums(seed):
+    # each triangle gives 1 to its 3 edges, each stored at 2 entries; the
+    # entries of row v see the 2 edges at v of every triangle through v
+    n, s, d = graphgen.kronecker(10, seed=seed)
+    g = oracle.build_csr(n, s, d)
+    sup = _both_edge(g)
+    assert int(sup.sum()) == 6 * oracle.count_emd(g)
+    u, v = _entries(g)
+    assert np.array_equal(np.bincount(u, weights=sup, minlength=g.n).astype(np.int64),
+                          2 * oracle.vertex_triangles(g).astype(np.int64))
+    # the two entries of an edge agree
+    rev = {(int(a), int(b)): int(c) for a, b, c in zip(u, v, sup)}
+    assert all(rev[(b, a)] == c for (a, b), c in rev.items())
+    with pytest.raises(ValueError):
+        oracle.edge_support_at(g, [g.nnz])
+
+
+# ------------------------------------------------------------ degree relabel
+
+def _check_relabel(g):
+    h, perm = oracle.relabel_degree(g)
+    deg = g.degrees()
+    # the order: numpy's lexsort by (decreasing degree, increasing id)
+    assert np.array_equal(perm, np.lexsort((np.arange(g.n), -deg)).astype(np.int32))
+    inv = np.empty(g.n, np.int64)
+    inv[perm] = np.arange(g.n)
+    # the same edge set under the map, rows sorted
+    u, v = _entries(g)
+    hu, hv = _entries(h)
+    assert np.array_equal(np.sort(inv[u] * g.n + inv[v]), hu * g.n + hv)
+    assert np.array_equal(h.degrees(), deg[perm])
+    return h, perm
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_relabel_degree_kronecker(seed):
+    n, s, d = graphgen.kronecker(10, seed=seed)
+    g = oracle.build_csr(n, s, d)
+    h, _ = _check_relabel(g)
+    assert oracle.count_emd(h) == oracle.count_emd(g)
+    lev, _ = oracle.bfs_levels(h)
+    assert oracle.alg4(h, lev).T == oracle.count_emd(g)
+
+
+def test_relabel_degree_star_and_ties():
+    # star with hub 5: the hub becomes 0; leaves keep their order
+    g = csr_from_edges(8, [(5, i) for i in range(8) if i != 5])
+    h, perm = _check_relabel(g)
+    assert perm.tolist() == [5, 0, 1, 2, 3, 4, 6, 7]
+    # all degrees equal: the identity
+    h, perm = _check_relabel(cycle(9))
+    assert perm.tolist() == list(range(9))
+    _check_relabel(csr_from_edges(4, []))
