@@ -272,8 +272,10 @@ uint64_t tc_count_profile(int32_t n, int64_t nnz, const int32_t *d_row_ptr, cons
  * t(x), t(y) and t(w), so sum_v t(v) = 3T.
  *   d_tv   device uint64[n], output, written in full (zeroed by the call)
  * Other arguments, the workspace size (tc_count_ws) and the return value as
- * for tc_count; opt->schedule, force_strategy and the tile options apply.
- * Scattered 64-bit atomics make this slower than tc_count.  Synchronises.
+ * for tc_count; opt->schedule, force_strategy and the tile options apply
+ * (the hash tables keep a hit counter beside each key, so wave_slots and
+ * wg_slots are capped at 1024 and 16384 here).  Hits are gathered in LDS
+ * counters and added to global memory with 64-bit atomics.  Synchronises.
  */
 uint64_t tc_vertex_triangles(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                              const int32_t *d_levels, const tc_options *opt, uint64_t *d_tv, tc_stats *stats,
@@ -289,8 +291,8 @@ uint64_t tc_vertex_triangles(int32_t n, int64_t nnz, const int32_t *d_row_ptr, c
  *          indexed like d_col_idx
  * The workspace is larger than tc_count's (two int32 maps of nnz entries from
  * the partitioned lists back to input entries): size it with
- * tc_edge_support_ws.  The hash tables carry the input entry of each key
- * beside it, so wave_slots and wg_slots are capped at 1024 and 16384 here.
+ * tc_edge_support_ws.  The hash tables keep a hit counter beside each key,
+ * so wave_slots and wg_slots are capped at 1024 and 16384 here.
  * The rows must be symmetric (every (u, v) has its (v, u)); TC_VALIDATE
  * checks this.  Returns T or TC_COUNT_ERROR.  Synchronises.
  */

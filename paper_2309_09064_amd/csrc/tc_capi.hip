@@ -447,10 +447,12 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
     if (cfg.schedule == TC_SCHED_TABLE && !cfg.table) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
     cfg.prof = reinterpret_cast<unsigned long long *>(d_prof);
     cfg.tv = reinterpret_cast<unsigned long long *>(d_tv);
+    if (edge || d_tv) {
+        // the hit counters beside every hash table halve the LDS per table
+        if (cfg.wg_slots > kCountedMaxWgSlots) cfg.wg_slots = kCountedMaxWgSlots;
+        if (cfg.wave_slots > kCountedMaxWaveSlots) cfg.wave_slots = kCountedMaxWaveSlots;
+    }
     if (edge) {
-        // the payload array beside every hash table halves the LDS per table
-        if (cfg.wg_slots > kEdgeMaxWgSlots) cfg.wg_slots = kEdgeMaxWgSlots;
-        if (cfg.wave_slots > kEdgeMaxWaveSlots) cfg.wave_slots = kEdgeMaxWaveSlots;
         cfg.sup = nnz > 0 ? d_sup : nullptr;   // no entries: nothing to count or write
         cfg.rp = d_row_ptr;
         cfg.col = d_col_idx;

@@ -358,13 +358,13 @@ struct HashTab {
     int32_t *tab;
     uint32_t bmask;   // buckets - 1
     int shift;        // 32 - log2(buckets)
-    int32_t *pos;     // per-edge counts: a payload per slot (the key's input entry), else unused
+    uint32_t *cnt;    // per-vertex / per-edge counts: a hit counter per slot, else unused
 };
 
-__device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots, int32_t *pos = nullptr) {
+__device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots, uint32_t *cnt = nullptr) {
     HashTab t;
     t.tab = tab;
-    t.pos = pos;
+    t.cnt = cnt;
     t.bmask = (1u << (lg_slots - 2)) - 1;
     t.shift = 32 - (lg_slots - 2);
     return t;
@@ -394,22 +394,9 @@ __device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
     }
 }
 
-// Insert with a payload stored beside the key's slot.
-__device__ __forceinline__ void hash_insert_pos(const HashTab &t, int32_t v, int32_t payload) {
-    uint32_t b = home_bucket(t, v);
-    for (;;) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (atomicCAS(&t.tab[4 * b + j], kEmpty, v) == kEmpty) {
-                t.pos[4 * b + j] = payload;
-                return;
-            }
-        b = (b + 1) & t.bmask;
-    }
-}
-
 // Lookup of up to kPer keys returning the mask of keys found and, for each
-// found key, the payload of its slot (per-edge counts only).
+// found key, the index of its slot (per-vertex / per-edge counts credit the
+// slot's counter).
 template <int kPer>
 __device__ __forceinline__ uint32_t hash_find(const HashTab &t, const int32_t (&v)[kPer], int32_t (&e)[kPer]) {
     uint32_t mask = 0;
@@ -424,7 +411,7 @@ __device__ __forceinline__ uint32_t hash_find(const HashTab &t, const int32_t (&
             const int slot = r.x == x ? 0 : r.y == x ? 1 : r.z == x ? 2 : r.w == x ? 3 : -1;
             if (slot >= 0) {
                 mask |= 1u << u;
-                e[u] = t.pos[4 * b + slot];
+                e[u] = (int32_t)(4 * b + slot);
                 break;
             }
             if (r.w == kEmpty) break;
@@ -555,11 +542,10 @@ __device__ __forceinline__ int32_t upper_idx(const int32_t *a, int32_t len, int3
     return lo;
 }
 
-// search_count that also returns, for each key found, apos[index of the key
-// in a] (per-edge counts: the input entry of the owner's edge to the key).
+// search_count that also returns, for each key found, its index in a.
 template <int kPer>
-__device__ __forceinline__ uint32_t search_find(const int32_t *a, const int32_t *apos, int32_t len,
-                                                const int32_t (&v)[kPer], int32_t (&e)[kPer]) {
+__device__ __forceinline__ uint32_t search_find(const int32_t *a, int32_t len, const int32_t (&v)[kPer],
+                                                int32_t (&e)[kPer]) {
     uint32_t mask = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -568,7 +554,7 @@ __device__ __forceinline__ uint32_t search_find(const int32_t *a, const int32_t 
         const int32_t lb = lower_idx(a, len, v[u]);
         if (lb < len && a[lb] == v[u]) {
             mask |= 1u << u;
-            e[u] = apos[lb];
+            e[u] = lb;
         }
     }
     return mask;
@@ -605,12 +591,12 @@ struct Graph {
 // to flatten a batch of partner lists: 64 * kPer marker bytes (window offset
 // o lives at byte (o % 64) * kPer + o / 64, so a lane reads its kPer window
 // slots with one load) and 64 partner records {start in the batch, list
-// offset}; with record tags (per-vertex and per-edge counts) 64 more ints
-// hold a tag per record: the partner vertex, or the input entry of the edge
-// owner-partner.
+// offset}; with records (per-vertex and per-edge counts, the cover-edge
+// count) 128 more ints hold a tag per record (the partner vertex, or the
+// input entry of the edge owner-partner) and a hit counter per record.
 constexpr int kPer = 8;
 constexpr int kScratchInts = 16 * kPer + 128;
-constexpr int kScratchIdsInts = kScratchInts + 64;
+constexpr int kScratchIdsInts = kScratchInts + 128;
 
 // What the intersection pass produces besides T0 and T1: per-graph counts of
 // a batch, per-vertex triangle counts, or per-edge supports.  kModeCover is
@@ -660,9 +646,12 @@ __device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t x, 
 // popcount, O(1) per element.
 // With `sliced`, only the part of each partner list with values in
 // [lo, hi) is streamed (two binary searches per partner).  kRec selects what
-// else travels with each element: nothing (`count(v)`), the partner vertex
-// (`count(v, y)`), or the input entry of the edge owner-partner and the
-// element's own index in the list array (`count(v, exy, idx)`).
+// else travels with each element: nothing (`count(v)`), the index of its
+// partner record (`count(v, rec)`), or that and the element's own index in
+// the list array (`count(v, rec, idx)`).  Records hold a tag (kRecVertex:
+// the partner vertex; kRecEdge: the input entry of the edge owner-partner)
+// and a hit counter that the functor may bump in LDS; `count.finish(tag, c)`
+// then sees every record with c > 0 once at the end of the chunk.
 enum { kRecNone = 0, kRecVertex = 1, kRecEdge = 2 };
 template <int kRec, class Count>
 __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p0,
@@ -684,7 +673,8 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     if (m == 0) return 0u;
     uint8_t *marker = reinterpret_cast<uint8_t *>(scr);
     int2 *pinfo = reinterpret_cast<int2 *>(scr + 16 * kPer);
-    int32_t *ptag = scr + kScratchInts;   // kRec != kRecNone only
+    int32_t *ptag = scr + kScratchInts;                                     // kRec != kRecNone only
+    uint32_t *pcnt = reinterpret_cast<uint32_t *>(scr + kScratchInts + 64);   // kept zero between chunks
     const int32_t len = mine ? sy : 0;
     const int32_t incl = wave_incl_scan(len);
     const int32_t start = incl - len;
@@ -725,7 +715,7 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
         for (int u = 0; u < kPer; ++u) pi[u] = pinfo[k[u]];
         if constexpr (kRec != kRecNone) {
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) ys[u] = ptag[k[u]];
+            for (int u = 0; u < kPer; ++u) ys[u] = k[u];
         }
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
@@ -751,8 +741,8 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
         int32_t vb[kPer], yb2[kPer], ib[kPer];
         gather(base + kStep, vb, yb2, ib);
         masked(base, va);
-        if constexpr (kRec == kRecEdge) hits += count(va, ya, ia);
-        else if constexpr (kRec == kRecVertex) hits += count(va, ya);
+        if constexpr (kRec == kRecEdge) hits += count(va, ya, ia, ptag, pcnt);
+        else if constexpr (kRec == kRecVertex) hits += count(va, ya, ptag, pcnt);
         else hits += count(va);
         if (base + kStep >= total) break;
 #pragma unroll
@@ -764,6 +754,16 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
         if constexpr (kRec == kRecEdge) {
 #pragma unroll
             for (int u = 0; u < kPer; ++u) ia[u] = ib[u];
+        }
+    }
+    if constexpr (kRec != kRecNone) {
+        wave_lds_sync();   // every lane's counter updates are done
+        if (l < __popcll(m)) {
+            const uint32_t c = pcnt[l];
+            if (c) {
+                count.finish(ptag[l], c);
+                pcnt[l] = 0;
+            }
         }
     }
     wave_lds_sync();   // pinfo is rewritten by the next batch
@@ -862,12 +862,12 @@ __device__ __forceinline__ uint32_t merge_chunk(const Graph &g, int kind, int32_
     return hits;
 }
 
-// The lookups of one window: plain modes count the keys found; vertex mode
-// takes their mask and adds the triangle to the common neighbour w and the
-// partner y of every key found.
-// Edge mode asks `find` for the mask and, per key found, the input entry of
-// the edge owner-key.
+// The lookups of one window.  Plain modes count the keys found.  The other
+// modes take the mask of keys found and, per key, where it was found: a hash
+// table slot (kSlots: its LDS counter is bumped and flushed once per item by
+// the caller) or an index in the owner list (credited at once).
 struct HashProbe {
+    static constexpr bool kSlots = true;
     HashTab t;
     template <bool kMask> __device__ __forceinline__ uint32_t run(const int32_t (&q)[4]) const {
         return hash_count<4, kMask>(t, q);
@@ -877,14 +877,14 @@ struct HashProbe {
     }
 };
 struct SearchProbe {
+    static constexpr bool kSlots = false;
     const int32_t *a;
     int32_t len;
-    const int32_t *apos;   // edge mode: input entry of every owner-list element
     template <bool kMask> __device__ __forceinline__ uint32_t run(const int32_t (&q)[4]) const {
         return search_count<4, kMask>(a, len, q);
     }
     __device__ __forceinline__ uint32_t find(const int32_t (&q)[4], int32_t (&e)[4]) const {
-        return search_find<4>(a, apos, len, q, e);
+        return search_find<4>(a, len, q, e);
     }
 };
 template <class Probe> struct WindowCount {
@@ -893,58 +893,85 @@ template <class Probe> struct WindowCount {
         return in_fours(v, [&](const int32_t(&q)[4]) { return p.template run<false>(q); });
     }
 };
+
+template <class Probe>
+__device__ __forceinline__ uint32_t find8(const Probe &p, const int32_t (&v)[kPer], int32_t (&e)[kPer]) {
+    const int32_t a[4] = {v[0], v[1], v[2], v[3]};
+    const int32_t b[4] = {v[4], v[5], v[6], v[7]};
+    int32_t ea[4], eb[4];
+    const uint32_t mk = p.find(a, ea) | (p.find(b, eb) << 4);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        e[u] = ea[u];
+        e[u + 4] = eb[u];
+    }
+    return mk;
+}
+
+// Per-vertex counts: the common neighbour w through the slot counter (hash)
+// or at once (search), the partner through its record counter; the owner's
+// share is added per item by the caller.
 template <class Probe> struct WindowVertex {
     Probe p;
     unsigned long long *tv;
-    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&y)[kPer]) const {
-        const int32_t a[4] = {v[0], v[1], v[2], v[3]};
-        const int32_t b[4] = {v[4], v[5], v[6], v[7]};
-        const uint32_t mk = p.template run<true>(a) | (p.template run<true>(b) << 4);
+    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&rec)[kPer],
+                                                   const int32_t *, uint32_t *pcnt) const {
+        int32_t e[kPer];
+        const uint32_t mk = find8(p, v, e);
 #pragma unroll
         for (int u = 0; u < kPer; ++u)
             if ((mk >> u) & 1u) {
-                atomicAdd(&tv[v[u]], 1ull);
-                atomicAdd(&tv[y[u]], 1ull);
+                if constexpr (Probe::kSlots) atomicAdd(&p.t.cnt[e[u]], 1u);
+                else atomicAdd(&tv[v[u]], 1ull);
+                atomicAdd(&pcnt[rec[u]], 1u);
             }
         return (uint32_t)__popc(mk);
     }
+    __device__ __forceinline__ void finish(int32_t y, uint32_t c) const { atomicAdd(&tv[y], (unsigned long long)c); }
 };
 
+// Per-edge counts: owner-w through the slot counter (hash) or at once
+// (search), partner-w at once (a distinct edge per element), owner-partner
+// through the record counter.
 template <class Probe> struct WindowEdge {
     Probe p;
     uint32_t *sup;
     const int32_t *lpos;   // input entry of every element of the list array streamed
-    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&exy)[kPer],
-                                                   const int32_t (&idx)[kPer]) const {
-        const int32_t a[4] = {v[0], v[1], v[2], v[3]};
-        const int32_t b[4] = {v[4], v[5], v[6], v[7]};
-        int32_t ea[4], eb[4];
-        const uint32_t mk = p.find(a, ea) | (p.find(b, eb) << 4);
+    const int32_t *apos;   // the same for the owner list (search only)
+    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&rec)[kPer],
+                                                   const int32_t (&idx)[kPer], const int32_t *,
+                                                   uint32_t *pcnt) const {
+        int32_t e[kPer];
+        const uint32_t mk = find8(p, v, e);
 #pragma unroll
         for (int u = 0; u < kPer; ++u)
             if ((mk >> u) & 1u) {
-                atomicAdd(&sup[u < 4 ? ea[u & 3] : eb[u & 3]], 1u);   // owner - w
-                atomicAdd(&sup[lpos[idx[u]]], 1u);                    // partner - w
-                atomicAdd(&sup[exy[u]], 1u);                          // owner - partner
+                if constexpr (Probe::kSlots) atomicAdd(&p.t.cnt[e[u]], 1u);
+                else atomicAdd(&sup[apos[e[u]]], 1u);
+                atomicAdd(&sup[lpos[idx[u]]], 1u);
+                atomicAdd(&pcnt[rec[u]], 1u);
             }
         return (uint32_t)__popc(mk);
     }
+    __device__ __forceinline__ void finish(int32_t exy, uint32_t c) const { atomicAdd(&sup[exy], c); }
 };
 
 template <class Probe> struct WindowCover {
     Probe p;
     const int32_t *lev;
     int32_t x, lx;
-    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&y)[kPer]) const {
+    __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&rec)[kPer],
+                                                   const int32_t *ptag, uint32_t *) const {
         const int32_t a[4] = {v[0], v[1], v[2], v[3]};
         const int32_t b[4] = {v[4], v[5], v[6], v[7]};
         const uint32_t mk = p.template run<true>(a) | (p.template run<true>(b) << 4);
         uint32_t c = 0;
 #pragma unroll
         for (int u = 0; u < kPer; ++u)
-            if ((mk >> u) & 1u) c += cover_counts(lev[v[u]], lx, v[u], max(x, y[u])) ? 1u : 0u;
+            if ((mk >> u) & 1u) c += cover_counts(lev[v[u]], lx, v[u], max(x, ptag[rec[u]])) ? 1u : 0u;
         return c;
     }
+    __device__ __forceinline__ void finish(int32_t, uint32_t) const {}
 };
 
 // One chunk of owned partners through a lookup structure, in the kernel's mode.
@@ -958,8 +985,11 @@ __device__ __forceinline__ uint32_t probe_chunk(const Graph &g, int kind, int32_
         return stream_chunk<kRecVertex>(g, kind, x, sx, p0, je, scr, WindowCover<Probe>{pr, sk.lev, x, sk.lev[x]},
                                         sliced, lo, hi);
     else if constexpr (kMode == kModeEdge)
-        return stream_chunk<kRecEdge>(g, kind, x, sx, p0, je, scr,
-                                      WindowEdge<Probe>{pr, sk.sup, kind == 0 ? g.pos0 : g.pos1}, sliced, lo, hi);
+        return stream_chunk<kRecEdge>(
+            g, kind, x, sx, p0, je, scr,
+            WindowEdge<Probe>{pr, sk.sup, kind == 0 ? g.pos0 : g.pos1,
+                              kind == 0 ? g.pos0 + g.rp0[x] : g.pos1 + g.rp1[x]},
+            sliced, lo, hi);
     else
         return stream_chunk<kRecNone>(g, kind, x, sx, p0, je, scr, WindowCount<Probe>{pr}, sliced, lo, hi);
 }
@@ -979,9 +1009,11 @@ __device__ __forceinline__ int table_log2(int32_t sx, int max_log2) {
 // kMode: kModeBatch adds each item's hits to the counter of the owner's
 // graph; kModeVertex adds every triangle to its three vertices (the owner's
 // share once per item); kModeEdge adds every triangle to its three edges,
-// each at one of the edge's two input entries, and keeps a payload array
-// (the owner-key edge's input entry) beside every hash table, so its LDS
-// holds two table regions.
+// each at one of the edge's two input entries.  These two modes keep a hit
+// counter beside every hash table slot (a second LDS region as large as the
+// tables), flushed to the common neighbour's count once per item, so a hub
+// that is a common neighbour of many pairs sees one global atomic per owner
+// list instead of one per triangle.
 template <bool kProf, int kMode>
 __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__restrict__ items,
                                                           int32_t *__restrict__ q, int wg_log2, int wave_log2,
@@ -993,11 +1025,34 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
     constexpr bool kBatch = kMode == kModeBatch;
     constexpr bool kEdge = kMode == kModeEdge;
     constexpr bool kOwnerSink = kMode == kModeBatch || kMode == kModeVertex;
+    constexpr bool kSlotCnt = kMode == kModeVertex || kEdge;   // counters beside the table slots
     constexpr int kScr = kMode == kModeVertex || kMode == kModeCover || kEdge ? kScratchIdsInts : kScratchInts;
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
-    int32_t *scr = lds + (kEdge ? 2 : 1) * table_ints + w * kScr;
+    int32_t *scr = lds + (kSlotCnt ? 2 : 1) * table_ints + w * kScr;
+    uint32_t *slot_cnt = reinterpret_cast<uint32_t *>(lds + table_ints);   // kSlotCnt only
     reinterpret_cast<uint64_t *>(scr)[l] = 0ull;   // markers start clear
+    if (kScr == kScratchIdsInts) scr[kScratchInts + 64 + l] = 0;   // record counters start clear
+    if constexpr (kSlotCnt)   // slot counters start clear (the first item's barrier orders this)
+        for (int i = threadIdx.x; i < table_ints; i += kIsectThreads) slot_cnt[i] = 0;
+    // a flush of the slot counters after an item's lookups: the hits of each
+    // owner-list key go to its vertex / to the input entry of the edge
+    // owner-key (found by binary search in the owner list)
+    auto flush_slots = [&](const HashTab &ht, int nslots, int first, int step, const int32_t *a, int32_t sx,
+                           int kind, int32_t x) {
+        for (int i = first; i < nslots; i += step) {
+            const uint32_t c = ht.cnt[i];
+            if (c == 0) continue;
+            ht.cnt[i] = 0;
+            const int32_t key = ht.tab[i];
+            if constexpr (kMode == kModeVertex) {
+                atomicAdd(&sk.tv[key], (unsigned long long)c);
+            } else if constexpr (kEdge) {
+                const int32_t *apos = kind == 0 ? g.pos0 + g.rp0[x] : g.pos1 + g.rp1[x];
+                atomicAdd(&sk.sup[apos[lower_idx(a, sx, key)]], c);
+            }
+        }
+    };
     uint64_t acc0 = 0, acc1 = 0;
 
     // ---- workgroup items, claimed by blocks from a counter (they are few):
@@ -1021,17 +1076,12 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const int32_t lo = sliced ? a[a_lo] : 0;
         const int32_t hi = sliced && a_hi < sx ? a[a_hi] : INT32_MAX;
         const int lg = table_log2(a_hi - a_lo, wg_log2);
-        const HashTab ht = make_tab(lds, lg, kEdge ? lds + table_ints : nullptr);
+        const HashTab ht = make_tab(lds, lg, kSlotCnt ? slot_cnt : nullptr);
         if (threadIdx.x == 0) s_chunk = 0;
         for (int i = threadIdx.x; i < (1 << lg) / 4; i += kIsectThreads)
             reinterpret_cast<int4 *>(lds)[i] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
-        __syncthreads();
-        if constexpr (kEdge) {
-            const int32_t *apos = (kind == 0 ? g.pos0 + g.rp0[x] : g.pos1 + g.rp1[x]);
-            for (int i = a_lo + (int)threadIdx.x; i < a_hi; i += kIsectThreads) hash_insert_pos(ht, a[i], apos[i]);
-        } else {
-            for (int i = a_lo + (int)threadIdx.x; i < a_hi; i += kIsectThreads) hash_insert(ht, a[i]);
-        }
+        __syncthreads();   // (slot counters are zero: the kernel starts them so and every flush clears them)
+        for (int i = a_lo + (int)threadIdx.x; i < a_hi; i += kIsectThreads) hash_insert(ht, a[i]);
         __syncthreads();
         uint32_t h = 0;
         for (;;) {
@@ -1040,6 +1090,10 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             const int32_t p0 = item.jb + __shfl(c, 0, kWave) * kWave;
             if (p0 >= item.je) break;
             h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr, HashProbe{ht}, sk, sliced, lo, hi);
+        }
+        if constexpr (kSlotCnt) {
+            __syncthreads();   // every wavefront's lookups are done
+            flush_slots(ht, 1 << lg, (int)threadIdx.x, kIsectThreads, a, sx, kind, x);
         }
         if (kind == 0) acc0 += h; else acc1 += h;
         if (kOwnerSink) {
@@ -1071,28 +1125,25 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         uint32_t h = 0;
         if (strat == TC_STRAT_WAVE_HASH) {
             const int lg = table_log2(sx, wave_log2);
-            const HashTab ht = make_tab(tab, lg, kEdge ? tab + table_ints : nullptr);
+            const HashTab ht = make_tab(tab, lg, kSlotCnt ? reinterpret_cast<uint32_t *>(tab + table_ints) : nullptr);
             for (int i = l; i < (1 << lg) / 4; i += kWave)
                 reinterpret_cast<int4 *>(tab)[i] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
             wave_lds_sync();
-            if constexpr (kEdge) {
-                const int32_t *apos = (kind == 0 ? g.pos0 + g.rp0[x] : g.pos1 + g.rp1[x]);
-                for (int i = l; i < sx; i += kWave) hash_insert_pos(ht, a[i], apos[i]);
-            } else {
-                for (int i = l; i < sx; i += kWave) hash_insert(ht, a[i]);
-            }
+            for (int i = l; i < sx; i += kWave) hash_insert(ht, a[i]);
             wave_lds_sync();
             for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave)
                 h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr, HashProbe{ht}, sk);
             wave_lds_sync();   // lookups done before the next item clears the table
+            if constexpr (kSlotCnt) {
+                flush_slots(ht, 1 << lg, l, kWave, a, sx, kind, x);
+                wave_lds_sync();
+            }
         } else if (strat == TC_STRAT_MERGE) {
             for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave) h += merge_chunk<kMode>(g, kind, x, sx, a, p0, item.je, sk);
         } else {
             for (int32_t p0 = item.jb; p0 < item.je; p0 += kWave)
                 h += probe_chunk<kMode>(g, kind, x, sx, p0, item.je, scr,
-                                        SearchProbe{a, sx, kEdge ? (kind == 0 ? g.pos0 + g.rp0[x] : g.pos1 + g.rp1[x])
-                                                                 : nullptr},
-                                        sk);
+                                        SearchProbe{a, sx}, sk);
         }
         if (kind == 0) acc0 += h; else acc1 += h;
         if (kOwnerSink) {
@@ -1324,7 +1375,7 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         if ((vertex || edge || cover) && (batch || cfg.prof)) return TC_ERR_ARG;
         if ((int)vertex + (int)edge + (int)cover > 1) return TC_ERR_ARG;
         if (edge && (!pb.pos0 || !pb.pos1 || !cfg.rp || !cfg.col)) return TC_ERR_ARG;
-        const size_t lds_bytes = (size_t)((edge ? 2 : 1) * table_ints +
+        const size_t lds_bytes = (size_t)((edge || vertex ? 2 : 1) * table_ints +
                                           kIsectWaves * (vertex || edge || cover ? kScratchIdsInts : kScratchInts)) *
                                  sizeof(int32_t);
         const void *kern = cfg.prof ? (batch ? (const void *)k_isect<true, kModeBatch>

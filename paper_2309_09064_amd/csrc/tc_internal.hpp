@@ -198,10 +198,10 @@ struct CountOut {
     int32_t strategy_items[TC_NUM_STRATEGIES] = {0, 0, 0, 0};
     float ms_bucket = 0.f, ms_isect = 0.f;
 };
-// Per-edge support keeps a payload array beside every hash table, so its
-// tables get half the LDS: at most these many slots.
-constexpr int kEdgeMaxWgSlots = 16384;
-constexpr int kEdgeMaxWaveSlots = 1024;
+// Per-vertex and per-edge counts keep a hit counter beside every hash table
+// slot, so their tables get half the LDS: at most these many slots.
+constexpr int kCountedMaxWgSlots = 16384;
+constexpr int kCountedMaxWaveSlots = 1024;
 
 struct CountCfg {
     int schedule = TC_SCHED_HEURISTIC;
