@@ -128,6 +128,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-schedule leg")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time only the main leg (no forward-hashed, per-vertex, per-edge or learned legs), "
+                         "so that a profile of the run holds the main leg's kernels alone")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -164,26 +167,29 @@ def main():
     # context: the same kernels with every edge horizontal (L = 0): plain
     # forward-hashed counting of the whole graph, no BFS (the paper's FH/FHD
     # comparison, Table I)
-    zero = torch.zeros(n, dtype=torch.int32, device="cuda")
-    fcounter = tc.Counter(n, nnz, tc.Options(timing=True))
-    for _ in range(args.warmup):
-        fcounter(rp, col, zero)
-    torch.cuda.synchronize()
-    fres = []
-    t_f0 = time.perf_counter()
-    for _ in range(args.steps):
-        fres.append(fcounter(rp, col, zero))
-    torch.cuda.synchronize()
-    fstep_s = (time.perf_counter() - t_f0) / args.steps
-    assert all(x.T == T for x in fres), "forward-hashed count differs"
-    forward_hashed = {"value": m / fstep_s, "ms_per_step": fstep_s * 1e3, "phase_ms": phase_means(fres)}
-    print(f"# forward-hashed (L = 0): {fstep_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    forward_hashed = None
+    if not args.main_only:
+        zero = torch.zeros(n, dtype=torch.int32, device="cuda")
+        fcounter = tc.Counter(n, nnz, tc.Options(timing=True))
+        for _ in range(args.warmup):
+            fcounter(rp, col, zero)
+        torch.cuda.synchronize()
+        fres = []
+        t_f0 = time.perf_counter()
+        for _ in range(args.steps):
+            fres.append(fcounter(rp, col, zero))
+        torch.cuda.synchronize()
+        fstep_s = (time.perf_counter() - t_f0) / args.steps
+        assert all(x.T == T for x in fres), "forward-hashed count differs"
+        forward_hashed = {"value": m / fstep_s, "ms_per_step": fstep_s * 1e3, "phase_ms": phase_means(fres)}
+        print(f"# forward-hashed (L = 0): {fstep_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
 
     # context: the per-vertex and per-edge modes of the same pass (triangles
     # through every vertex / every edge; whole pipeline, output allocation
     # included)
     local = {}
-    for name, fn in (("vertex_triangles", tc.vertex_triangles), ("edge_support", tc.edge_support)):
+    for name, fn in () if args.main_only else (("vertex_triangles", tc.vertex_triangles),
+                                                ("edge_support", tc.edge_support)):
         for _ in range(max(args.warmup, 1)):
             fn(rp, col)
         torch.cuda.synchronize()
@@ -197,7 +203,7 @@ def main():
         print(f"# {name}: {x_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
 
     learned = None
-    if not args.no_learned:
+    if not (args.no_learned or args.main_only):
         # learned schedule: profile this graph under each forced strategy,
         # train the cost network on the profile, schedule (all untimed), then
         # time the same steps with the network's strategy table
