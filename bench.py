@@ -115,6 +115,19 @@ def timed_steps(counter, rp, col, steps, warmup):
     return (time.perf_counter() - t0) / steps, results
 
 
+def time_calls(fn, steps, warmup):
+    """Mean wall time per call (seconds) of fn() and its last result."""
+    import torch
+    for _ in range(max(warmup, 1)):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
 def phase_means(results):
     return {k: float(np.mean([x.ms[k] for x in results])) for k in ("bfs", "partition", "bucket", "isect")}
 
@@ -190,17 +203,33 @@ def main():
     local = {}
     for name, fn in () if args.main_only else (("vertex_triangles", tc.vertex_triangles),
                                                 ("edge_support", tc.edge_support)):
-        for _ in range(max(args.warmup, 1)):
-            fn(rp, col)
-        torch.cuda.synchronize()
-        t_x0 = time.perf_counter()
-        for _ in range(args.steps):
-            _, rx = fn(rp, col)
-        torch.cuda.synchronize()
-        x_s = (time.perf_counter() - t_x0) / args.steps
+        x_s, (_, rx) = time_calls(lambda: fn(rp, col), args.steps, args.warmup)
         assert rx.T == T, f"{name} count differs"
         local[name] = {"value": m / x_s, "ms_per_step": x_s * 1e3}
         print(f"# {name}: {x_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # context: the paper's variants on the same kernels: Alg. 3 (cover-edge,
+    # one pass over full rows), the degree relabel, and Alg. 4 / Alg. 3 on the
+    # relabelled graph (BaderD / CED, relabel charged as pre-processing)
+    variants = None
+    if not args.main_only:
+        ce_s, rce = time_calls(lambda: tc.count_cover_edge(rp, col), args.steps, args.warmup)
+        rl_s, (rp2, col2, _) = time_calls(lambda: tc.relabel_by_degree(rp, col), args.steps, args.warmup)
+        dcounter = tc.Counter(n, nnz, tc.Options(timing=True))
+        bd_s, rbd = time_calls(lambda: dcounter(rp2, col2), args.steps, args.warmup)
+        ced_s, rced = time_calls(lambda: tc.count_cover_edge(rp2, col2), args.steps, args.warmup)
+        assert rce.T == T and rbd.T == T and rced.T == T, "a variant's count differs"
+        variants = {"cover_edge_alg3": {"ms_per_step": ce_s * 1e3, "value": m / ce_s},
+                    "degree_relabel_ms": rl_s * 1e3,
+                    "baderd": {"ms_per_step": (rl_s + bd_s) * 1e3, "value": m / (rl_s + bd_s),
+                               "count_ms": bd_s * 1e3, "k_percent": round(100.0 * rbd.e0 / m, 2),
+                               "levels": rbd.levels, "phase_ms": dict(rbd.ms)},
+                    "ced": {"ms_per_step": (rl_s + ced_s) * 1e3, "value": m / (rl_s + ced_s),
+                            "count_ms": ced_s * 1e3}}
+        print(f"# cover-edge (Alg. 3): {ce_s * 1e3:.3f} ms; relabel {rl_s * 1e3:.3f} ms; "
+              f"BaderD count {bd_s * 1e3:.3f} ms (k {variants['baderd']['k_percent']} %); CED count {ced_s * 1e3:.3f} ms",
+              file=sys.stderr, flush=True)
+        del rp2, col2
 
     learned = None
     if not (args.no_learned or args.main_only):
@@ -263,7 +292,7 @@ def main():
                    "k_percent": round(100.0 * r.e0 / m, 2), "levels": r.levels, "counts_bit_exact": exact,
                    "phase_ms": ms, "items": r.items, "strategy_items": r.strategy_items,
                    "learned_schedule": learned, "forward_hashed_same_kernels": forward_hashed,
-                   "per_vertex_and_edge": local},
+                   "per_vertex_and_edge": local, "paper_variants": variants},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_isect",
                      "bytes_per_launch": balg, "ms_per_launch": ms["isect"]},
