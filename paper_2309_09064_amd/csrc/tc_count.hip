@@ -350,14 +350,17 @@ __global__ __launch_bounds__(1024) void k_bucket_order(const int32_t *__restrict
 
 // ---------------------------------------------------------------- probes
 
-// LDS hash table of 4-slot buckets (open addressing over buckets).  A key's
-// home bucket is a multiplicative hash of the id; slots of a bucket fill in
-// order, so a lookup that meets a bucket whose last slot is empty can stop.
-// Tables are sized so at most half the slots are used.
+// LDS hash table with linear probing over single 32-bit slots.  A key's
+// home slot is a multiplicative hash of the id; a lookup walks from it to
+// the key or to an empty slot.  One 4-byte read per probe spreads a
+// wavefront's 64 random probes over all 32 LDS banks: wider buckets (one
+// 16-byte read per probe) saturate the LDS address unit on this workload.
+// Tables are sized so at most half the slots are used (1/8 where LDS
+// allows, where about one probe in eight continues past the home slot).
 struct HashTab {
     int32_t *tab;
-    uint32_t bmask;   // buckets - 1
-    int shift;        // 32 - log2(buckets)
+    uint32_t mask;    // slots - 1
+    int shift;        // 32 - log2(slots)
     uint32_t *cnt;    // per-vertex / per-edge counts: a hit counter per slot, else unused
 };
 
@@ -365,95 +368,56 @@ __device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots, uint32_t
     HashTab t;
     t.tab = tab;
     t.cnt = cnt;
-    t.bmask = (1u << (lg_slots - 2)) - 1;
-    t.shift = 32 - (lg_slots - 2);
+    t.mask = (1u << lg_slots) - 1;
+    t.shift = 32 - lg_slots;
     return t;
 }
 
-__device__ __forceinline__ uint32_t home_bucket(const HashTab &t, int32_t v) {
+__device__ __forceinline__ uint32_t home_slot(const HashTab &t, int32_t v) {
     return ((uint32_t)v * 0x9E3779B1u) >> t.shift;
 }
 
-// Whether bucket q holds x: the smallest of the four xors is zero exactly
-// when a slot equals x (xor + min instead of four compares whose boolean
-// reduction the compiler expands into mask arithmetic).
-__device__ __forceinline__ bool bucket_has(const int4 &q, int32_t x) {
-    const uint32_t ux = (uint32_t)x;
-    const uint32_t a = min((uint32_t)q.x ^ ux, (uint32_t)q.y ^ ux);
-    const uint32_t b = min((uint32_t)q.z ^ ux, (uint32_t)q.w ^ ux);
-    return min(a, b) == 0u;
-}
-
+// Keys are distinct, so an insertion only needs an empty slot.
 __device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
-    uint32_t b = home_bucket(t, v);
-    for (;;) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (atomicCAS(&t.tab[4 * b + j], kEmpty, v) == kEmpty) return;
-        b = (b + 1) & t.bmask;
-    }
-}
-
-// Lookup of up to kPer keys returning the mask of keys found and, for each
-// found key, the index of its slot (per-vertex / per-edge counts credit the
-// slot's counter).
-template <int kPer>
-__device__ __forceinline__ uint32_t hash_find(const HashTab &t, const int32_t (&v)[kPer], int32_t (&e)[kPer]) {
-    uint32_t mask = 0;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        e[u] = 0;
-        const int32_t x = v[u];
-        if (x < 0) continue;
-        uint32_t b = home_bucket(t, x);
-        for (;;) {
-            const int4 r = *reinterpret_cast<const int4 *>(&t.tab[4 * b]);
-            const int slot = r.x == x ? 0 : r.y == x ? 1 : r.z == x ? 2 : r.w == x ? 3 : -1;
-            if (slot >= 0) {
-                mask |= 1u << u;
-                e[u] = (int32_t)(4 * b + slot);
-                break;
-            }
-            if (r.w == kEmpty) break;
-            b = (b + 1) & t.bmask;
-        }
-    }
-    return mask;
+    uint32_t b = home_slot(t, v);
+    while (atomicCAS(&t.tab[b], kEmpty, v) != kEmpty) b = (b + 1) & t.mask;
 }
 
 // Membership of up to kPer keys (negative = absent slot).  Every key's home
-// bucket is read once, unconditionally and interleaved; a key whose home
-// bucket is full and holds no match (rare at the tables' load) then follows
-// its probe chain, one pending key at a time per lane.  Keeping the common
-// case free of per-key predication is what bounds the instruction count:
-// the slowest of a wavefront's keys no longer sets the work of all of them.
-// With kMask the result is the mask of keys found (bit u for key u) instead
-// of their number.
-template <int kPer, bool kMask = false>
-__device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (&v)[kPer]) {
+// slot is read once, unconditionally and interleaved; a key whose home slot
+// holds another key (about one in eight at the tables' load) then follows
+// its probe sequence, one pending key at a time per lane.  Keeping the
+// common case free of per-key predication is what bounds the instruction
+// count: the slowest of a wavefront's keys no longer sets the work of all of
+// them.  With kMask the result is the mask of keys found (bit u for key u)
+// instead of their number; with kSlots as well, slot[u] receives the slot of
+// each key found (per-vertex / per-edge counts credit the slot's counter).
+template <int kPer, bool kMask = false, bool kSlots = false>
+__device__ __forceinline__ uint32_t hash_probe(const HashTab &t, const int32_t (&v)[kPer], int32_t *slot) {
     uint32_t b[kPer];
-    int4 q[kPer];
+    int32_t q[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) b[u] = home_bucket(t, v[u]);
+    for (int u = 0; u < kPer; ++u) b[u] = home_slot(t, v[u]);
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) q[u] = *reinterpret_cast<const int4 *>(&t.tab[4 * b[u]]);
+    for (int u = 0; u < kPer; ++u) q[u] = t.tab[b[u]];
     uint32_t hits = 0;
     bool any_pend = false;   // a wavefront mask: no per-lane bits in the common case
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int32_t x = v[u];
-        const bool m = bucket_has(q[u], x);
+        const bool m = q[u] == x;
         const bool live = x >= 0;
         if constexpr (kMask) hits |= (live & m) ? (1u << u) : 0u;
         else hits += (live & m) ? 1u : 0u;
-        any_pend |= live & !m & (q[u].w != kEmpty);
+        if constexpr (kSlots) slot[u] = (int32_t)b[u];
+        any_pend |= live & !m & (q[u] != kEmpty);
     }
     if (__ballot(any_pend) == 0) return hits;
     uint32_t pend = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int32_t x = v[u];
-        pend |= ((x >= 0) & !bucket_has(q[u], x) & (q[u].w != kEmpty)) ? (1u << u) : 0u;
+        pend |= ((x >= 0) & (q[u] != x) & (q[u] != kEmpty)) ? (1u << u) : 0u;
     }
     while (pend) {
         const int u = __builtin_ctz(pend);
@@ -466,17 +430,32 @@ __device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (
             bb = u == j ? b[j] : bb;
         }
         for (;;) {
-            bb = (bb + 1) & t.bmask;
-            const int4 r = *reinterpret_cast<const int4 *>(&t.tab[4 * bb]);
-            if (bucket_has(r, x)) {
+            bb = (bb + 1) & t.mask;
+            const int32_t r = t.tab[bb];
+            if (r == x) {
                 if constexpr (kMask) hits |= 1u << u;
                 else ++hits;
+                if constexpr (kSlots) {
+#pragma unroll
+                    for (int j = 0; j < kPer; ++j)
+                        if (j == u) slot[j] = (int32_t)bb;
+                }
                 break;
             }
-            if (r.w == kEmpty) break;
+            if (r == kEmpty) break;
         }
     }
     return hits;
+}
+
+template <int kPer, bool kMask = false>
+__device__ __forceinline__ uint32_t hash_count(const HashTab &t, const int32_t (&v)[kPer]) {
+    return hash_probe<kPer, kMask, false>(t, v, nullptr);
+}
+
+template <int kPer>
+__device__ __forceinline__ uint32_t hash_find(const HashTab &t, const int32_t (&v)[kPer], int32_t (&e)[kPer]) {
+    return hash_probe<kPer, true, true>(t, v, e);
 }
 
 // Lookups of the kPer keys of a window in two interleaved groups of four
@@ -638,6 +617,73 @@ __device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t x, 
     return owns(sx, sy, x, y);
 }
 
+// Partner lists at least this long stream through stream_long.
+constexpr int32_t kLongList = kWave;
+
+// Streams lists of at least 64 elements as one virtual array, 64 * kPer
+// elements per step like stream_chunk, without its LDS markers: a row of 64
+// consecutive positions then spans at most two lists, so a lane finds its
+// list by one compare against the next list's start.  The cursor (current
+// list, next list) is uniform and lives in scalar registers, read from the
+// owning lanes with readlane.  m: lanes holding a list; len / yb: the list's
+// length (0 off m) and offset in `lists`.
+template <class Count>
+__device__ __forceinline__ uint32_t stream_long(const int32_t *lists, uint64_t m, int32_t len, int32_t yb,
+                                                Count count) {
+    const int l = lane_id();
+    const int32_t incl = wave_incl_scan(len);
+    const int32_t start = incl - len;
+    const int32_t total = __shfl(incl, kWave - 1, kWave);
+    const int32_t offv = yb - start;   // position p of this lane's list is lists[offv + p]
+    uint64_t rest = m;
+    const int first = (int)__builtin_ctzll(rest);
+    rest &= rest - 1;
+    int32_t c_off = __builtin_amdgcn_readlane(offv, first);
+    int32_t n_start = INT32_MAX, n_off = 0;
+    auto next = [&]() {
+        if (rest) {
+            const int nl = (int)__builtin_ctzll(rest);
+            rest &= rest - 1;
+            n_start = __builtin_amdgcn_readlane(start, nl);
+            n_off = __builtin_amdgcn_readlane(offv, nl);
+        } else {
+            n_start = INT32_MAX;
+            n_off = 0;
+        }
+    };
+    next();
+    constexpr int32_t kStep = kPer * kWave;
+    // rows must be visited in increasing order: the cursor only moves forward.
+    // Positions past the end are clamped into the last list and masked later.
+    auto gather = [&](int32_t base, int32_t (&v)[kPer]) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int32_t row = base + u * kWave;
+            while (n_start <= row) {
+                c_off = n_off;
+                next();
+            }
+            const int32_t pos = row + l;
+            const int32_t off = pos >= n_start ? n_off : c_off;
+            v[u] = lists[off + min(pos, total - 1)];
+        }
+    };
+    uint32_t hits = 0;
+    int32_t va[kPer];
+    gather(0, va);
+    for (int32_t base = 0;; base += kStep) {
+        int32_t vb[kPer];
+        gather(base + kStep, vb);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) va[u] = base + u * kWave + l < total ? va[u] : -1;
+        hits += count(va);
+        if (base + kStep >= total) break;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) va[u] = vb[u];
+    }
+    return hits;
+}
+
 // Streams the owned partner lists among the 64 c0 positions starting at p0
 // through `count` (a functor over kPer keys).  The lists are concatenated
 // into one virtual array that the wavefront consumes 64 * kPer elements per
@@ -669,8 +715,15 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
         sy = e - b;
         mine = sy > 0;   // two lists may not start at one window offset
     }
+    uint32_t long_hits = 0;
+    if constexpr (kRec == kRecNone) {   // long lists take the marker-free path
+        const bool lng = mine && sy >= kLongList;
+        const uint64_t ml = __ballot(lng);
+        if (ml) long_hits = stream_long(lists, ml, lng ? sy : 0, yb, count);
+        mine = mine && !lng;
+    }
     const uint64_t m = __ballot(mine);
-    if (m == 0) return 0u;
+    if (m == 0) return long_hits;
     uint8_t *marker = reinterpret_cast<uint8_t *>(scr);
     int2 *pinfo = reinterpret_cast<int2 *>(scr + 16 * kPer);
     int32_t *ptag = scr + kScratchInts;                                     // kRec != kRecNone only
@@ -707,7 +760,7 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const uint64_t mw = __ballot((mk >> (8 * u)) & 0xffu);
-            k[u] = max(before + __popcll(mw & le) - 1, 0);
+            k[u] = max(before + (int32_t)__popcll(mw & le) - 1, 0);   // int max: a mixed signed / unsigned max resolves to double
             before += __popcll(mw);
         }
         int2 pi[kPer];
@@ -767,7 +820,7 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
         }
     }
     wave_lds_sync();   // pinfo is rewritten by the next batch
-    return hits;
+    return hits + long_hits;
 }
 
 // Merge strategy for a small owner, one lane per item: the lane walks the
@@ -868,16 +921,24 @@ __device__ __forceinline__ uint32_t merge_chunk(const Graph &g, int kind, int32_
 // the caller) or an index in the owner list (credited at once).
 struct HashProbe {
     static constexpr bool kSlots = true;
+    static constexpr bool kWide = true;   // all kPer keys of a window in one group
     HashTab t;
     template <bool kMask> __device__ __forceinline__ uint32_t run(const int32_t (&q)[4]) const {
         return hash_count<4, kMask>(t, q);
     }
+    template <bool kMask> __device__ __forceinline__ uint32_t run8(const int32_t (&q)[kPer]) const {
+        return hash_count<kPer, kMask>(t, q);
+    }
     __device__ __forceinline__ uint32_t find(const int32_t (&q)[4], int32_t (&e)[4]) const {
         return hash_find<4>(t, q, e);
+    }
+    __device__ __forceinline__ uint32_t find8(const int32_t (&q)[kPer], int32_t (&e)[kPer]) const {
+        return hash_find<kPer>(t, q, e);
     }
 };
 struct SearchProbe {
     static constexpr bool kSlots = false;
+    static constexpr bool kWide = false;
     const int32_t *a;
     int32_t len;
     template <bool kMask> __device__ __forceinline__ uint32_t run(const int32_t (&q)[4]) const {
@@ -890,12 +951,14 @@ struct SearchProbe {
 template <class Probe> struct WindowCount {
     Probe p;
     __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer]) const {
-        return in_fours(v, [&](const int32_t(&q)[4]) { return p.template run<false>(q); });
+        if constexpr (Probe::kWide) return p.template run8<false>(v);
+        else return in_fours(v, [&](const int32_t(&q)[4]) { return p.template run<false>(q); });
     }
 };
 
 template <class Probe>
 __device__ __forceinline__ uint32_t find8(const Probe &p, const int32_t (&v)[kPer], int32_t (&e)[kPer]) {
+    if constexpr (Probe::kWide) return p.find8(v, e);
     const int32_t a[4] = {v[0], v[1], v[2], v[3]};
     const int32_t b[4] = {v[4], v[5], v[6], v[7]};
     int32_t ea[4], eb[4];
@@ -962,9 +1025,14 @@ template <class Probe> struct WindowCover {
     int32_t x, lx;
     __device__ __forceinline__ uint32_t operator()(const int32_t (&v)[kPer], const int32_t (&rec)[kPer],
                                                    const int32_t *ptag, uint32_t *) const {
-        const int32_t a[4] = {v[0], v[1], v[2], v[3]};
-        const int32_t b[4] = {v[4], v[5], v[6], v[7]};
-        const uint32_t mk = p.template run<true>(a) | (p.template run<true>(b) << 4);
+        uint32_t mk;
+        if constexpr (Probe::kWide) {
+            mk = p.template run8<true>(v);
+        } else {
+            const int32_t a[4] = {v[0], v[1], v[2], v[3]};
+            const int32_t b[4] = {v[4], v[5], v[6], v[7]};
+            mk = p.template run<true>(a) | (p.template run<true>(b) << 4);
+        }
         uint32_t c = 0;
 #pragma unroll
         for (int u = 0; u < kPer; ++u)
