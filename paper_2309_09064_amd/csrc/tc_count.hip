@@ -35,6 +35,10 @@ constexpr int kMinPartnersPerItem = 8;     // wavefront items
 constexpr int kMinPartnersPerWgItem = 4096; // workgroup items
 constexpr int kWgItemWaves = 4 * kIsectWaves; // a workgroup item holds this many wavefront items of work
 constexpr int32_t kEmpty = -1;
+// A workgroup table (2^wg_log2 slots) holds at most 2^(wg_log2 - kWgCapShift)
+// owner elements (load 1/8: linear probing stays short); longer owner lists
+// are cut into value-range slices.
+constexpr int kWgCapShift = 3;
 constexpr int kLaneMergeOb = 4;            // merge items with owner lists below 32: one lane each
 constexpr int kLanePartners = 32;          // row positions per lane item
 
@@ -1137,7 +1141,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
         const int32_t sx = list_size(kind, g.up0, g.rp1, x);
         // the owner slice of this item: positions [a_lo, a_hi), values [lo, hi)
-        const int32_t nsl = owner_slices(sx, wg_log2 - 1);
+        const int32_t nsl = owner_slices(sx, wg_log2 - kWgCapShift);
         const int32_t si = (int32_t)((uint32_t)item.code >> kSliceShift);
         const int32_t a_lo = (int32_t)((int64_t)sx * si / nsl), a_hi = (int32_t)((int64_t)sx * (si + 1) / nsl);
         const bool sliced = nsl > 1;
@@ -1368,13 +1372,15 @@ static SchedCfg sched_cfg(int32_t n, int64_t nnz, const CountCfg &cfg) {
     sc.table = cfg.table;
     sc.force = cfg.force;
     sc.wave_ob_max = wave_log2 - 2;
-    sc.wg_ob_max = wg_log2 - 2;
-    sc.wg_cap_log2 = wg_log2 - 1;
+    sc.wg_ob_max = wg_log2 - kWgCapShift - 1;
+    sc.wg_cap_log2 = wg_log2 - kWgCapShift;
     {   // slicing needs at most 2^18 slices per owner list (list length <= min(n - 1, nnz))
         const int64_t longest = (int64_t)n - 1 < nnz ? (int64_t)n - 1 : nnz;
         sc.wg_slicing = longest <= ((int64_t)1 << (kMaxSlicesLog2 + sc.wg_cap_log2)) ? 1 : 0;
     }
-    sc.heur_wave_ob = cfg.wave_max_owner > 0 ? ilog2_host(cfg.wave_max_owner) : wave_log2 - 2;
+    // heuristic default: wavefront tables up to a quarter full (linear
+    // probing lengthens quickly above that; the feasibility limit is half)
+    sc.heur_wave_ob = cfg.wave_max_owner > 0 ? ilog2_host(cfg.wave_max_owner) : wave_log2 - 3;
     sc.heur_merge_ob = cfg.merge_max_owner < 0 ? -1 : ilog2_host(cfg.merge_max_owner > 0 ? cfg.merge_max_owner : 7);
     if (sc.heur_merge_ob > kLaneMergeOb) sc.heur_merge_ob = kLaneMergeOb;
     sc.chunk_work = cfg.chunk_work;
