@@ -498,15 +498,6 @@ __device__ __forceinline__ uint32_t search_count(const int32_t *a, int32_t len, 
     return hits;
 }
 
-__device__ __forceinline__ uint32_t bsearch_has(const int32_t *a, int32_t len, int32_t v) {
-    int32_t lo = 0, hi = len;
-    while (lo < hi) {
-        int32_t mid = (lo + hi) >> 1;
-        if (a[mid] < v) lo = mid + 1; else hi = mid;
-    }
-    return (lo < len && a[lo] == v) ? 1u : 0u;
-}
-
 // first index with a[i] >= v (lower) or a[i] > v (upper)
 __device__ __forceinline__ int32_t lower_idx(const int32_t *a, int32_t len, int32_t v) {
     int32_t lo = 0, hi = len;
