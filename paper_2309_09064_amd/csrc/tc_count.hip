@@ -39,6 +39,13 @@ constexpr int32_t kEmpty = -1;
 // owner elements (load 1/8: linear probing stays short); longer owner lists
 // are cut into value-range slices.
 constexpr int kWgCapShift = 3;
+// Claim counters of the intersection pass: kClaimStreams streams (one per
+// XCD), each with a wavefront-item and a lane-group counter in its own
+// 128-byte line after the first kQueueInts ints of the queue block.
+constexpr int kClaimStreams = 8;
+constexpr int kQueueInts = 64;
+constexpr int kClaimStride = 32;
+constexpr int kQueueBlockInts = kQueueInts + kClaimStreams * kClaimStride;
 constexpr int kLaneMergeOb = 4;            // merge items with owner lists below 32: one lane each
 constexpr int kLanePartners = 32;          // row positions per lane item
 
@@ -311,7 +318,9 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
 // Queue layout: workgroup-table buckets first, then the rest; inside each
 // queue larger owners first.  One block: place every bucket's item count at
 // its queue position, exclusive-scan the 4096 positions, read offsets back.
-// q[2] = workgroup items, q[3] = all items.
+// q[2] = workgroup items, q[3] = all items.  (q[0] is the intersection
+// pass's workgroup-item counter; its stream counters follow the first
+// kQueueInts ints.)
 // Three sections: workgroup-table items, then wavefront items, then the
 // lane items (merge strategy with owner lists below 2^(kLaneMergeOb + 1)),
 // which wavefronts take 64 at a time, one per lane.
@@ -1171,13 +1180,31 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         }
     }
 
-    // ---- wavefront items, static round-robin over all wavefronts.  Items
-    // are ordered heavy-first, so each wavefront gets one of the heaviest,
-    // then one of the next, and so on; no shared counter is needed.
+    // ---- wavefront items in queue order (heavy first), claimed one at a
+    // time so that wavefronts finish together: a static round-robin left up
+    // to a fifth of the pass to the slowest wavefronts.  One counter would
+    // serialise the claims, so the items are dealt to kClaimStreams
+    // interleaved streams, one per XCD (blocks are placed on XCDs
+    // round-robin), each with its own counter in its own cache line.  A
+    // claim is issued before the claimed item is needed, hiding the
+    // atomic's latency.
     int32_t *tab = lds + (w << wave_log2);
-    const int32_t G = (int32_t)gridDim.x * kIsectWaves;
     const int32_t n_lane0 = q[4];
-    for (int32_t it = n_wg + (int32_t)blockIdx.x * kIsectWaves + w; it < n_lane0; it += G) {
+    // (fewer streams when the grid has fewer blocks: every stream needs one)
+    const int32_t n_streams = min((int32_t)gridDim.x, kClaimStreams);
+    const int32_t stream = (int32_t)blockIdx.x % n_streams;
+    int32_t *ctr_wave = q + kQueueInts + kClaimStride * stream;
+    int32_t *ctr_lane = ctr_wave + 1;
+    auto claim = [&](int32_t *ctr) {
+        int32_t c = 0;
+        if (l == 0) c = atomicAdd(ctr, 1);
+        return c;
+    };
+    int32_t c_next = __shfl(claim(ctr_wave), 0, kWave);
+    for (;;) {
+        const int32_t it = n_wg + stream + n_streams * c_next;
+        if (it >= n_lane0) break;
+        const int32_t c_pend = claim(ctr_wave);
         const uint64_t t_beg = kProf ? wall_clock64() : 0;
         const Item item = items[it];
         const int kind = item.code & 1;
@@ -1218,10 +1245,16 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             atomicAdd(&pr[0], (unsigned long long)(wall_clock64() - t_beg));
             atomicAdd(&pr[2], 1ull);
         }
+        c_next = __shfl(c_pend, 0, kWave);
     }
 
-    // ---- lane items: groups of 64 consecutive items, one per lane
-    for (int32_t g0 = n_lane0 + ((int32_t)blockIdx.x * kIsectWaves + w) * kWave; g0 < n_all; g0 += G * kWave) {
+    // ---- lane items: groups of 64 consecutive items, one per lane, claimed
+    // like the wavefront items
+    int32_t g_next = __shfl(claim(ctr_lane), 0, kWave);
+    for (;;) {
+        const int32_t g0 = n_lane0 + (stream + n_streams * g_next) * kWave;
+        if (g0 >= n_all) break;
+        const int32_t g_pend = claim(ctr_lane);
         const uint64_t t_beg = kProf ? wall_clock64() : 0;
         const int32_t it = g0 + l;
         int32_t code = 0;
@@ -1243,6 +1276,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
                 atomicAdd(&pr[2], 1ull);
             }
         }
+        g_next = __shfl(g_pend, 0, kWave);
     }
 
     const uint64_t t0 = wave_sum(acc0);
@@ -1325,7 +1359,7 @@ CountLayout carve_count(Carver &c, int32_t n, int64_t nnz) {
     L.bucket_items = c.take<int32_t>(kBuckets + 1);
     L.bucket_off = c.take<int32_t>(kBuckets + 1);
     L.bucket_cur = c.take<int32_t>(kBuckets);
-    L.q = c.take<int32_t>(64);
+    L.q = c.take<int32_t>(kQueueBlockInts);
     L.items = c.take<Item>(item_capacity(n, nnz));
     L.stats = c.take<unsigned long long>(16);
     return L;
@@ -1410,7 +1444,7 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     TC_HIP_TRY(hipMemsetAsync(L.work, 0, sizeof(unsigned long long) * 2 * nn, s));
     TC_HIP_TRY(hipMemsetAsync(L.bucket_items, 0, sizeof(int32_t) * (kBuckets + 1), s));
     TC_HIP_TRY(hipMemsetAsync(L.bucket_cur, 0, sizeof(int32_t) * kBuckets, s));
-    TC_HIP_TRY(hipMemsetAsync(L.q, 0, sizeof(int32_t) * 64, s));
+    TC_HIP_TRY(hipMemsetAsync(L.q, 0, sizeof(int32_t) * kQueueBlockInts, s));
     TC_HIP_TRY(hipMemsetAsync(L.stats, 0, sizeof(unsigned long long) * 16, s));
     if (cfg.tv && n > 0) TC_HIP_TRY(hipMemsetAsync(cfg.tv, 0, sizeof(unsigned long long) * (size_t)n, s));
     if (cfg.sup && nnz > 0) TC_HIP_TRY(hipMemsetAsync(cfg.sup, 0, sizeof(uint32_t) * (size_t)nnz, s));

@@ -271,8 +271,10 @@ def test_schedule_table_entry_point(tc):
 
 def test_learned_schedule_gain_is_measured(tc, sched):
     # what the trained network gains over the heuristic on one graph: the
-    # counts are identical; the ratio of intersection times is reported
-    g = kron(16, seed=11)
+    # counts are identical; the ratio of intersection times is reported and
+    # bounded.  Scale 18: on smaller graphs the whole pass takes a few tenths
+    # of a millisecond, so per-bucket costs measure latency, not throughput.
+    g = kron(18, seed=11)
     rp, col = to_gpu(g)
     lev, _ = tc.bfs_levels(rp, col)
     table, net, ds, losses = sched.learn_schedule([(rp, col, lev)], steps=1500, lr=5e-3)
