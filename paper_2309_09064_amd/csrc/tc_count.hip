@@ -363,17 +363,19 @@ __global__ __launch_bounds__(1024) void k_bucket_order(const int32_t *__restrict
 
 // ---------------------------------------------------------------- probes
 
-// LDS hash table with linear probing over single 32-bit slots.  A key's
-// home slot is a multiplicative hash of the id; a lookup walks from it to
-// the key or to an empty slot.  One 4-byte read per probe spreads a
-// wavefront's 64 random probes over all 32 LDS banks: wider buckets (one
-// 16-byte read per probe) saturate the LDS address unit on this workload.
+// LDS hash table of 2-slot buckets with linear probing over buckets.  A
+// key's home bucket is a multiplicative hash of the id; a lookup reads the
+// bucket (one 8-byte read) and walks on only while the bucket is full
+// without the key.  The bucket width is a measured balance: 16-byte buckets
+// saturate the LDS address unit (a wavefront's 64 random reads fall into 8
+// bank groups), while single slots send about one key in eight past its home
+// slot at load 1/8 against about one in forty here.
 // Tables are sized so at most half the slots are used (1/8 where LDS
-// allows, where about one probe in eight continues past the home slot).
+// allows).
 struct HashTab {
     int32_t *tab;
-    uint32_t mask;    // slots - 1
-    int shift;        // 32 - log2(slots)
+    uint32_t mask;    // buckets - 1 (2 slots a bucket)
+    int shift;        // 32 - log2(buckets)
     uint32_t *cnt;    // per-vertex / per-edge counts: a hit counter per slot, else unused
 };
 
@@ -381,8 +383,8 @@ __device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots, uint32_t
     HashTab t;
     t.tab = tab;
     t.cnt = cnt;
-    t.mask = (1u << lg_slots) - 1;
-    t.shift = 32 - lg_slots;
+    t.mask = (1u << (lg_slots - 1)) - 1;
+    t.shift = 32 - (lg_slots - 1);
     return t;
 }
 
@@ -390,47 +392,52 @@ __device__ __forceinline__ uint32_t home_slot(const HashTab &t, int32_t v) {
     return ((uint32_t)v * 0x9E3779B1u) >> t.shift;
 }
 
-// Keys are distinct, so an insertion only needs an empty slot.
+// Slots of a bucket fill in order: a bucket whose second slot is empty ends
+// every probe sequence through it.
 __device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
     uint32_t b = home_slot(t, v);
-    while (atomicCAS(&t.tab[b], kEmpty, v) != kEmpty) b = (b + 1) & t.mask;
+    for (;;) {
+        if (atomicCAS(&t.tab[2 * b], kEmpty, v) == kEmpty) return;
+        if (atomicCAS(&t.tab[2 * b + 1], kEmpty, v) == kEmpty) return;
+        b = (b + 1) & t.mask;
+    }
 }
 
 // Membership of up to kPer keys (negative = absent slot).  Every key's home
-// slot is read once, unconditionally and interleaved; a key whose home slot
-// holds another key (about one in eight at the tables' load) then follows
-// its probe sequence, one pending key at a time per lane.  Keeping the
-// common case free of per-key predication is what bounds the instruction
-// count: the slowest of a wavefront's keys no longer sets the work of all of
-// them.  With kMask the result is the mask of keys found (bit u for key u)
-// instead of their number; with kSlots as well, slot[u] receives the slot of
-// each key found (per-vertex / per-edge counts credit the slot's counter).
+// bucket is read once, unconditionally and interleaved; a key whose home
+// bucket is full without it (rare at the tables' load) then follows its
+// probe sequence, one pending key at a time per lane.  Keeping the common
+// case free of per-key predication is what bounds the instruction count:
+// the slowest of a wavefront's keys no longer sets the work of all of them.
+// With kMask the result is the mask of keys found (bit u for key u) instead
+// of their number; with kSlots as well, slot[u] receives the slot of each key
+// found (per-vertex / per-edge counts credit the slot's counter).
 template <int kPer, bool kMask = false, bool kSlots = false>
 __device__ __forceinline__ uint32_t hash_probe(const HashTab &t, const int32_t (&v)[kPer], int32_t *slot) {
     uint32_t b[kPer];
-    int32_t q[kPer];
+    int2 q[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) b[u] = home_slot(t, v[u]);
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) q[u] = t.tab[b[u]];
+    for (int u = 0; u < kPer; ++u) q[u] = *reinterpret_cast<const int2 *>(&t.tab[2 * b[u]]);
     uint32_t hits = 0;
-    bool any_pend = false;   // a wavefront mask: no per-lane bits in the common case
+    bool any_pend = false;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int32_t x = v[u];
-        const bool m = q[u] == x;
+        const bool m0 = q[u].x == x, m1 = q[u].y == x;
         const bool live = x >= 0;
-        if constexpr (kMask) hits |= (live & m) ? (1u << u) : 0u;
-        else hits += (live & m) ? 1u : 0u;
-        if constexpr (kSlots) slot[u] = (int32_t)b[u];
-        any_pend |= live & !m & (q[u] != kEmpty);
+        if constexpr (kMask) hits |= (live & (m0 | m1)) ? (1u << u) : 0u;
+        else hits += (live & (m0 | m1)) ? 1u : 0u;
+        if constexpr (kSlots) slot[u] = (int32_t)(2 * b[u] + (m0 ? 0 : 1));
+        any_pend |= live & !(m0 | m1) & (q[u].y != kEmpty);
     }
     if (__ballot(any_pend) == 0) return hits;
     uint32_t pend = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int32_t x = v[u];
-        pend |= ((x >= 0) & (q[u] != x) & (q[u] != kEmpty)) ? (1u << u) : 0u;
+        pend |= ((x >= 0) & (q[u].x != x) & (q[u].y != x) & (q[u].y != kEmpty)) ? (1u << u) : 0u;
     }
     while (pend) {
         const int u = __builtin_ctz(pend);
@@ -444,18 +451,18 @@ __device__ __forceinline__ uint32_t hash_probe(const HashTab &t, const int32_t (
         }
         for (;;) {
             bb = (bb + 1) & t.mask;
-            const int32_t r = t.tab[bb];
-            if (r == x) {
+            const int2 r = *reinterpret_cast<const int2 *>(&t.tab[2 * bb]);
+            if (r.x == x || r.y == x) {
                 if constexpr (kMask) hits |= 1u << u;
                 else ++hits;
                 if constexpr (kSlots) {
 #pragma unroll
                     for (int j = 0; j < kPer; ++j)
-                        if (j == u) slot[j] = (int32_t)bb;
+                        if (j == u) slot[j] = (int32_t)(2 * bb + (r.x == x ? 0 : 1));
                 }
                 break;
             }
-            if (r == kEmpty) break;
+            if (r.y == kEmpty) break;
         }
     }
     return hits;
