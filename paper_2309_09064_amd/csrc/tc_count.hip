@@ -370,7 +370,7 @@ __global__ __launch_bounds__(1024) void k_bucket_order(const int32_t *__restrict
 // saturate the LDS address unit (a wavefront's 64 random reads fall into 8
 // bank groups), while single slots send about one key in eight past its home
 // slot at load 1/8 against about one in forty here.
-// Tables are sized so at most half the slots are used (1/8 where LDS
+// Tables are sized so at most half the slots are used (1/32 where LDS
 // allows).
 struct HashTab {
     int32_t *tab;
@@ -1073,12 +1073,13 @@ __device__ __forceinline__ uint32_t probe_chunk(const Graph &g, int kind, int32_
         return stream_chunk<kRecNone>(g, kind, x, sx, p0, je, scr, WindowCount<Probe>{pr}, sliced, lo, hi);
 }
 
-// Table size for sx keys: load at most 1/8 where the space allows (probe
-// chains then almost never leave the home bucket), never above max_log2;
-// feasibility guarantees load at most 1/2 at the cap.
+// Table size for sx keys: load at most 1/32 where the space allows, never
+// above max_log2 (the LDS region is reserved either way; only the clearing
+// grows, and fewer probes leave their home bucket); feasibility guarantees
+// load at most 1/2 at the cap.
 __device__ __forceinline__ int table_log2(int32_t sx, int max_log2) {
     int lg = 6;   // at least 64 slots
-    while (lg < max_log2 && (1 << lg) < 8 * sx) ++lg;
+    while (lg < max_log2 && (1 << lg) < 32 * sx) ++lg;
     return lg;
 }
 
