@@ -839,11 +839,42 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
 // owner's) with the owner list.  Hits of this lane; in vertex mode every
 // common neighbour w and the partner get their triangles (the owner's are
 // added by the caller), in edge mode the three edges of every triangle.
+// Owners of at most kRegOwner elements (the heuristic's lane items) when
+// only counts are needed: the owner list sits in registers and each partner
+// list (never longer) is loaded with independent loads and compared with
+// all of it, so a partner costs a few load latencies instead of a chain of
+// dependent merge steps.
+constexpr int kRegOwner = 8;
+
+__device__ __forceinline__ uint32_t lane_reg_item(const Graph &g, int kind, int32_t x, int32_t sx, const int32_t *a,
+                                                  int32_t jb, int32_t je) {
+    const int32_t *lists = kind == 0 ? g.c0 : g.c1;
+    int32_t ao[kRegOwner];
+#pragma unroll
+    for (int k = 0; k < kRegOwner; ++k) ao[k] = k < sx ? a[k] : -1;
+    uint32_t hits = 0;
+    for (int32_t p = jb; p < je; ++p) {
+        int32_t sy, yb, y;
+        if (!partner_at(g, kind, x, sx, p, je, sy, yb, y)) continue;   // owned: sx >= sy >= 1
+        const int32_t *b = lists + yb;
+        int32_t bv[kRegOwner];
+#pragma unroll
+        for (int k = 0; k < kRegOwner; ++k) bv[k] = k < sy ? b[k] : -2;
+#pragma unroll
+        for (int i = 0; i < kRegOwner; ++i)
+#pragma unroll
+            for (int j = 0; j < kRegOwner; ++j) hits += ao[i] == bv[j] ? 1u : 0u;
+    }
+    return hits;
+}
+
 template <int kMode>
 __device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, int32_t x, int32_t jb, int32_t je,
                                                     const Sink &sk) {
     const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
     const int32_t sx = list_size(kind, g.up0, g.rp1, x);
+    if constexpr (kMode == kModePlain || kMode == kModeBatch)
+        if (sx <= kRegOwner) return lane_reg_item(g, kind, x, sx, a, jb, je);
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     const int32_t *lpos = kind == 0 ? g.pos0 : g.pos1;   // edge mode only
     const int32_t xb = (int32_t)(a - lists);
