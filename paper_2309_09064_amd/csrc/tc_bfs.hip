@@ -1,10 +1,17 @@
 // BFS levels with the serial semantics of Algorithm 4's first loop: each
-// component is searched from its smallest vertex id.  The roots are found as
-// connected components whose labels converge to the minimum id (links always
-// hook the larger root under the smaller; the sampling-then-finish order of
-// Sutton, Ben-Nun and Bar-Yossef's Afforest), then one multi-source
-// level-synchronous BFS runs from all roots at once.  Hop distances are
-// unique, so the result does not depend on the order of the parallel work.
+// component is searched from its smallest vertex id.  Two passes:
+//  1. the smallest vertex with an edge is necessarily the root of its
+//     component (every smaller id is isolated), and isolated vertices are
+//     their own roots at level 0, so a level-synchronous BFS from that one
+//     vertex labels its component at once (on these graphs the giant
+//     component: all but 0.1% of the vertices with edges);
+//  2. only if vertices are left unvisited, their roots are found as
+//     connected components whose labels converge to the minimum id (links
+//     always hook the larger root under the smaller; the sampling-then-
+//     finish order of Sutton, Ben-Nun and Bar-Yossef's Afforest), restricted
+//     to those vertices, and one multi-source BFS runs from all of them.
+// Hop distances are unique, so the result does not depend on the order of
+// the parallel work.
 #include "tc_internal.hpp"
 
 namespace tc {
@@ -12,7 +19,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kRun = 8;           // CSR entries per thread in edge passes
-constexpr int kSamples = 256;
 
 __device__ __forceinline__ void link(int32_t *comp, int32_t u, int32_t v) {
     int32_t p1 = comp[u], p2 = comp[v];
@@ -27,14 +33,10 @@ __device__ __forceinline__ void link(int32_t *comp, int32_t u, int32_t v) {
     }
 }
 
-__global__ void k_cc_init(int32_t n, int32_t *comp) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        comp[v] = (int32_t)v;
-}
-
 __global__ void k_cc_link_round(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                 int r, int32_t *comp) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        if (comp[v] < 0) continue;   // labelled by the first pass
         int32_t b = rp[v], e = rp[v + 1];
         if (e - b > r) link(comp, (int32_t)v, col[b + r]);
     }
@@ -43,43 +45,15 @@ __global__ void k_cc_link_round(int32_t n, const int32_t *__restrict__ rp, const
 __global__ void k_cc_compress(int32_t n, int32_t *comp) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         int32_t c = comp[v];
+        if (c < 0) continue;   // labelled by the first pass
         while (c != comp[c]) c = comp[c];
         comp[v] = c;
     }
 }
 
-// Most frequent label among kSamples hashed vertices (one block): every
-// thread counts the samples equal to its own, ties go to the smaller label.
-__global__ __launch_bounds__(kSamples) void k_cc_sample_mode(int32_t n, const int32_t *comp, int32_t *giant) {
-    __shared__ int32_t smp[kSamples];
-    __shared__ int64_t best[kSamples / kWave];
-    const int t = threadIdx.x;
-    uint32_t h = (uint32_t)t * 2654435761u + 0x9E3779B9u;
-    h ^= h >> 15;
-    h *= 2246822519u;
-    h ^= h >> 13;
-    smp[t] = comp[(int64_t)h % n];
-    __syncthreads();
-    const int32_t mine = smp[t];
-    int32_t c = 0;
-    for (int i = 0; i < kSamples; ++i) c += smp[i] == mine;
-    // larger count wins, then smaller label: pack as (count, -label)
-    int64_t key = ((int64_t)c << 32) | (uint32_t)(0x7fffffff - mine);
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        int64_t o = __shfl_xor(key, d, kWave);
-        key = o > key ? o : key;
-    }
-    if (lane_id() == 0) best[t / kWave] = key;
-    __syncthreads();
-    if (t == 0) {
-        int64_t b = best[0];
-        for (int i = 1; i < kSamples / kWave; ++i) b = best[i] > b ? best[i] : b;
-        *giant = 0x7fffffff - (int32_t)(b & 0xffffffff);
-    }
-}
-
-// Finish the linking: every edge whose row is outside the sampled giant
-// component, except the first two entries of each row (already linked).
+// Finish the linking: every edge whose row's label is not *skip (the first
+// pass's vertices carry -1), except the first two entries of each row
+// (already linked by the rounds).
 __global__ __launch_bounds__(kThreads) void k_cc_link_rest(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ col, const int32_t *giant,
                                                             int32_t *comp) {
@@ -103,17 +77,65 @@ __global__ __launch_bounds__(kThreads) void k_cc_link_rest(int32_t n, int64_t nn
     }
 }
 
-// Level 0: the roots (label == own id); every other vertex starts unvisited.
-__global__ void k_bfs_init(int32_t n, const int32_t *__restrict__ comp, int32_t *__restrict__ lev) {
+// The smallest vertex with an edge (*first starts above n): a wavefront
+// minimum, then one atomic per wavefront (one per vertex would serialise on
+// the address).
+__global__ void k_first_active(int32_t n, const int32_t *__restrict__ rp, int32_t *first) {
+    int32_t best = INT32_MAX;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        lev[v] = comp[v] == (int32_t)v ? 0 : -1;
+        if (rp[v + 1] > rp[v]) {
+            best = (int32_t)v;
+            break;   // later vertices of this thread are larger
+        }
+    for (int d = kWave / 2; d > 0; d >>= 1) best = min(best, __shfl_xor(best, d, kWave));
+    if (lane_id() == 0 && best != INT32_MAX) atomicMin(first, best);
 }
 
-// Frontier of `level`: flag[v] = 1 for vertices on that level with an edge.
-__global__ void k_level_flags(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ lev,
-                              int32_t level, int32_t *__restrict__ flag) {
+// Finish the linking of a small second pass: a thread per vertex of the pass
+// links the rest of its row (entries from the third; the rounds linked the
+// first two).  For a large second pass the tiled k_cc_link_rest is used.
+__global__ void k_cc_link_rows(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                               int32_t *comp) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        if (comp[v] < 0) continue;   // labelled by the first pass
+        for (int32_t e = rp[v] + 2; e < rp[v + 1]; ++e) link(comp, (int32_t)v, col[e]);
+    }
+}
+
+// First pass, level 0: that vertex and every isolated vertex; the rest
+// starts unvisited.
+__global__ void k_bfs_init_first(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ first,
+                                 int32_t *__restrict__ lev) {
+    const int32_t f = *first;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        flag[v] = lev[v] == level && rp[v + 1] > rp[v];
+        lev[v] = ((int32_t)v == f || rp[v + 1] == rp[v]) ? 0 : -1;
+}
+
+// Unvisited vertices after the first pass: their count, and their labels for
+// the second pass (own id; -1 marks the first pass's vertices).
+__global__ void k_rest_init(int32_t n, const int32_t *__restrict__ lev, int32_t *__restrict__ comp,
+                            int32_t *__restrict__ count) {
+    int32_t c = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const bool rest = lev[v] < 0;
+        comp[v] = rest ? (int32_t)v : -1;
+        c += rest;
+    }
+    if (c) atomicAdd(count, c);
+}
+
+// Second pass, level 0: the roots (label == own id) among the unvisited.
+__global__ void k_bfs_init_rest(int32_t n, const int32_t *__restrict__ comp, int32_t *__restrict__ lev) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        if (comp[v] == (int32_t)v) lev[v] = 0;
+}
+
+// Frontier of `level`: flag[v] = 1 for vertices on that level with an edge
+// (in the second pass, only those of the pass: comp[v] >= 0).
+__global__ void k_level_flags(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ lev,
+                              int32_t level, const int32_t *__restrict__ only, int32_t *__restrict__ flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        flag[v] = lev[v] == level && rp[v + 1] > rp[v] && (only == nullptr || only[v] >= 0);
 }
 
 __global__ void k_compact(int32_t n, const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
@@ -247,55 +269,81 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
     DeviceInfo di;
     TC_TRY(device_info(&di));
     const unsigned gv = grid_for(n, kThreads);
-    hipLaunchKernelGGL(k_cc_init, dim3(gv), dim3(kThreads), 0, s, n, L.comp);
-    for (int r = 0; r < 2; ++r) {
-        hipLaunchKernelGGL(k_cc_link_round, dim3(gv), dim3(kThreads), 0, s, n, rp, col, r, L.comp);
-        hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(kThreads), 0, s, n, L.comp);
-    }
-    hipLaunchKernelGGL(k_cc_sample_mode, dim3(1), dim3(kSamples), 0, s, n, L.comp, L.giant);
-    if (nnz > 0) {
-        const unsigned ge = grid_for((nnz + kRun - 1) / kRun, kThreads, (int64_t)di.cus * 8);
-        hipLaunchKernelGGL(k_cc_link_rest, dim3(ge), dim3(kThreads), 0, s, n, nnz, rp, col, L.giant, L.comp);
-    }
-    hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(kThreads), 0, s, n, L.comp);
-    TC_HIP_TRY(hipGetLastError());
-
-    hipLaunchKernelGGL(k_bfs_init, dim3(gv), dim3(kThreads), 0, s, n, L.comp, lev);
-    TC_HIP_TRY(hipGetLastError());
     Mailbox mb;
     TC_TRY(mailbox(&mb));
-    int32_t level = 0, rounds = 0;
     const unsigned gb = grid_for(n, kThreads, (int64_t)di.cus * 8);
-    for (;;) {
-        // frontier of `level` (vertices with an edge), compacted in id order
-        hipLaunchKernelGGL(k_level_flags, dim3(gv), dim3(kThreads), 0, s, n, rp, lev, level, L.flag);
-        TC_HIP_TRY(hipGetLastError());
-        TC_TRY(scan_exclusive_i32_to_i32(L.flag, L.pos, n, L.scan, s));
-        TC_TRY(mail_i32(L.pos + n, mb.dev, s));
-        TC_HIP_TRY(hipStreamSynchronize(s));
-        const int32_t f = (int32_t)mb.host[0];
-        if (f == 0) break;
-        ++rounds;
-        if ((int64_t)f * 16 > (int64_t)n) {
-            // large frontier: bottom-up, every unvisited vertex checks its row
-            hipLaunchKernelGGL(k_bfs_bottom_up, dim3(gb), dim3(kThreads), 0, s, n, rp, col, level, lev);
+    int32_t rounds = 0;
+    // level-synchronous BFS from the vertices at level 0 (restricted to
+    // only[v] >= 0 when `only` is given); returns the number of expansions
+    auto level_loop = [&](const int32_t *only, int32_t *levels_out) -> int {
+        int32_t level = 0;
+        for (;;) {
+            // frontier of `level` (vertices with an edge), compacted in id order
+            hipLaunchKernelGGL(k_level_flags, dim3(gv), dim3(kThreads), 0, s, n, rp, lev, level, only, L.flag);
             TC_HIP_TRY(hipGetLastError());
-        } else {
-            hipLaunchKernelGGL(k_compact, dim3(gv), dim3(kThreads), 0, s, n, L.flag, L.pos, L.front);
-            hipLaunchKernelGGL(k_front_deg, dim3(grid_for(f, kThreads)), dim3(kThreads), 0, s, f, L.front, rp,
-                               L.fdeg);
-            TC_HIP_TRY(hipGetLastError());
-            TC_TRY(scan_exclusive_i32_to_i64(L.fdeg, L.fpre, f, L.scan, s));
-            hipLaunchKernelGGL(k_bfs_expand, dim3((unsigned)di.cus * 8), dim3(kThreads), 0, s, f, L.front, L.fpre,
-                               rp, col, level + 1, lev);
-            TC_HIP_TRY(hipGetLastError());
+            TC_TRY(scan_exclusive_i32_to_i32(L.flag, L.pos, n, L.scan, s));
+            TC_TRY(mail_i32(L.pos + n, mb.dev, s));
+            TC_HIP_TRY(hipStreamSynchronize(s));
+            const int32_t f = (int32_t)mb.host[0];
+            if (f == 0) break;
+            ++rounds;
+            if ((int64_t)f * 16 > (int64_t)n) {
+                // large frontier: bottom-up, every unvisited vertex checks its row
+                hipLaunchKernelGGL(k_bfs_bottom_up, dim3(gb), dim3(kThreads), 0, s, n, rp, col, level, lev);
+                TC_HIP_TRY(hipGetLastError());
+            } else {
+                hipLaunchKernelGGL(k_compact, dim3(gv), dim3(kThreads), 0, s, n, L.flag, L.pos, L.front);
+                hipLaunchKernelGGL(k_front_deg, dim3(grid_for(f, kThreads)), dim3(kThreads), 0, s, f, L.front, rp,
+                                   L.fdeg);
+                TC_HIP_TRY(hipGetLastError());
+                TC_TRY(scan_exclusive_i32_to_i64(L.fdeg, L.fpre, f, L.scan, s));
+                hipLaunchKernelGGL(k_bfs_expand, dim3((unsigned)di.cus * 8), dim3(kThreads), 0, s, f, L.front,
+                                   L.fpre, rp, col, level + 1, lev);
+                TC_HIP_TRY(hipGetLastError());
+            }
+            ++level;
         }
-        ++level;
+        // `level` is the number of expansions; the last one found nothing
+        // unless no vertex has an edge, so the deepest level is level - 1
+        *levels_out = level > 0 ? level : 1;
+        return TC_OK;
+    };
+
+    // pass 1: from the smallest vertex with an edge, isolated vertices at 0
+    TC_HIP_TRY(hipMemsetAsync(L.giant, 0x7f, sizeof(int32_t), s));   // above any vertex id
+    hipLaunchKernelGGL(k_first_active, dim3(gv), dim3(kThreads), 0, s, n, rp, L.giant);
+    hipLaunchKernelGGL(k_bfs_init_first, dim3(gv), dim3(kThreads), 0, s, n, rp, L.giant, lev);
+    TC_HIP_TRY(hipGetLastError());
+    int32_t levels1 = 1, levels2 = 1;
+    TC_TRY(level_loop(nullptr, &levels1));
+
+    // pass 2: the components the first pass did not reach
+    TC_HIP_TRY(hipMemsetAsync(L.giant + 1, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_rest_init, dim3(gb), dim3(kThreads), 0, s, n, lev, L.comp, L.giant + 1);
+    TC_HIP_TRY(hipGetLastError());
+    TC_TRY(mail_i32(L.giant + 1, mb.dev, s));
+    TC_HIP_TRY(hipStreamSynchronize(s));
+    if (mb.host[0] > 0) {
+        for (int r = 0; r < 2; ++r) {
+            hipLaunchKernelGGL(k_cc_link_round, dim3(gv), dim3(kThreads), 0, s, n, rp, col, r, L.comp);
+            hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(kThreads), 0, s, n, L.comp);
+        }
+        if ((int64_t)mb.host[0] * 64 < (int64_t)n) {
+            hipLaunchKernelGGL(k_cc_link_rows, dim3(gv), dim3(kThreads), 0, s, n, rp, col, L.comp);
+        } else if (nnz > 0) {
+            // rows of the first pass carry label -1: pass that label as the one to skip
+            TC_HIP_TRY(hipMemsetAsync(L.giant + 2, 0xff, sizeof(int32_t), s));
+            const unsigned ge = grid_for((nnz + kRun - 1) / kRun, kThreads, (int64_t)di.cus * 8);
+            hipLaunchKernelGGL(k_cc_link_rest, dim3(ge), dim3(kThreads), 0, s, n, nnz, rp, col, L.giant + 2,
+                               L.comp);
+        }
+        hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(kThreads), 0, s, n, L.comp);
+        hipLaunchKernelGGL(k_bfs_init_rest, dim3(gv), dim3(kThreads), 0, s, n, L.comp, lev);
+        TC_HIP_TRY(hipGetLastError());
+        TC_TRY(level_loop(L.comp, &levels2));
     }
-    // `level` is the number of expansions; the last one found nothing unless
-    // no vertex has an edge, so the deepest level equals level - 1 (or 0).
     if (out) {
-        out->levels = level > 0 ? level : 1;
+        out->levels = levels1 > levels2 ? levels1 : levels2;
         out->rounds = rounds;
     }
     return TC_OK;
