@@ -47,7 +47,17 @@ constexpr int kQueueInts = 64;
 constexpr int kClaimStride = 32;
 constexpr int kQueueBlockInts = kQueueInts + kClaimStreams * kClaimStride;
 constexpr int kLaneMergeOb = 4;            // merge items with owner lists below 32: one lane each
-constexpr int kLanePartners = 32;          // row positions per lane item
+constexpr int kLanePartners = 32;          // row positions per lane item (owner classes 0-2)
+
+// Row positions per lane item of owner class ob.  A lane walks both lists
+// of each of its partners in turn, up to 2^(ob+2) steps per partner, and its
+// wavefront holds the group of 64 items until the slowest lane is done, so
+// the partner count halves per class above 2: every lane's walk stays within
+// about 512 steps.  Per-element cost profiles cannot see such a walk's
+// latency, only its share of the wavefront's time.
+__host__ __device__ constexpr int lane_partners(int ob) {
+    return ob <= 2 ? kLanePartners : kLanePartners >> (ob - 2);
+}
 
 struct Item {
     int32_t owner;
@@ -253,8 +263,10 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
         int64_t cap = (je - jb + minp - 1) / minp;
         if (nsl > 1) cap = (cap + nsl - 1) / nsl;
         if (nch > cap) nch = cap;
-        if (s == TC_STRAT_MERGE && ((b >> 5) & 31) <= kLaneMergeOb)   // one lane walks an item's partners
-            nch = (je - jb + kLanePartners - 1) / kLanePartners;
+        if (s == TC_STRAT_MERGE && ((b >> 5) & 31) <= kLaneMergeOb) {   // one lane walks an item's partners
+            const int lp = lane_partners((b >> 5) & 31);
+            nch = (je - jb + lp - 1) / lp;
+        }
         if (nch < 1) nch = 1;
         bk[k] = b;
         st[k] = s;
@@ -1384,6 +1396,8 @@ struct CountLayout {
     Item *items;
     unsigned long long *stats;   // [0..6] unit stats, [8..9] T0/T1
 };
+
+static_assert(lane_partners(kLaneMergeOb) >= kMinPartnersPerItem, "lane items must respect the item capacity");
 
 int64_t item_capacity(int32_t n, int64_t nnz) {
     // per unit: at most ceil(|N0(x)| / kMinPartnersPerItem) items
