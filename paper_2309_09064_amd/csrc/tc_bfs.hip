@@ -77,10 +77,15 @@ __global__ __launch_bounds__(kThreads) void k_cc_link_rest(int32_t n, int64_t nn
     }
 }
 
-// The smallest vertex with an edge (*first starts above n): a wavefront
-// minimum, then one atomic per wavefront (one per vertex would serialise on
-// the address).
-__global__ void k_first_active(int32_t n, const int32_t *__restrict__ rp, int32_t *first) {
+// The smallest vertex with an edge (*first starts above n).  Launched on at
+// most kFirstBlocks blocks that stride over the vertices: each thread stops
+// at its first vertex with an edge, the block takes the minimum, and one
+// atomic per block follows (one per wavefront over a vertex-sized grid
+// serialised some 16K atomics on the one word).
+constexpr int kFirstBlocks = 256;
+__global__ __launch_bounds__(kThreads) void k_first_active(int32_t n, const int32_t *__restrict__ rp,
+                                                            int32_t *first) {
+    __shared__ int32_t s_min[kThreads / kWave];
     int32_t best = INT32_MAX;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
         if (rp[v + 1] > rp[v]) {
@@ -88,7 +93,12 @@ __global__ void k_first_active(int32_t n, const int32_t *__restrict__ rp, int32_
             break;   // later vertices of this thread are larger
         }
     for (int d = kWave / 2; d > 0; d >>= 1) best = min(best, __shfl_xor(best, d, kWave));
-    if (lane_id() == 0 && best != INT32_MAX) atomicMin(first, best);
+    if (lane_id() == 0) s_min[threadIdx.x / kWave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / kWave; ++w) best = min(best, s_min[w]);
+        if (best != INT32_MAX) atomicMin(first, best);
+    }
 }
 
 // Finish the linking of a small second pass: a thread per vertex of the pass
@@ -311,7 +321,7 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
 
     // pass 1: from the smallest vertex with an edge, isolated vertices at 0
     TC_HIP_TRY(hipMemsetAsync(L.giant, 0x7f, sizeof(int32_t), s));   // above any vertex id
-    hipLaunchKernelGGL(k_first_active, dim3(gv), dim3(kThreads), 0, s, n, rp, L.giant);
+    hipLaunchKernelGGL(k_first_active, dim3(gv < kFirstBlocks ? gv : kFirstBlocks), dim3(kThreads), 0, s, n, rp, L.giant);
     hipLaunchKernelGGL(k_bfs_init_first, dim3(gv), dim3(kThreads), 0, s, n, rp, L.giant, lev);
     TC_HIP_TRY(hipGetLastError());
     int32_t levels1 = 1, levels2 = 1;
