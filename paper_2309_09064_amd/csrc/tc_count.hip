@@ -387,7 +387,7 @@ __global__ __launch_bounds__(1024) void k_bucket_order(const int32_t *__restrict
 struct HashTab {
     int32_t *tab;
     uint32_t mask;    // buckets - 1 (2 slots a bucket)
-    int shift;        // 32 - log2(buckets)
+    int off, bits;    // home bucket: bits [off, off + bits) of the 24-bit product, bits = log2(buckets)
     uint32_t *cnt;    // per-vertex / per-edge counts: a hit counter per slot, else unused
 };
 
@@ -396,12 +396,19 @@ __device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots, uint32_t
     t.tab = tab;
     t.cnt = cnt;
     t.mask = (1u << (lg_slots - 1)) - 1;
-    t.shift = 32 - (lg_slots - 1);
+    t.bits = lg_slots - 1;
+    t.off = 24 - t.bits;
     return t;
 }
 
+// Fibonacci hashing on a 2^24 ring: the top log2(buckets) bits of
+// (v * floor(2^24 / golden ratio)) mod 2^24.  The 24-bit multiply and the
+// field extract both issue at full rate, where a 32-bit multiply takes four
+// passes; ids of 2^24 and above share the hash of their low 24 bits, which
+// only lengthens probe sequences.
 __device__ __forceinline__ uint32_t home_slot(const HashTab &t, int32_t v) {
-    return ((uint32_t)v * 0x9E3779B1u) >> t.shift;
+    const uint32_t p = (uint32_t)__umul24((uint32_t)v, 0x9E3779u);
+    return __builtin_amdgcn_ubfe(p, (uint32_t)t.off, (uint32_t)t.bits);
 }
 
 // Slots of a bucket fill in order: a bucket whose second slot is empty ends
