@@ -172,7 +172,21 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
                 n0 = n1 = 0;
                 w0 = w1 = 0;
             };
-            for (int64_t e = e0; e < e1; ++e) {
+            // the run's partners and their list sizes, issued before the
+            // row walk (two memory latencies per thread, not per entry)
+            int32_t y[kRun];
+            int2 sy[kRun];
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? c0[e0 + k] : 0;
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const int4 ry = e0 + k < e1 ? vrec[y[k]] : make_int4(0, 0, 0, 0);
+                sy[k] = make_int2(ry.y, ry.w);
+            }
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const int64_t e = e0 + k;
+                if (e >= e1) break;
                 while (e >= xe) {
                     flush();
                     ++x;
@@ -180,11 +194,8 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
                     s0x = up0[x];
                     s1x = rp1[x + 1] - rp1[x];
                 }
-                const int32_t y = c0[e];
-                const int4 ry = vrec[y];
-                const int32_t s0y = ry.y, s1y = ry.w;
-                if (owns(s0x, s0y, (int32_t)x, y)) { ++n0; w0 += (unsigned)s0y; }
-                if (owns(s1x, s1y, (int32_t)x, y)) { ++n1; w1 += (unsigned)s1y; }
+                if (owns(s0x, sy[k].x, (int32_t)x, y[k])) { ++n0; w0 += (unsigned)sy[k].x; }
+                if (owns(s1x, sy[k].y, (int32_t)x, y[k])) { ++n1; w1 += (unsigned)sy[k].y; }
             }
             flush();
         }

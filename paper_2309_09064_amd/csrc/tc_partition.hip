@@ -78,6 +78,15 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
             }
             ch = cu = 0;
         };
+        // the run's neighbour ids, then their records, all issued before
+        // the row walk: two memory latencies per thread instead of two per
+        // entry
+        int32_t y[kRun];
+        int2 iy[kRun];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? col[e0 + k] : 0;
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) iy[k] = e0 + k < e1 ? vld[y[k]] : make_int2(0, 0);
         uint8_t f[kRun];
 #pragma unroll
         for (int k = 0; k < kRun; ++k) f[k] = 0;
@@ -92,10 +101,8 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
                     lx = vld[x].x;
                     dx = (int32_t)(xe - rp[x]);
                 }
-                const int32_t y = col[e];
-                const int2 iy = vld[y];
-                const bool hor = iy.x == lx;
-                const bool up = hor && rank_above(iy.y, y, (int32_t)x, dx);
+                const bool hor = iy[k].x == lx;
+                const bool up = hor && rank_above(iy[k].y, y[k], (int32_t)x, dx);
                 f[k] = (uint8_t)(hor | (up << 1));
                 ch += hor;
                 cu += up;
