@@ -207,21 +207,30 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
     if (e0 >= e1) return;
     int64_t H = (int64_t)bh_off[blockIdx.x] + (before >> 32);
     int64_t U = (int64_t)bu_off[blockIdx.x] + (before & 0xffffffffll);
+    int32_t y[kRun];   // issued before the row walk
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? col[e0 + k] : 0;
     int64_t x = row_of(rp, rows[0], rows[1], e0);
     int64_t xe = rp[x + 1];
+    // N0+ entries of row x go to rp0[x] + (U - rpu[x]), the rest of its
+    // horizontal entries to H - U + rpu[x + 1]: two per-row terms
+    int64_t up_base = (int64_t)rp0[x] - rpu[x], lo_base = rpu[x + 1];
 #pragma unroll
     for (int k = 0; k < kRun; ++k) {
         const int64_t e = e0 + k;
         if (e < e1) {
-            while (e >= xe) { ++x; xe = rp[x + 1]; }
+            if (e >= xe) {
+                do { ++x; xe = rp[x + 1]; } while (e >= xe);
+                up_base = (int64_t)rp0[x] - rpu[x];
+                lo_base = rpu[x + 1];
+            }
             const uint8_t fe = f[k];
-            const int32_t y = col[e];
             if (fe & 1) {
-                const int64_t d = (fe & 2) ? (int64_t)rp0[x] + U - rpu[x] : H - U + rpu[x + 1];
-                c0[d] = y;
+                const int64_t d = (fe & 2) ? up_base + U : H - U + lo_base;
+                c0[d] = y[k];
                 if (kPos) pos0[d] = (int32_t)e;
             } else {
-                c1[e - H] = y;
+                c1[e - H] = y[k];
                 if (kPos) pos1[e - H] = (int32_t)e;
             }
             H += fe & 1;
