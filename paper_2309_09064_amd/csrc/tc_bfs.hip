@@ -141,11 +141,47 @@ __global__ void k_bfs_init_rest(int32_t n, const int32_t *__restrict__ comp, int
 }
 
 // Frontier of `level`: flag[v] = 1 for vertices on that level with an edge
-// (in the second pass, only those of the pass: comp[v] >= 0).
-__global__ void k_level_flags(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ lev,
-                              int32_t level, const int32_t *__restrict__ only, int32_t *__restrict__ flag) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        flag[v] = lev[v] == level && rp[v + 1] > rp[v] && (only == nullptr || only[v] >= 0);
+// (in the second pass, only those of the pass: comp[v] >= 0).  Each block
+// also writes the degree sum of its frontier vertices to part[blockIdx.x]
+// (launched on at most kFlagBlocks blocks; k_front_mail adds them up).
+constexpr int kFlagBlocks = 1024;
+__global__ __launch_bounds__(kThreads) void k_level_flags(int32_t n, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ lev, int32_t level,
+                                                           const int32_t *__restrict__ only,
+                                                           int32_t *__restrict__ flag,
+                                                           unsigned long long *__restrict__ part) {
+    __shared__ unsigned long long s_sum[kThreads / kWave];
+    unsigned long long d = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t deg = rp[v + 1] - rp[v];
+        const bool in = lev[v] == level && deg > 0 && (only == nullptr || only[v] >= 0);
+        flag[v] = in;
+        d += in ? (unsigned long long)deg : 0ull;
+    }
+    d = wave_sum(d);
+    if (lane_id() == 0) s_sum[threadIdx.x / kWave] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / kWave; ++w) d += s_sum[w];
+        part[blockIdx.x] = d;
+    }
+}
+
+// Mailbox: dst[0] = frontier size (the flag scan's total), dst[1] = the
+// frontier's degree sum (the blocks' partial sums).  One block.
+__global__ __launch_bounds__(kThreads) void k_front_mail(const unsigned long long *__restrict__ part, int nparts,
+                                                          const int32_t *__restrict__ fsize, uint64_t *dst) {
+    __shared__ unsigned long long s_sum[kThreads / kWave];
+    unsigned long long d = 0;
+    for (int i = threadIdx.x; i < nparts; i += kThreads) d += part[i];
+    d = wave_sum(d);
+    if (lane_id() == 0) s_sum[threadIdx.x / kWave] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / kWave; ++w) d += s_sum[w];
+        dst[0] = (uint64_t)(int64_t)fsize[0];
+        dst[1] = d;
+    }
 }
 
 __global__ void k_compact(int32_t n, const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
@@ -243,6 +279,7 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65536) {
 struct BfsLayout {
     int32_t *comp, *front, *flag, *pos, *fdeg, *giant;
     int64_t *fpre;
+    unsigned long long *part;   // per-block frontier degree sums
     void *scan;
 };
 
@@ -256,6 +293,7 @@ BfsLayout carve_bfs(Carver &c, int32_t n) {
     L.fdeg = c.take<int32_t>(nn);
     L.fpre = c.take<int64_t>(nn + 1);
     L.giant = c.take<int32_t>(64);
+    L.part = c.take<unsigned long long>(kFlagBlocks);
     L.scan = c.take<char>(scan_ws_bytes(nn));
     return L;
 }
@@ -285,19 +323,31 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
     int32_t rounds = 0;
     // level-synchronous BFS from the vertices at level 0 (restricted to
     // only[v] >= 0 when `only` is given); returns the number of expansions
+    // Direction switch after Beamer, Asanovic and Patterson's
+    // direction-optimising BFS: bottom-up once the frontier's edges exceed
+    // 1/kAlpha of the edges not yet explored, or the frontier holds more
+    // than n/16 vertices.  Every choice gives the same levels.
+    constexpr int64_t kAlpha = 14;
+    int64_t m_unexplored = nnz;   // across both passes: the second starts with the rest's edges
+    const unsigned gf = gv < kFlagBlocks ? gv : kFlagBlocks;
     auto level_loop = [&](const int32_t *only, int32_t *levels_out) -> int {
         int32_t level = 0;
         for (;;) {
             // frontier of `level` (vertices with an edge), compacted in id order
-            hipLaunchKernelGGL(k_level_flags, dim3(gv), dim3(kThreads), 0, s, n, rp, lev, level, only, L.flag);
+            hipLaunchKernelGGL(k_level_flags, dim3(gf), dim3(kThreads), 0, s, n, rp, lev, level, only, L.flag,
+                               L.part);
             TC_HIP_TRY(hipGetLastError());
             TC_TRY(scan_exclusive_i32_to_i32(L.flag, L.pos, n, L.scan, s));
-            TC_TRY(mail_i32(L.pos + n, mb.dev, s));
+            hipLaunchKernelGGL(k_front_mail, dim3(1), dim3(kThreads), 0, s, L.part, (int)gf, L.pos + n, mb.dev);
+            TC_HIP_TRY(hipGetLastError());
             TC_HIP_TRY(hipStreamSynchronize(s));
             const int32_t f = (int32_t)mb.host[0];
+            const int64_t m_front = (int64_t)mb.host[1];
             if (f == 0) break;
             ++rounds;
-            if ((int64_t)f * 16 > (int64_t)n) {
+            const bool bottom_up = m_front * kAlpha > m_unexplored || (int64_t)f * 16 > (int64_t)n;
+            m_unexplored -= m_front;
+            if (bottom_up) {
                 // large frontier: bottom-up, every unvisited vertex checks its row
                 hipLaunchKernelGGL(k_bfs_bottom_up, dim3(gb), dim3(kThreads), 0, s, n, rp, col, level, lev);
                 TC_HIP_TRY(hipGetLastError());
