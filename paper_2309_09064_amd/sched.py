@@ -19,6 +19,9 @@ schedule only decides speed.  The cycle:
 4. ``CostNet.schedule``: per bucket the cheapest feasible strategy by the
    network's prediction (``tc_mlp_schedule``), a table that
    ``Options(sched_table=...)`` hands to ``tc_count``.
+5. ``verify_schedule``: the table's changes against the heuristic, one class
+   (heuristic strategy -> proposed strategy) at a time, are kept only where
+   the measured pass is faster with them.
 
 Every numeric step of the network runs in the library's HIP kernels; this
 module marshals arguments and turns profile counters into training rows.
@@ -190,16 +193,69 @@ def dataset(profile: torch.Tensor, min_elements: int = 1 << 14, weight_power: fl
                    elements=e, w=w.astype(np.float32))
 
 
+def isect_ms(graphs, table: np.ndarray | None, options: Options | None = None, runs: int = 7) -> float:
+    """Intersection-pass time (HIP events, median of ``runs`` after one
+    warm-up) summed over the graphs, under ``table`` (None: the heuristic)."""
+    base = options or Options()
+    total = 0.0
+    for g in graphs:
+        rp, col = g[0], g[1]
+        lev = g[2] if len(g) > 2 else None
+        t = None if table is None else torch.from_numpy(np.ascontiguousarray(table, dtype=np.int32)).to(rp.device)
+        o = Options(**{**base.__dict__, "timing": True, "force_strategy": -1, "sched_table": t})
+        cnt = Counter(rp.numel() - 1, col.numel(), o, rp.device)
+        cnt(rp, col, lev)
+        total += float(np.median([cnt(rp, col, lev).ms["isect"] for _ in range(runs)]))
+    return total
+
+
+def verify_schedule(graphs, table, options: Options | None = None, runs: int = 7, margin: float = 0.01):
+    """Measured check of a proposed table on the graphs it was learned from.
+
+    Per-bucket costs measured one bucket group at a time do not add up to
+    the pass's wall time (a bucket's items can end up on the critical path),
+    so each class of change, (heuristic strategy a -> proposed strategy b),
+    is tried on its own: a class is reverted to the heuristic's choice when
+    the pass runs faster without it (by more than ``margin``).  If the
+    result is still not faster than the heuristic, the heuristic's table is
+    returned.  Returns (table as an int32 device tensor, {"heuristic_ms",
+    "proposed_ms", "ms", "reverted": [(a, b), ...]})."""
+    rp0, col0 = graphs[0][0], graphs[0][1]
+    heur = schedule_table(rp0.numel() - 1, col0.numel(), Options(**{**(options or Options()).__dict__,
+                                                                   "sched_table": None}), rp0.device).cpu().numpy()
+    cur = (table.cpu().numpy() if isinstance(table, torch.Tensor) else np.asarray(table)).astype(np.int32)
+    t_heur = isect_ms(graphs, None, options, runs)
+    t_prop = t_cur = isect_ms(graphs, cur, options, runs)
+    reverted = []
+    for a, b in sorted({(int(x), int(y)) for x, y in zip(heur, cur) if x != y}):
+        trial = cur.copy()
+        trial[(heur == a) & (cur == b)] = a
+        t = isect_ms(graphs, trial, options, runs)
+        if t < t_cur * (1.0 - margin):
+            cur, t_cur = trial, t
+            reverted.append((a, b))
+    if t_cur >= t_heur:
+        cur, t_cur = heur.astype(np.int32), t_heur
+    info = {"heuristic_ms": t_heur, "proposed_ms": t_prop, "ms": t_cur, "reverted": reverted}
+    return torch.from_numpy(np.ascontiguousarray(cur)).to(rp0.device), info
+
+
 def learn_schedule(graphs, options: Options | None = None, seed: int = 0, steps: int = 3000, lr: float = 1e-2,
-                   repeats: int = 1, min_elements: int = 1 << 14, weight_power: float = 1.0):
-    """Profile, train, schedule.  Returns (table, net, dataset, losses)."""
+                   repeats: int = 1, min_elements: int = 1 << 14, weight_power: float = 1.0, verify: bool = True):
+    """Profile, train, schedule and (with ``verify``) check the table by
+    measurement on the same graphs (``verify_schedule``).  Returns (table,
+    net, dataset, losses); the network's own table is ``net.schedule()``."""
     prof = collect_profile(graphs, options, repeats=repeats)
     ds = dataset(prof, min_elements, weight_power)
     if len(ds.c) == 0:
         raise ValueError("the profile holds no bucket with enough work to learn from")
     net = CostNet(seed=seed)
     losses = net.train(ds.X, ds.c, ds.t, steps, lr=lr, w=ds.w)
-    return net.schedule(options), net, ds, losses
+    table = net.schedule(options)
+    if verify:
+        table, _ = verify_schedule(graphs, table, options)
+    return table, net, ds, losses
 
 
-__all__ = ["CostNet", "Dataset", "bucket_features", "collect_profile", "dataset", "learn_schedule", "TCError"]
+__all__ = ["CostNet", "Dataset", "bucket_features", "collect_profile", "dataset", "isect_ms", "learn_schedule",
+           "verify_schedule", "TCError"]

@@ -228,7 +228,8 @@ def test_profile_accumulates(tc):
 
 def test_learned_schedule_counts_exactly(tc, sched):
     train = [to_gpu(kron(13, seed=s)) for s in (2, 3)]
-    table, net, ds, losses = sched.learn_schedule(train, steps=300, min_elements=1024)
+    # the network's own table (verify=False): any table must count exactly
+    table, net, ds, losses = sched.learn_schedule(train, steps=300, min_elements=1024, verify=False)
     assert len(ds.c) > 10 and losses[-1] < losses[0]
     t = table.cpu().numpy()
     assert t.shape == (2048,) and np.all((t >= 0) & (t < 4))
@@ -270,25 +271,23 @@ def test_schedule_table_entry_point(tc):
 
 
 def test_learned_schedule_gain_is_measured(tc, sched):
-    # what the trained network gains over the heuristic on one graph: the
-    # counts are identical; the ratio of intersection times is reported and
-    # bounded.  Scale 18: on smaller graphs the whole pass takes a few tenths
-    # of a millisecond, so per-bucket costs measure latency, not throughput.
+    # what the trained network gains over the heuristic on one graph.  The
+    # network proposes a table; verify_schedule keeps only the classes of
+    # change that measure faster.  Counts are identical under every table;
+    # the verified table is not slower than the heuristic beyond timing
+    # noise.  Scale 18: on smaller graphs the whole pass takes a few tenths of
+    # a millisecond, so per-bucket costs measure latency, not throughput.
     g = kron(18, seed=11)
     rp, col = to_gpu(g)
     lev, _ = tc.bfs_levels(rp, col)
-    table, net, ds, losses = sched.learn_schedule([(rp, col, lev)], steps=1500, lr=5e-3)
-
-    def isect_ms(opts):
-        c = tc.Counter(g.n, g.nnz, opts)
-        ms = []
-        for _ in range(6):
-            r = c(rp, col, lev)
-            ms.append(r.ms["isect"])
-        return r.T, float(np.median(ms[1:]))
-
-    Th, th = isect_ms(tc.Options(timing=True))
-    Tl, tl = isect_ms(tc.Options(timing=True, sched_table=table))
-    assert Th == Tl == oracle.alg4(g).T
-    print(f"\nlearned / heuristic intersection time: {tl / th:.3f} ({tl:.3f} ms vs {th:.3f} ms)")
-    assert tl < 1.5 * th
+    gs = [(rp, col, lev)]
+    proposed, net, ds, losses = sched.learn_schedule(gs, steps=1500, lr=5e-3, verify=False)
+    table, info = sched.verify_schedule(gs, proposed)
+    T = oracle.alg4(g).T
+    for t in (None, proposed, table):
+        assert tc.Counter(g.n, g.nnz, tc.Options(sched_table=t))(rp, col, lev).T == T
+    th = sched.isect_ms(gs, None)
+    tl = sched.isect_ms(gs, table.cpu().numpy())
+    print(f"\nproposed / heuristic {info['proposed_ms'] / info['heuristic_ms']:.3f}, reverted {info['reverted']}; "
+          f"verified / heuristic {tl / th:.3f} ({tl:.3f} ms vs {th:.3f} ms)")
+    assert tl < 1.15 * th
