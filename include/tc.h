@@ -113,7 +113,8 @@ typedef struct tc_options {
     int32_t wg_slots;         /* LDS hash slots per workgroup (power of 2,
                                  1024..32768); 0 = default 32768             */
     int32_t chunk_work;       /* target probe elements per work item;
-                                 0 = default 16384                           */
+                                 0 = by input size: 16384 below 2^23
+                                 entries, 32768 below 2^24, else 65536     */
     int32_t grid_blocks;      /* persistent grid size; 0 = as many 1024-thread
                                  blocks as fit in LDS, at most 2 per CU      */
     int32_t wave_max_owner;   /* heuristic: largest owner list for the

@@ -208,7 +208,7 @@ struct CountCfg {
     int force = TC_STRAT_AUTO;
     int wave_slots = 2048;
     int wg_slots = 32768;
-    int chunk_work = 16384;
+    int chunk_work = 0;   // 0: by input size (default_chunk_work)
     int grid_blocks = 0;
     int wave_max_owner = 0;
     int merge_max_owner = 0;
@@ -222,6 +222,9 @@ struct CountCfg {
     const int32_t *cover_lev = nullptr;   // cover-edge count (over a cover_view_run view): the levels, or NULL
     bool timing = false;
 };
+// Probe elements per wavefront item when the options leave it at 0: 16384
+// below 2^23 input entries, 32768 below 2^24, 65536 from there on.
+int default_chunk_work(int64_t nnz);
 // Checked options -> configuration (TC_ERR_ARG for invalid options).
 int options_cfg(const tc_options *opt, CountCfg *cfg, int *flags);
 size_t count_ws_bytes(int32_t n, int64_t nnz);
