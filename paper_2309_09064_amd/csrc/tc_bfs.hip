@@ -142,44 +142,64 @@ __global__ void k_bfs_init_rest(int32_t n, const int32_t *__restrict__ comp, int
 
 // Frontier of `level`: flag[v] = 1 for vertices on that level with an edge
 // (in the second pass, only those of the pass: comp[v] >= 0).  Each block
-// also writes the degree sum of its frontier vertices to part[blockIdx.x]
-// (launched on at most kFlagBlocks blocks; k_front_mail adds them up).
+// also writes the number and the degree sum of its frontier vertices to
+// part[2 * blockIdx.x] and part[2 * blockIdx.x + 1] (launched on at most
+// kFlagBlocks blocks; k_front_mail adds them up).
 constexpr int kFlagBlocks = 1024;
 __global__ __launch_bounds__(kThreads) void k_level_flags(int32_t n, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ lev, int32_t level,
                                                            const int32_t *__restrict__ only,
                                                            int32_t *__restrict__ flag,
                                                            unsigned long long *__restrict__ part) {
-    __shared__ unsigned long long s_sum[kThreads / kWave];
-    unsigned long long d = 0;
+    __shared__ unsigned long long s_sum[kThreads / kWave][2];
+    unsigned long long c = 0, d = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t deg = rp[v + 1] - rp[v];
         const bool in = lev[v] == level && deg > 0 && (only == nullptr || only[v] >= 0);
         flag[v] = in;
+        c += in ? 1ull : 0ull;
         d += in ? (unsigned long long)deg : 0ull;
     }
+    c = wave_sum(c);
     d = wave_sum(d);
-    if (lane_id() == 0) s_sum[threadIdx.x / kWave] = d;
+    if (lane_id() == 0) {
+        s_sum[threadIdx.x / kWave][0] = c;
+        s_sum[threadIdx.x / kWave][1] = d;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kThreads / kWave; ++w) d += s_sum[w];
-        part[blockIdx.x] = d;
+        for (int w = 1; w < kThreads / kWave; ++w) {
+            c += s_sum[w][0];
+            d += s_sum[w][1];
+        }
+        part[2 * blockIdx.x] = c;
+        part[2 * blockIdx.x + 1] = d;
     }
 }
 
-// Mailbox: dst[0] = frontier size (the flag scan's total), dst[1] = the
-// frontier's degree sum (the blocks' partial sums).  One block.
+// Mailbox: dst[0] = frontier size, dst[1] = the frontier's degree sum, from
+// the nparts blocks' partial sums.  One block.
 __global__ __launch_bounds__(kThreads) void k_front_mail(const unsigned long long *__restrict__ part, int nparts,
-                                                          const int32_t *__restrict__ fsize, uint64_t *dst) {
-    __shared__ unsigned long long s_sum[kThreads / kWave];
-    unsigned long long d = 0;
-    for (int i = threadIdx.x; i < nparts; i += kThreads) d += part[i];
+                                                          uint64_t *dst) {
+    __shared__ unsigned long long s_sum[kThreads / kWave][2];
+    unsigned long long c = 0, d = 0;
+    for (int i = threadIdx.x; i < nparts; i += kThreads) {
+        c += part[2 * i];
+        d += part[2 * i + 1];
+    }
+    c = wave_sum(c);
     d = wave_sum(d);
-    if (lane_id() == 0) s_sum[threadIdx.x / kWave] = d;
+    if (lane_id() == 0) {
+        s_sum[threadIdx.x / kWave][0] = c;
+        s_sum[threadIdx.x / kWave][1] = d;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kThreads / kWave; ++w) d += s_sum[w];
-        dst[0] = (uint64_t)(int64_t)fsize[0];
+        for (int w = 1; w < kThreads / kWave; ++w) {
+            c += s_sum[w][0];
+            d += s_sum[w][1];
+        }
+        dst[0] = c;
         dst[1] = d;
     }
 }
@@ -279,7 +299,7 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65536) {
 struct BfsLayout {
     int32_t *comp, *front, *flag, *pos, *fdeg, *giant;
     int64_t *fpre;
-    unsigned long long *part;   // per-block frontier degree sums
+    unsigned long long *part;   // per-block frontier sizes and degree sums
     void *scan;
 };
 
@@ -293,7 +313,7 @@ BfsLayout carve_bfs(Carver &c, int32_t n) {
     L.fdeg = c.take<int32_t>(nn);
     L.fpre = c.take<int64_t>(nn + 1);
     L.giant = c.take<int32_t>(64);
-    L.part = c.take<unsigned long long>(kFlagBlocks);
+    L.part = c.take<unsigned long long>(2 * kFlagBlocks);
     L.scan = c.take<char>(scan_ws_bytes(nn));
     return L;
 }
@@ -336,9 +356,7 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
             // frontier of `level` (vertices with an edge), compacted in id order
             hipLaunchKernelGGL(k_level_flags, dim3(gf), dim3(kThreads), 0, s, n, rp, lev, level, only, L.flag,
                                L.part);
-            TC_HIP_TRY(hipGetLastError());
-            TC_TRY(scan_exclusive_i32_to_i32(L.flag, L.pos, n, L.scan, s));
-            hipLaunchKernelGGL(k_front_mail, dim3(1), dim3(kThreads), 0, s, L.part, (int)gf, L.pos + n, mb.dev);
+            hipLaunchKernelGGL(k_front_mail, dim3(1), dim3(kThreads), 0, s, L.part, (int)gf, mb.dev);
             TC_HIP_TRY(hipGetLastError());
             TC_HIP_TRY(hipStreamSynchronize(s));
             const int32_t f = (int32_t)mb.host[0];
@@ -352,6 +370,8 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
                 hipLaunchKernelGGL(k_bfs_bottom_up, dim3(gb), dim3(kThreads), 0, s, n, rp, col, level, lev);
                 TC_HIP_TRY(hipGetLastError());
             } else {
+                // positions in the frontier list: only top-down levels need them
+                TC_TRY(scan_exclusive_i32_to_i32(L.flag, L.pos, n, L.scan, s));
                 hipLaunchKernelGGL(k_compact, dim3(gv), dim3(kThreads), 0, s, n, L.flag, L.pos, L.front);
                 hipLaunchKernelGGL(k_front_deg, dim3(grid_for(f, kThreads)), dim3(kThreads), 0, s, f, L.front, rp,
                                    L.fdeg);
