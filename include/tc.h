@@ -405,7 +405,9 @@ int tc_mlp_schedule(const float *d_params, int32_t hidden, int32_t k, const tc_o
 
 /*
  * The two CSRs of the partition (Algorithm 4, partition loop), for tests and
- * for callers that reuse them.  Outputs (device, caller-owned):
+ * for callers that reuse them.  d_levels: int32[n] device, levels that differ
+ * by at most one on every edge (BFS levels do; TC_VALIDATE on tc_count checks
+ * it).  Outputs (device, caller-owned):
  *   d_rp0  int32[n+1], d_c0 int32[nnz]: N0(x) per row = the neighbours of
  *          equal level with rank above x, ascending, then those with rank
  *          below x, ascending; rank(y) = (deg(y), y) lexicographic.

@@ -33,17 +33,33 @@ __device__ __forceinline__ bool rank_above(int32_t dy, int32_t y, int32_t x, int
     return dy > dx || (dy == dx && y > x);
 }
 
-// {level, degree} of every vertex in one 8-byte record, so the marking pass
-// reads one record per neighbour instead of three scattered words.
+// {level, degree} of every vertex in one 4-byte record, so the marking pass
+// gathers one word per neighbour: degree << 2 | (level mod 4).  Levels of
+// adjacent vertices differ by at most one (BFS levels do; caller-given
+// levels must), so two neighbours share a level exactly when their levels
+// agree mod 4.  Degrees saturate at kDegSat; the rank test reads the exact
+// degree when both sides are that large.
+constexpr uint32_t kDegSat = (1u << 30) - 1;
 __global__ void k_part_vld(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ lev,
-                           int2 *__restrict__ vld) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        vld[v] = make_int2(lev[v], rp[v + 1] - rp[v]);
+                           uint32_t *__restrict__ vld) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t d = (uint32_t)(rp[v + 1] - rp[v]);
+        vld[v] = (d < kDegSat ? d : kDegSat) << 2 | ((uint32_t)lev[v] & 3u);
+    }
+}
+
+// rank_above with y's degree from its record (dyp, saturated at kDegSat)
+// and x's exact degree dx.
+__device__ __forceinline__ bool rank_above_rec(uint32_t dyp, int32_t y, int32_t x, int32_t dx,
+                                               const int32_t *__restrict__ rp) {
+    int32_t dy = (int32_t)dyp;
+    if (dyp == kDegSat && dx >= (int32_t)kDegSat) dy = rp[y + 1] - rp[y];
+    return rank_above(dy, y, x, dx);
 }
 
 __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
-                                                         const int2 *__restrict__ vld,
+                                                         const uint32_t *__restrict__ vld,
                                                          uint8_t *__restrict__ flags, int32_t *__restrict__ d0,
                                                          int32_t *__restrict__ up0, int32_t *__restrict__ bh,
                                                          int32_t *__restrict__ bu) {
@@ -66,7 +82,8 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
         const int64_t e1 = e0 + kRun < nnz ? e0 + kRun : nnz;
         int64_t x = row_of(rp, r_lo, r_hi, e0);
         int64_t xe = rp[x + 1];
-        int32_t lx = vld[x].x, dx = (int32_t)(xe - rp[x]);
+        uint32_t lx = vld[x] & 3u;
+        int32_t dx = (int32_t)(xe - rp[x]);
         int32_t ch = 0, cu = 0;
         auto flush = [&]() {
             if (local) {
@@ -82,11 +99,11 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
         // the row walk: two memory latencies per thread instead of two per
         // entry
         int32_t y[kRun];
-        int2 iy[kRun];
+        uint32_t iy[kRun];
 #pragma unroll
         for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? col[e0 + k] : 0;
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) iy[k] = e0 + k < e1 ? vld[y[k]] : make_int2(0, 0);
+        for (int k = 0; k < kRun; ++k) iy[k] = e0 + k < e1 ? vld[y[k]] : 0u;
         uint8_t f[kRun];
 #pragma unroll
         for (int k = 0; k < kRun; ++k) f[k] = 0;
@@ -98,11 +115,11 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
                     flush();
                     ++x;
                     xe = rp[x + 1];
-                    lx = vld[x].x;
+                    lx = vld[x] & 3u;
                     dx = (int32_t)(xe - rp[x]);
                 }
-                const bool hor = iy[k].x == lx;
-                const bool up = hor && rank_above(iy[k].y, y[k], (int32_t)x, dx);
+                const bool hor = (iy[k] & 3u) == lx;
+                const bool up = hor && rank_above_rec(iy[k] >> 2, y[k], (int32_t)x, dx, rp);
                 f[k] = (uint8_t)(hor | (up << 1));
                 ch += hor;
                 cu += up;
@@ -240,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
 }
 
 struct PartLayout {
-    int2 *vld;
+    uint32_t *vld;
     uint8_t *flags;
     int32_t *bh, *bu;
     void *scan;
@@ -249,7 +266,7 @@ struct PartLayout {
 PartLayout carve_part(Carver &c, int32_t n, int64_t nnz) {
     PartLayout L;
     const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
-    L.vld = c.take<int2>(n > 0 ? n : 1);
+    L.vld = c.take<uint32_t>(n > 0 ? n : 1);
     L.flags = c.take<uint8_t>(nnz > 0 ? nnz : 1);
     L.bh = c.take<int32_t>(nblk + 1);
     L.bu = c.take<int32_t>(nblk + 1);
