@@ -35,6 +35,7 @@ constexpr int kMinPartnersPerItem = 8;     // wavefront items
 constexpr int kMinPartnersPerWgItem = 4096; // workgroup items
 constexpr int kWgItemWaves = 4 * kIsectWaves; // a workgroup item holds this many wavefront items of work
 constexpr int32_t kEmpty = -1;
+constexpr int32_t kNoKey = -2;   // window padding: never stored, never equal to kEmpty
 // A workgroup table (2^wg_log2 slots) holds at most 2^(wg_log2 - kWgCapShift)
 // owner elements (load 1/8: linear probing stays short); longer owner lists
 // are cut into value-range slices.
@@ -433,7 +434,9 @@ __device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
     }
 }
 
-// Membership of up to kPer keys (negative = absent slot).  Every key's home
+// Membership of up to kPer keys: ids >= 0, or kNoKey for window padding,
+// which matches no slot (never kEmpty, which would match empty ones).  Every
+// key's home
 // bucket is read once, unconditionally and interleaved; a key whose home
 // bucket is full without it (rare at the tables' load) then follows its
 // probe sequence, one pending key at a time per lane.  Keeping the common
@@ -456,18 +459,19 @@ __device__ __forceinline__ uint32_t hash_probe(const HashTab &t, const int32_t (
     for (int u = 0; u < kPer; ++u) {
         const int32_t x = v[u];
         const bool m0 = q[u].x == x, m1 = q[u].y == x;
-        const bool live = x >= 0;
-        if constexpr (kMask) hits |= (live & (m0 | m1)) ? (1u << u) : 0u;
-        else hits += (live & (m0 | m1)) ? 1u : 0u;
+        if constexpr (kMask) hits |= (m0 | m1) ? (1u << u) : 0u;
+        else hits += (m0 | m1) ? 1u : 0u;
         if constexpr (kSlots) slot[u] = (int32_t)(2 * b[u] + (m0 ? 0 : 1));
-        any_pend |= live & !(m0 | m1) & (q[u].y != kEmpty);
+        // a full bucket (second slot used: keys are >= 0) without the key;
+        // padding keys walk on too, rarely, and never match
+        any_pend |= !(m0 | m1) & (q[u].y >= 0);
     }
     if (__ballot(any_pend) == 0) return hits;
     uint32_t pend = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int32_t x = v[u];
-        pend |= ((x >= 0) & (q[u].x != x) & (q[u].y != x) & (q[u].y != kEmpty)) ? (1u << u) : 0u;
+        pend |= ((q[u].x != x) & (q[u].y != x) & (q[u].y >= 0)) ? (1u << u) : 0u;
     }
     while (pend) {
         const int u = __builtin_ctz(pend);
@@ -716,7 +720,7 @@ __device__ __forceinline__ uint32_t stream_long(const int32_t *lists, uint64_t m
         int32_t vb[kPer];
         gather(base + kStep, vb);
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) va[u] = base + u * kWave + l < total ? va[u] : -1;
+        for (int u = 0; u < kPer; ++u) va[u] = base + u * kWave + l < total ? va[u] : kNoKey;
         hits += count(va);
         if (base + kStep >= total) break;
 #pragma unroll
@@ -821,7 +825,7 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     };
     auto masked = [&](int32_t base, int32_t (&v)[kPer]) {
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) v[u] = base + u * kWave + l < total ? v[u] : -1;
+        for (int u = 0; u < kPer; ++u) v[u] = base + u * kWave + l < total ? v[u] : kNoKey;
     };
     // software pipeline: the next window's loads are issued before this
     // window's lookups, so their latency overlaps the LDS probes.  The next
