@@ -700,7 +700,10 @@ __device__ __forceinline__ uint32_t stream_long(const int32_t *lists, uint64_t m
     constexpr int32_t kStep = kPer * kWave;
     // rows must be visited in increasing order: the cursor only moves forward.
     // Positions past the end are clamped into the last list and masked later.
+    // Only a step that reaches past the end clamps positions and masks keys
+    // (a uniform branch): full steps skip four VALU instructions per key.
     auto gather = [&](int32_t base, int32_t (&v)[kPer]) {
+        const bool whole = base + kStep <= total;
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int32_t row = base + u * kWave;
@@ -710,7 +713,8 @@ __device__ __forceinline__ uint32_t stream_long(const int32_t *lists, uint64_t m
             }
             const int32_t pos = row + l;
             const int32_t off = pos >= n_start ? n_off : c_off;
-            v[u] = lists[off + min(pos, total - 1)];
+            if (whole) v[u] = lists[off + pos];
+            else v[u] = lists[off + min(pos, total - 1)];
         }
     };
     uint32_t hits = 0;
@@ -719,8 +723,10 @@ __device__ __forceinline__ uint32_t stream_long(const int32_t *lists, uint64_t m
     for (int32_t base = 0;; base += kStep) {
         int32_t vb[kPer];
         gather(base + kStep, vb);
+        if (base + kStep > total) {
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) va[u] = base + u * kWave + l < total ? va[u] : kNoKey;
+            for (int u = 0; u < kPer; ++u) va[u] = base + u * kWave + l < total ? va[u] : kNoKey;
+        }
         hits += count(va);
         if (base + kStep >= total) break;
 #pragma unroll
