@@ -139,6 +139,31 @@ def test_bfs_levels_match_oracle(tc, name):
     assert nlev == (int(ref.max()) + 1 if g.n else 0)
 
 
+def _bfs_mix(first_small):
+    # isolated vertices first (the first BFS starts past vertex 0), a long
+    # path (600 top-down levels), a star (its leaves' level goes bottom-up
+    # by the edge rule) and a Kronecker graph.  The first BFS covers the
+    # smallest-id component, the path or (with first_small) a short cycle;
+    # the second pass - linking over every row left, then a multi-source BFS
+    # - covers the rest, most of the vertices.
+    path = csr_from_edges(600, [(i, i + 1) for i in range(599)])
+    star = csr_from_edges(3000, [(0, i) for i in range(1, 3000)])
+    parts = [csr_from_edges(5, [])] + ([cycle(40)] if first_small else []) + [path, star, kron(12, 8)]
+    return disjoint_union(*parts)
+
+
+@pytest.mark.parametrize("first_small", [False, True], ids=["path_first", "cycle_first"])
+def test_bfs_levels_direction_mix(tc, first_small):
+    # both BFS directions and a large second pass, checked level by level
+    # against the serial BFS
+    g = _bfs_mix(first_small)
+    ref, _ = oracle.bfs_levels(g)
+    rp, col = to_gpu(g)
+    lev, nlev = tc.bfs_levels(rp, col)
+    assert np.array_equal(lev.cpu().numpy(), ref)
+    assert nlev == int(ref.max()) + 1
+
+
 # ------------------------------------------------------------------ partition
 
 @pytest.mark.parametrize("name", ["k12", "wheel9", "union", "gnp", "kron11", "kron14", "er_dense", "chunglu14"])
