@@ -454,7 +454,7 @@ __device__ __forceinline__ uint32_t hash_probe(const HashTab &t, const int32_t (
 #pragma unroll
     for (int u = 0; u < kPer; ++u) q[u] = *reinterpret_cast<const int2 *>(&t.tab[2 * b[u]]);
     uint32_t hits = 0;
-    bool any_pend = false;
+    uint32_t pend = 0;   // keys whose home bucket is full (second slot used: keys are >= 0) without them
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int32_t x = v[u];
@@ -462,17 +462,10 @@ __device__ __forceinline__ uint32_t hash_probe(const HashTab &t, const int32_t (
         if constexpr (kMask) hits |= (m0 | m1) ? (1u << u) : 0u;
         else hits += (m0 | m1) ? 1u : 0u;
         if constexpr (kSlots) slot[u] = (int32_t)(2 * b[u] + (m0 ? 0 : 1));
-        // a full bucket (second slot used: keys are >= 0) without the key;
         // padding keys walk on too, rarely, and never match
-        any_pend |= !(m0 | m1) & (q[u].y >= 0);
+        pend |= (!(m0 | m1) & (q[u].y >= 0)) ? (1u << u) : 0u;
     }
-    if (__ballot(any_pend) == 0) return hits;
-    uint32_t pend = 0;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int32_t x = v[u];
-        pend |= ((q[u].x != x) & (q[u].y != x) & (q[u].y >= 0)) ? (1u << u) : 0u;
-    }
+    if (__ballot(pend != 0) == 0) return hits;
     while (pend) {
         const int u = __builtin_ctz(pend);
         pend &= pend - 1;
