@@ -470,12 +470,9 @@ __device__ __forceinline__ uint32_t hash_probe(const HashTab &t, const int32_t (
         const int u = __builtin_ctz(pend);
         pend &= pend - 1;
         int32_t x = v[0];
-        uint32_t bb = b[0];
 #pragma unroll
-        for (int j = 1; j < kPer; ++j) {
-            x = u == j ? v[j] : x;
-            bb = u == j ? b[j] : bb;
-        }
+        for (int j = 1; j < kPer; ++j) x = u == j ? v[j] : x;
+        uint32_t bb = home_slot(t, x);   // recomputed: cheaper than a second select chain
         for (;;) {
             bb = (bb + 1) & t.mask;
             const int2 r = *reinterpret_cast<const int2 *>(&t.tab[2 * bb]);
