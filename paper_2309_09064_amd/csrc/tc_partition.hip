@@ -66,24 +66,37 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
     __shared__ int32_t sh[kWaves], su[kWaves];
     __shared__ int64_t rows[2];
     __shared__ int32_t acc_h[kTileRowsMax], acc_u[kTileRowsMax];
+    __shared__ int32_t s_rp[kTileRowsMax + 1];
+    __shared__ uint8_t s_lv[kTileRowsMax];
     const int64_t t0 = (int64_t)blockIdx.x * kBlockEntries;
     tile_rows(rp, n, t0, t0 + kBlockEntries < nnz ? t0 + kBlockEntries : nnz, rows);
     const int64_t r_lo = rows[0], r_hi = rows[1];
     const int64_t nr = r_hi - r_lo + 1;
     // rows of the tile are counted in LDS; only the two boundary rows can be
-    // shared with other tiles
+    // shared with other tiles.  Their row pointers and levels are staged in
+    // LDS too: a thread's walk across row boundaries then waits on LDS, not
+    // on one dependent global load per boundary.
     const bool local = nr <= kTileRowsMax;
-    if (local)
-        for (int64_t i = threadIdx.x; i < nr; i += kThreads) { acc_h[i] = 0; acc_u[i] = 0; }
+    if (local) {
+        for (int64_t i = threadIdx.x; i < nr; i += kThreads) {
+            acc_h[i] = 0;
+            acc_u[i] = 0;
+            s_rp[i] = rp[r_lo + i];
+            s_lv[i] = (uint8_t)(vld[r_lo + i] & 3u);
+        }
+        if (threadIdx.x == 0) s_rp[nr] = rp[r_hi + 1];
+    }
     __syncthreads();
+    auto rpx = [&](int64_t r) -> int64_t { return local ? (int64_t)s_rp[r - r_lo] : (int64_t)rp[r]; };
+    auto lvx = [&](int64_t r) -> uint32_t { return local ? (uint32_t)s_lv[r - r_lo] : vld[r] & 3u; };
     const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
     int32_t th = 0, tu = 0;
     if (e0 < nnz) {
         const int64_t e1 = e0 + kRun < nnz ? e0 + kRun : nnz;
-        int64_t x = row_of(rp, r_lo, r_hi, e0);
-        int64_t xe = rp[x + 1];
-        uint32_t lx = vld[x] & 3u;
-        int32_t dx = (int32_t)(xe - rp[x]);
+        int64_t x = local ? r_lo + row_of(s_rp, 0, nr - 1, e0) : row_of(rp, r_lo, r_hi, e0);
+        int64_t xe = rpx(x + 1);
+        uint32_t lx = lvx(x);
+        int32_t dx = (int32_t)(xe - rpx(x));
         int32_t ch = 0, cu = 0;
         auto flush = [&]() {
             if (local) {
@@ -114,9 +127,10 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
                 while (e >= xe) {
                     flush();
                     ++x;
-                    xe = rp[x + 1];
-                    lx = vld[x] & 3u;
-                    dx = (int32_t)(xe - rp[x]);
+                    const int64_t xb = xe;
+                    xe = rpx(x + 1);
+                    lx = lvx(x);
+                    dx = (int32_t)(xe - xb);
                 }
                 const bool hor = (iy[k] & 3u) == lx;
                 const bool up = hor && rank_above_rec(iy[k] >> 2, y[k], (int32_t)x, dx, rp);
@@ -195,8 +209,24 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
                                                             int32_t *__restrict__ pos0, int32_t *__restrict__ pos1) {
     __shared__ int64_t wsum[kWaves];
     __shared__ int64_t rows[2];
+    __shared__ int32_t s_rp[kTileRowsMax + 1], s_ub[kTileRowsMax], s_lb[kTileRowsMax];
     const int64_t t0 = (int64_t)blockIdx.x * kBlockEntries;
     tile_rows(rp, n, t0, t0 + kBlockEntries < nnz ? t0 + kBlockEntries : nnz, rows);
+    // the tile's row pointers and per-row targets staged in LDS (made
+    // visible by the scan's barrier below): the walk across row boundaries
+    // then waits on LDS, not on dependent global loads
+    const int64_t r_lo = rows[0], r_hi = rows[1];
+    const int64_t nr = r_hi - r_lo + 1;
+    const bool local = nr <= kTileRowsMax;
+    if (local) {
+        for (int64_t i = threadIdx.x; i < nr; i += kThreads) {
+            const int64_t r = r_lo + i;
+            s_rp[i] = rp[r];
+            s_ub[i] = rp0[r] - rpu[r];
+            s_lb[i] = rpu[r + 1];
+        }
+        if (threadIdx.x == 0) s_rp[nr] = rp[r_hi + 1];
+    }
     const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
     const int64_t e1 = e0 < nnz ? (e0 + kRun < nnz ? e0 + kRun : nnz) : e0;
     uint8_t f[kRun];
@@ -227,19 +257,22 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
     int32_t y[kRun];   // issued before the row walk
 #pragma unroll
     for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? col[e0 + k] : 0;
-    int64_t x = row_of(rp, rows[0], rows[1], e0);
-    int64_t xe = rp[x + 1];
+    auto rpx = [&](int64_t r) -> int64_t { return local ? (int64_t)s_rp[r - r_lo] : (int64_t)rp[r]; };
     // N0+ entries of row x go to rp0[x] + (U - rpu[x]), the rest of its
     // horizontal entries to H - U + rpu[x + 1]: two per-row terms
-    int64_t up_base = (int64_t)rp0[x] - rpu[x], lo_base = rpu[x + 1];
+    auto upb = [&](int64_t r) -> int64_t { return local ? (int64_t)s_ub[r - r_lo] : (int64_t)rp0[r] - rpu[r]; };
+    auto lob = [&](int64_t r) -> int64_t { return local ? (int64_t)s_lb[r - r_lo] : (int64_t)rpu[r + 1]; };
+    int64_t x = local ? r_lo + row_of(s_rp, 0, nr - 1, e0) : row_of(rp, r_lo, r_hi, e0);
+    int64_t xe = rpx(x + 1);
+    int64_t up_base = upb(x), lo_base = lob(x);
 #pragma unroll
     for (int k = 0; k < kRun; ++k) {
         const int64_t e = e0 + k;
         if (e < e1) {
             if (e >= xe) {
-                do { ++x; xe = rp[x + 1]; } while (e >= xe);
-                up_base = (int64_t)rp0[x] - rpu[x];
-                lo_base = rpu[x + 1];
+                do { ++x; xe = rpx(x + 1); } while (e >= xe);
+                up_base = upb(x);
+                lo_base = lob(x);
             }
             const uint8_t fe = f[k];
             if (fe & 1) {
