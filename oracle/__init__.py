@@ -11,8 +11,10 @@ Counting" (arXiv 2309.09064):
 * :func:`build_csr`          simple undirected CSR from tuples (Introduction)
 * :func:`bfs_levels`         BFS from each unvisited vertex in id order (Alg. 4)
 * :func:`partition`          E0/E1 split, N0 rank-split rows (Alg. 4)
-* :func:`alg4`               T0 by forward-hashed (Alg. 2) + T1 hashed (Alg. 4)
+* :func:`alg4`               T0 = triangles inside G0, T1 = triangles with one
+                             horizontal edge (the two sums of Alg. 4), by merges
 * :func:`count_emd`          direction-oriented sorted-merge edge iterator
+* :func:`count_emd_rows`     the same over a sample of rows, on host threads
 * :func:`alg3`               cover-edge count (Alg. 3)
 * :func:`vertex_triangles`   per-vertex triangle counts
 * :func:`vertex_triangles_at`  the same for sampled vertices, by another definition
@@ -46,7 +48,7 @@ def build(force: bool = True, opt: str = "-O2") -> str:
     """Compile the oracle with gcc (``-O2``, as the paper compiled its C)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", opt, "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", opt, "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -68,6 +70,8 @@ def _load():
         lib.orc_alg4.restype = ctypes.c_int
         lib.orc_count_emd.argtypes = [ctypes.c_int64, _i64, _i32]
         lib.orc_count_emd.restype = ctypes.c_uint64
+        lib.orc_count_emd_rows.argtypes = [ctypes.c_int64, _i64, _i32, ctypes.c_int64, _i64, ctypes.c_int]
+        lib.orc_count_emd_rows.restype = ctypes.c_uint64
         lib.orc_alg3.argtypes = [ctypes.c_int64, _i64, _i32, _i32]
         lib.orc_alg3.restype = ctypes.c_uint64
         lib.orc_vertex_triangles.argtypes = [ctypes.c_int64, _i64, _i32, _u64]
@@ -167,7 +171,9 @@ class Alg4Result:
 
 
 def alg4(g: CSR, level: np.ndarray | None = None) -> Alg4Result:
-    """Algorithm 4; computes serial BFS levels when ``level`` is None."""
+    """The counts of Algorithm 4 for levels ``level`` (serial BFS levels when
+    None): T0 = triangles whose three edges are horizontal, T1 = triangles
+    with exactly one horizontal edge, T = T0 + T1, |E0| and k."""
     if level is None:
         level, _ = bfs_levels(g)
     lev = np.ascontiguousarray(level, dtype=np.int32)
@@ -185,6 +191,17 @@ def alg4(g: CSR, level: np.ndarray | None = None) -> Alg4Result:
 
 def count_emd(g: CSR) -> int:
     return int(_load().orc_count_emd(g.n, g.row_ptr, _col_or_dummy(g)))
+
+
+def count_emd_rows(g: CSR, rows, threads: int = 1) -> int:
+    """Triangles u < v < w whose smallest vertex u is in ``rows``, by the same
+    sorted-merge edge iterator, the rows shared among ``threads`` host
+    threads.  All rows give T."""
+    us = np.ascontiguousarray(rows, dtype=np.int64)
+    if us.size and (us.min() < 0 or us.max() >= g.n):
+        raise ValueError("row out of range")
+    return int(_load().orc_count_emd_rows(g.n, g.row_ptr, _col_or_dummy(g), us.size,
+                                          us if us.size else np.zeros(1, np.int64), int(threads)))
 
 
 def alg3(g: CSR, level: np.ndarray | None = None) -> int:

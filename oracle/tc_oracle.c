@@ -5,7 +5,9 @@
  * benchmark's CPU-baseline leg may load this library.  It shares no code with
  * the GPU library: no headers, kernels, helpers or tables.
  *
- * Plain, serial, obviously-correct C.  Every routine names the passage of
+ * Plain, serial, obviously-correct C (one routine, orc_count_emd_rows, shares
+ * its rows among OpenMP threads to time the definition on every host core).
+ * Every routine names the passage of
  * Bader, "Fast Triangle Counting" (arXiv 2309.09064) that it follows.  Row
  * pointers are int64 here; the Python wrapper converts.
  *
@@ -144,48 +146,28 @@ void orc_partition(int64_t n, const int64_t *row_ptr, const int32_t *col, const 
     }
 }
 
-/* -------------------------------------------------------------- Algorithm 2 */
+/* ------------------------------------------------ T0 and T1 of Algorithm 4 */
 
 /*
- * Forward-hashed triangle count (Algorithm 2) on the graph given by
- * (rp, adj).  Edges are enumerated row by row, u ascending, and each
- * undirected edge is taken once, from its smaller endpoint (u < v).  A(v)
- * grows as in the algorithm; `hash` is a Boolean array indexed by vertex id.
- */
-static uint64_t forward_hashed(int64_t n, const int64_t *rp, const int32_t *adj)
-{
-    int64_t *a_off = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
-    int64_t *a_len = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
-    int32_t *a_set = (int32_t *)malloc((size_t)(rp[n] > 0 ? rp[n] : 1) * sizeof(int32_t));
-    unsigned char *hash = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
-    if (!a_off || !a_len || !a_set || !hash) { free(a_off); free(a_len); free(a_set); free(hash); return UINT64_MAX; }
-    for (int64_t v = 0; v <= n; ++v) a_off[v] = rp[v];   /* A(v) holds at most deg(v) ids */
-    uint64_t T = 0;
-    for (int64_t u = 0; u < n; ++u) {
-        for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
-            int64_t v = adj[j];
-            if (!(u < v)) continue;
-            for (int64_t i = 0; i < a_len[u]; ++i) hash[a_set[a_off[u] + i]] = 1;
-            for (int64_t i = 0; i < a_len[v]; ++i)
-                if (hash[a_set[a_off[v] + i]]) ++T;
-            for (int64_t i = 0; i < a_len[u]; ++i) hash[a_set[a_off[u] + i]] = 0;
-            a_set[a_off[v] + a_len[v]++] = (int32_t)u;
-        }
-    }
-    free(a_off); free(a_len); free(a_set); free(hash);
-    return T;
-}
-
-/* -------------------------------------------------------------- Algorithm 4 */
-
-/*
- * Fast triangle counting (Algorithm 4) given levels L:
- *   partition E into G0 (horizontal) and G1;
- *   T0 = forward-hashed count of G0 (Algorithm 2);
- *   T1 = for each u: mark N_G1(u) in Hash; for each v in N_G0(u) with u < v,
- *        count w in N_G1(v) that are marked; unmark.
+ * The two counts Algorithm 4 adds up, for levels L, each computed from what
+ * it counts rather than by the algorithm's loops:
+ *   G0 = (V, E0) with E0 = {uv : L(u) = L(v)} (the partition loop), and
+ *   G1 = (V, E \ E0), each as a CSR;
+ *   T0 = triangles with all three edges in E0 (Algorithm 4 hands G0 to the
+ *        forward algorithm, Algorithm 2, which counts exactly these): every
+ *        triangle u < v < w of G0 once, from its two smaller vertices;
+ *   T1 = for every horizontal edge uv with u < v, the common members of
+ *        N1(u) and N1(v) (the hashed loop's intersection): the triangles whose
+ *        third vertex lies on another level, each counted from its one
+ *        horizontal edge.
+ * A common member is found by marking the set N(u) in a vertex-indexed
+ * Boolean array and testing each member of the other list against it.
+ * With |L(u) - L(v)| <= 1 on every edge, a triangle with two horizontal
+ * edges has all three on one level, and one with none would need three
+ * distinct levels each within one of the others, which integers do not
+ * allow; so T0 + T1 = T (the cover-edge argument of Section II).
  * Outputs T0, T1 and |E0| (undirected).  Returns 0, or -3 on allocation
- * failure.  Correct for any levels with |L(u) - L(v)| <= 1 on every edge.
+ * failure.
  */
 int orc_alg4(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *level,
              uint64_t *t0_out, uint64_t *t1_out, int64_t *e0_out)
@@ -195,9 +177,9 @@ int orc_alg4(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_
     int64_t *rp1 = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
     int32_t *g0 = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
     int32_t *g1 = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
-    unsigned char *hash = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
-    if (!rp0 || !rp1 || !g0 || !g1 || !hash) {
-        free(rp0); free(rp1); free(g0); free(g1); free(hash);
+    unsigned char *in_u = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!rp0 || !rp1 || !g0 || !g1 || !in_u) {
+        free(rp0); free(rp1); free(g0); free(g1); free(in_u);
         return -3;
     }
     /* partition: each stored (directed) CSR entry goes to G0 or G1 */
@@ -211,23 +193,32 @@ int orc_alg4(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_
         rp0[u + 1] = p0;
         rp1[u + 1] = p1;
     }
-    uint64_t T0 = forward_hashed(n, rp0, g0);
-    uint64_t T1 = 0;
+    uint64_t T0 = 0, T1 = 0;
     for (int64_t u = 0; u < n; ++u) {
-        for (int64_t j = rp1[u]; j < rp1[u + 1]; ++j) hash[g1[j]] = 1;
+        /* T0: w in N0(u) and in N0(v), u < v < w */
+        for (int64_t j = rp0[u]; j < rp0[u + 1]; ++j) in_u[g0[j]] = 1;
         for (int64_t j = rp0[u]; j < rp0[u + 1]; ++j) {
             int64_t v = g0[j];
-            if (!(u < v)) continue;
-            for (int64_t i = rp1[v]; i < rp1[v + 1]; ++i)
-                if (hash[g1[i]]) ++T1;
+            if (v <= u) continue;
+            for (int64_t i = rp0[v]; i < rp0[v + 1]; ++i)
+                if (g0[i] > v && in_u[g0[i]]) ++T0;
         }
-        for (int64_t j = rp1[u]; j < rp1[u + 1]; ++j) hash[g1[j]] = 0;
+        for (int64_t j = rp0[u]; j < rp0[u + 1]; ++j) in_u[g0[j]] = 0;
+        /* T1: w in N1(u) and in N1(v) for the horizontal edge uv, u < v */
+        for (int64_t j = rp1[u]; j < rp1[u + 1]; ++j) in_u[g1[j]] = 1;
+        for (int64_t j = rp0[u]; j < rp0[u + 1]; ++j) {
+            int64_t v = g0[j];
+            if (v <= u) continue;
+            for (int64_t i = rp1[v]; i < rp1[v + 1]; ++i)
+                if (in_u[g1[i]]) ++T1;
+        }
+        for (int64_t j = rp1[u]; j < rp1[u + 1]; ++j) in_u[g1[j]] = 0;
     }
     *t0_out = T0;
     *t1_out = T1;
     *e0_out = rp0[n] / 2;
-    free(rp0); free(rp1); free(g0); free(g1); free(hash);
-    return (T0 == UINT64_MAX) ? -3 : 0;
+    free(rp0); free(rp1); free(g0); free(g1); free(in_u);
+    return 0;
 }
 
 /* ----------------------------------------------------- plain-definition count */
@@ -242,6 +233,34 @@ uint64_t orc_count_emd(int64_t n, const int64_t *row_ptr, const int32_t *col)
 {
     uint64_t T = 0;
     for (int64_t u = 0; u < n; ++u) {
+        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+            int64_t v = col[j];
+            if (v <= u) continue;
+            int64_t a = row_ptr[u], ae = row_ptr[u + 1], b = row_ptr[v], be = row_ptr[v + 1];
+            while (a < ae && b < be) {
+                if (col[a] < col[b]) ++a;
+                else if (col[a] > col[b]) ++b;
+                else { if (col[a] > v) ++T; ++a; ++b; }
+            }
+        }
+    }
+    return T;
+}
+
+/*
+ * The same count restricted to the rows u listed in us[0..k) (ascending or
+ * not): the triangles whose smallest vertex is one of them.  The rows are
+ * shared among `threads` OpenMP threads (1 = serial), so a sample of rows
+ * times the definition on every host core; the whole range of u gives T.
+ */
+uint64_t orc_count_emd_rows(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t k, const int64_t *us,
+                            int threads)
+{
+    (void)n;
+    uint64_t T = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : T) num_threads(threads)
+    for (int64_t i = 0; i < k; ++i) {
+        int64_t u = us[i];
         for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
             int64_t v = col[j];
             if (v <= u) continue;

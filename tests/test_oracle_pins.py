@@ -464,3 +464,54 @@ def test_relabel_degree_star_and_ties():
     h, perm = _check_relabel(cycle(9))
     assert perm.tolist() == list(range(9))
     _check_relabel(csr_from_edges(4, []))
+
+
+# ---------------------------------------------------------------- row-sampled edge iterator
+
+@pytest.mark.parametrize("n", [4, 7, 12])
+def test_emd_rows_complete_graph(n):
+    # in K_n the triangles whose smallest vertex is u number C(n - 1 - u, 2)
+    g = complete(n)
+    for u in range(n):
+        assert oracle.count_emd_rows(g, [u]) == choose(n - 1 - u, 2)
+    assert oracle.count_emd_rows(g, np.arange(n), threads=3) == choose(n, 3)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_emd_rows_partition_sums_to_brute_force(seed):
+    g = gnp(30, 0.3, seed)
+    want = brute_force(g)
+    rng = np.random.default_rng(seed)
+    part = rng.integers(0, 3, g.n)
+    parts = [oracle.count_emd_rows(g, np.nonzero(part == k)[0], threads=k + 1) for k in range(3)]
+    assert sum(parts) == want
+    assert oracle.count_emd_rows(g, [], threads=2) == 0
+
+
+def test_emd_rows_threads_agree(kron12):
+    g = kron12
+    rows = np.arange(0, g.n, 7)
+    one = oracle.count_emd_rows(g, rows, threads=1)
+    assert oracle.count_emd_rows(g, rows, threads=4) == one
+    assert oracle.count_emd_rows(g, np.arange(g.n), threads=4) == oracle.count_emd(g)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_t0_t1_by_brute_force(seed):
+    # every triangle classified by its number of horizontal edges: T0 counts
+    # those with three, T1 those with one; none has zero or two
+    rng = np.random.default_rng(500 + seed)
+    g = gnp(int(rng.integers(8, 34)), float(rng.uniform(0.1, 0.7)), 900 + seed)
+    lev, _ = oracle.bfs_levels(g)
+    A = dense(g).astype(bool)
+    hist = [0, 0, 0, 0]
+    for a in range(g.n):
+        for b in range(a + 1, g.n):
+            if not A[a, b]:
+                continue
+            for c in range(b + 1, g.n):
+                if A[a, c] and A[b, c]:
+                    hist[int(lev[a] == lev[b]) + int(lev[a] == lev[c]) + int(lev[b] == lev[c])] += 1
+    assert hist[0] == 0 and hist[2] == 0
+    r = oracle.alg4(g, lev)
+    assert (r.T0, r.T1) == (hist[3], hist[1])
