@@ -1,24 +1,38 @@
 """Benchmark: triangle count throughput (input edges/s) on one MI355X.
 
-One step = one full pass of the method over the resident graph: BFS levels
-(components + multi-source BFS), the E0/E1 partition, bucketing and the
-intersections, ending with the uint64 count on the host (tc_count with no
-levels given).  The CSR is built on the GPU beforehand (the paper's input is
-the CSR) and stays resident in HBM.
+One step = one full pass of the method over the resident graph: BFS levels,
+the E0/E1 partition, bucketing and the intersections, ending with the uint64
+count on the host (tc_count with no levels given).  The CSR is built on the
+GPU beforehand (the paper's input is the CSR) and stays resident in HBM.
 
-Prints one JSON line.  Default workload: Graph500-style Kronecker graph,
-scale 20, edgefactor 16, initiator (.57, .19, .19, .05), seed 1.
+Prints one JSON line.  Headline workload: Graph500-style Kronecker graph,
+scale 24 (16.8 M vertices, 268 M generated edges), edgefactor 16, initiator
+(.57, .19, .19, .05), seed 1, int32 CSR, the degree-threshold heuristic
+schedule.  `value` = m / mean step time.
 
-`value` is the heuristic ("plain") schedule; `config.learned_schedule` holds the
-same steps under the learned cost network's strategy table.
+Beside it (in `config`):
+  * learned_schedule -- the same steps under the cost network's strategy
+    table, the network trained on other graphs (Kronecker scale 22, seeds 2
+    and 3; Chung-Lu 2^20, seed 2) than the ones timed: the network's own
+    table, and the table after its classes of change were checked by
+    measurement on those training graphs;
+  * secondary -- Chung-Lu 2^22 (power law, gamma 2.1, mean degree 32) under
+    both schedules; Kronecker scale 20 with the forward-hashed, per-vertex,
+    per-edge and Algorithm 3 / degree-relabel legs; the 4096-graph batch.
 
-The roofline object describes the intersection kernel (k_isect): its
-algorithmic bytes per launch over its mean duration, taken from HIP events
-that the library records around the launch on its own stream during the
-timed steps.  Its `traffic` field comes from the committed counter summary
-in profiles/ (FETCH_SIZE + WRITE_SIZE, scaled by what the same counters read
-for a plain copy of known size) and is null when the kernel sources have
+`roofline` describes the intersection kernel (k_isect) on the headline
+graph: its algorithmic bytes B_alg per launch over its mean duration, taken
+from HIP events that the library records around the launch on the stream it
+launches on, during the timed steps.  `traffic` comes from the committed
+counter summary in profiles/ and is null when the kernel sources have
 changed since those counters were taken.
+
+`cpu_baseline` is the oracle's sorted-merge edge iterator on the host cores
+of this machine, timed on a bounded sample of the headline graph's edges
+(interleaved slices of 1/1024 of the CSR entries each, run until about 15 s
+of work; its time is scaled by the share of entries sampled); the oracle's
+serial BFS + Algorithm 4 counts on the whole scale-20 graph are a second,
+stated figure.
 """
 from __future__ import annotations
 
@@ -37,9 +51,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "input edges/s + % HBM peak, plain vs learned-scheduled, counts bit-exact"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_isect_kronecker_s20_traffic.txt")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_isect_kronecker_s24_traffic.txt")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "large_counts.txt")
 KERNEL_SOURCES = ("paper_2309_09064_amd/csrc/tc_count.hip", "paper_2309_09064_amd/csrc/tc_internal.hpp")
 COPY_PROBE_BYTES = 1 << 30
+CPU_SLICE = 1024          # a CPU-baseline slice is every 1024th CSR entry
+CPU_SECONDS = 15.0        # slices are run until this much time has passed
+TRAIN_GRAPHS = (("kronecker", 22, 2), ("kronecker", 22, 3), ("chunglu", 20, 2))
 
 
 def kernel_source_hash():
@@ -50,23 +68,32 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def b_alg(row_ptr, col, levels):
-    """Algorithmic bytes of the intersection pass: every live intersection
-    streams its smaller list once, every owner list is read once, plus 8 B per
-    oriented horizontal edge and 8 B per vertex (row pointers)."""
-    n = len(row_ptr) - 1
-    deg = np.diff(row_ptr).astype(np.int64)
-    u = np.repeat(np.arange(n, dtype=np.int64), deg)
-    v = col.astype(np.int64)
-    lev = levels.astype(np.int64)
-    hor = lev[u] == lev[v]
-    d0 = np.bincount(u[hor], minlength=n)
+def b_alg(rp, col, levels):
+    """Algorithmic bytes of the intersection pass, from torch tensors (any
+    device): every live intersection streams its smaller list once (4 B an
+    element), every owner list is read once, plus 8 B per oriented
+    horizontal edge and 8 B per vertex (its list records).  Lists: N0+ (the
+    rank-oriented horizontal neighbours, rank = (degree, id)) and N1 (the
+    neighbours on other levels)."""
+    import torch
+    n = rp.numel() - 1
+    dev = rp.device
+    deg = (rp[1:] - rp[:-1]).to(torch.int64)
+    u = torch.repeat_interleave(torch.arange(n, device=dev, dtype=torch.int32), deg)
+    v = col.to(torch.int32)
+    hor = levels[u.long()] == levels[v.long()]
+    d0 = torch.bincount(u[hor], minlength=n)
     d1 = deg - d0
-    up = hor & ((deg[v] > deg[u]) | ((deg[v] == deg[u]) & (v > u)))
-    d0p = np.bincount(u[up], minlength=n)
-    eu, ev = u[up], v[up]                      # each horizontal edge once
-    smin = np.minimum(d1[eu], d1[ev]).sum() + np.minimum(d0p[eu], d0p[ev]).sum()
-    return int(4 * smin + 4 * (d1.sum() + d0p.sum()) + 8 * len(eu) + 8 * n)
+    du, dv = deg[u.long()], deg[v.long()]
+    up = hor & ((dv > du) | ((dv == du) & (v > u)))
+    del du, dv, hor
+    d0p = torch.bincount(u[up], minlength=n)
+    eu, ev = u[up].long(), v[up].long()
+    del u, v
+    smin = (torch.minimum(d1[eu], d1[ev]).sum(dtype=torch.int64) +
+            torch.minimum(d0p[eu], d0p[ev]).sum(dtype=torch.int64))
+    total = 4 * int(smin) + 4 * int(d1.sum() + d0p.sum()) + 8 * int(eu.numel()) + 8 * n
+    return total
 
 
 def read_traffic(expect_hash):
@@ -83,11 +110,20 @@ def read_traffic(expect_hash):
     try:
         if kv["kernel_source_sha256"] != expect_hash:
             return None
-        f_scale = float(kv["copy_bytes"]) / (1024.0 * float(kv["copy_fetch_kib"]))
-        w_scale = float(kv["copy_bytes"]) / (1024.0 * float(kv["copy_write_kib"]))
-        return 1024.0 * (float(kv["isect_fetch_kib"]) * f_scale + float(kv["isect_write_kib"]) * w_scale)
-    except (KeyError, ValueError, ZeroDivisionError):
+        return float(kv["isect_hbm_bytes"])
+    except (KeyError, ValueError):
         return None
+
+
+def golden(name):
+    """(n, m, T, T0, T1, |E0|) the oracle stored for a large graph, or None."""
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                parts = line.split()
+                if parts[0] == name:
+                    return tuple(int(x) for x in parts[1:])
+    return None
 
 
 def copy_probe(torch):
@@ -101,16 +137,31 @@ def copy_probe(torch):
     del a, b
 
 
-def timed_steps(counter, rp, col, steps, warmup):
+def log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
+def make_graph(tc, torch, kind, size, seed):
+    import graphgen
+    if kind == "kronecker":
+        n, s, d = graphgen.kronecker(size, 16, seed=seed)
+    else:
+        n, s, d = graphgen.chung_lu(1 << size, 2.1, 32.0, float(1 << 17), seed=seed)
+    rp, col = tc.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    del s, d
+    return n, rp, col
+
+
+def timed_steps(counter, rp, col, steps, warmup, levels=None):
     """Mean wall time per step (seconds) and the per-step results."""
     import torch
     for _ in range(warmup):
-        counter(rp, col)
+        counter(rp, col, levels)
     torch.cuda.synchronize()
     results = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        results.append(counter(rp, col))
+        results.append(counter(rp, col, levels))
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, results
 
@@ -132,153 +183,173 @@ def phase_means(results):
     return {k: float(np.mean([x.ms[k] for x in results])) for k in ("bfs", "partition", "bucket", "isect")}
 
 
+def exact_vs_golden(name, n, m, r):
+    g = golden(name)
+    if g is None:
+        return None
+    return g == (n, m, r.T, r.T0, r.T1, r.e0)
+
+
+def learned_tables(tc, torch, steps):
+    """The cost network trained on the training graphs (none of them timed):
+    (network's table, verified table, info)."""
+    from paper_2309_09064_amd import sched
+    t0 = time.perf_counter()
+    train = []
+    for kind, size, seed in TRAIN_GRAPHS:
+        _, rp, col = make_graph(tc, torch, kind, size, seed)
+        lev, _ = tc.bfs_levels(rp, col)
+        train.append((rp, col, lev))
+    proposed, net, ds, losses = sched.learn_schedule(train, steps=steps, lr=1e-2, verify=False)
+    verified, vinfo = sched.verify_schedule(train, proposed)
+    info = {"train_graphs": [f"{k} {'scale' if k == 'kronecker' else 'n = 2^'}{s}, seed {sd}"
+                             for k, s, sd in TRAIN_GRAPHS],
+            "train_rows": int(len(ds.c)), "final_loss": float(losses[-1]),
+            "train_isect_ms": {"heuristic": vinfo["heuristic_ms"], "network": vinfo["proposed_ms"],
+                               "verified": vinfo["ms"]},
+            "reverted_classes": [list(x) for x in vinfo["reverted"]],
+            "profile_train_verify_s": time.perf_counter() - t0}
+    del train
+    torch.cuda.empty_cache()
+    return proposed, verified, info
+
+
+def schedule_legs(tc, torch, n, rp, col, tables, steps, warmup, T):
+    """Whole steps under each learned table; counts must equal T."""
+    m = col.numel() // 2
+    out = {}
+    for name, table in tables:
+        c = tc.Counter(n, col.numel(), tc.Options(timing=True, sched_table=table))
+        st, res = timed_steps(c, rp, col, steps, warmup)
+        assert all(x.T == T for x in res), f"{name} table changed the count"
+        out[name] = {"value": m / st, "ms_per_step": st * 1e3, "phase_ms": phase_means(res),
+                     "strategy_items": res[-1].strategy_items}
+    return out
+
+
+def cpu_baseline(rp, col, seconds):
+    """The oracle's edge iterator on a bounded sample of this graph's edges,
+    on every host core it may use."""
+    import oracle
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    g = oracle.as_csr(rp.numel() - 1, rp.cpu().numpy().astype(np.int64), col.cpu().numpy())
+    nnz = g.nnz
+    order = np.random.default_rng(0).permutation(CPU_SLICE)
+    done, T_part, t_used = 0, 0, 0.0
+    for off in order:
+        es = np.arange(int(off), nnz, CPU_SLICE, dtype=np.int64)
+        t0 = time.perf_counter()
+        T_part += oracle.count_emd_entries(g, es, threads)
+        t_used += time.perf_counter() - t0
+        done += 1
+        if t_used >= seconds:
+            break
+    frac = done / CPU_SLICE
+    est = t_used / frac
+    return {"value": g.m / est, "unit": "input edges/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} interleaved slices of 1/{CPU_SLICE} of the CSR entries (every {CPU_SLICE}th "
+                      f"entry from a random offset; {100 * frac:.2f} % of the edges) of the headline graph "
+                      f"through the oracle's sorted-merge edge iterator (C, gcc -O2, OpenMP over entries, "
+                      f"{threads} threads): {t_used:.1f} s, scaled by {1 / frac:.1f} to {est:.1f} s for the "
+                      f"whole graph",
+            "sample_T_estimate": int(round(T_part / frac))}
+
+
+def cpu_alg4_context(n, rp, col):
+    """Second stated CPU figure: the oracle's serial BFS levels + the counts of
+    Algorithm 4 on one whole graph, one thread."""
+    import oracle
+    g = oracle.as_csr(n, rp.cpu().numpy().astype(np.int64), col.cpu().numpy())
+    t0 = time.perf_counter()
+    lev, _ = oracle.bfs_levels(g)
+    r = oracle.alg4(g, lev)
+    dt = time.perf_counter() - t0
+    return {"value": g.m / dt, "unit": "input edges/s", "cores": 1, "seconds": dt, "T": r.T,
+            "what": "oracle serial BFS levels + Algorithm 4's T0 and T1 (C, gcc -O2, one thread), whole graph"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-schedule leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline legs")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-schedule legs")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the Chung-Lu, scale-20 and batch legs")
     ap.add_argument("--main-only", action="store_true",
-                    help="time only the main leg (no forward-hashed, per-vertex, per-edge or learned legs), "
-                         "so that a profile of the run holds the main leg's kernels alone")
+                    help="time only the headline leg, so that a profile of the run holds its kernels alone")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--train-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported "
                                    "(the multi-GPU sharding is described, not built)"}))
         sys.exit(2)
+    if args.main_only:
+        args.no_cpu = args.no_learned = args.no_secondary = True
 
     import torch
-    import graphgen
     import paper_2309_09064_amd as tc
 
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(torch)
-    n, src, dst = graphgen.kronecker(args.scale, 16, seed=args.seed)
-    rp, col = tc.build_csr(n, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
+    n, rp, col = make_graph(tc, torch, "kronecker", args.scale, args.seed)
     nnz = col.numel()
     m = nnz // 2
-    print(f"# graph: kronecker scale {args.scale}, n={n}, m={m}", file=sys.stderr, flush=True)
+    log(f"graph: kronecker scale {args.scale} seed {args.seed}, n={n}, m={m}")
 
     # TC_TIMING makes the library record HIP events around each phase on the
-    # stream it launches on; the cost is four event records per phase
+    # stream it launches on; the cost is a few event records per step
     counter = tc.Counter(n, nnz, tc.Options(timing=True))
     step_s, results = timed_steps(counter, rp, col, args.steps, args.warmup)
-    Ts = {r.T for r in results}
-    assert len(Ts) == 1, "count changed between steps"
+    assert len({r.T for r in results}) == 1, "count changed between steps"
     r = results[-1]
     T = r.T
     ms = phase_means(results)
-    print(f"# timed: {args.steps} steps, {step_s * 1e3:.3f} ms/step, T={T}; phase ms {ms}", file=sys.stderr,
-          flush=True)
-
-    # context: the same kernels with every edge horizontal (L = 0): plain
-    # forward-hashed counting of the whole graph, no BFS (the paper's FH/FHD
-    # comparison, Table I)
-    forward_hashed = None
-    if not args.main_only:
-        zero = torch.zeros(n, dtype=torch.int32, device="cuda")
-        fcounter = tc.Counter(n, nnz, tc.Options(timing=True))
-        for _ in range(args.warmup):
-            fcounter(rp, col, zero)
-        torch.cuda.synchronize()
-        fres = []
-        t_f0 = time.perf_counter()
-        for _ in range(args.steps):
-            fres.append(fcounter(rp, col, zero))
-        torch.cuda.synchronize()
-        fstep_s = (time.perf_counter() - t_f0) / args.steps
-        assert all(x.T == T for x in fres), "forward-hashed count differs"
-        forward_hashed = {"value": m / fstep_s, "ms_per_step": fstep_s * 1e3, "phase_ms": phase_means(fres)}
-        print(f"# forward-hashed (L = 0): {fstep_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-
-    # context: the per-vertex and per-edge modes of the same pass (triangles
-    # through every vertex / every edge; whole pipeline, output allocation
-    # included)
-    local = {}
-    for name, fn in () if args.main_only else (("vertex_triangles", tc.vertex_triangles),
-                                                ("edge_support", tc.edge_support)):
-        x_s, (_, rx) = time_calls(lambda: fn(rp, col), args.steps, args.warmup)
-        assert rx.T == T, f"{name} count differs"
-        local[name] = {"value": m / x_s, "ms_per_step": x_s * 1e3}
-        print(f"# {name}: {x_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-
-    # context: the paper's variants on the same kernels: Alg. 3 (cover-edge,
-    # one pass over full rows), the degree relabel, and Alg. 4 / Alg. 3 on the
-    # relabelled graph (BaderD / CED, relabel charged as pre-processing)
-    variants = None
-    if not args.main_only:
-        ce_s, rce = time_calls(lambda: tc.count_cover_edge(rp, col), args.steps, args.warmup)
-        rl_s, (rp2, col2, _) = time_calls(lambda: tc.relabel_by_degree(rp, col), args.steps, args.warmup)
-        dcounter = tc.Counter(n, nnz, tc.Options(timing=True))
-        bd_s, rbd = time_calls(lambda: dcounter(rp2, col2), args.steps, args.warmup)
-        ced_s, rced = time_calls(lambda: tc.count_cover_edge(rp2, col2), args.steps, args.warmup)
-        assert rce.T == T and rbd.T == T and rced.T == T, "a variant's count differs"
-        variants = {"cover_edge_alg3": {"ms_per_step": ce_s * 1e3, "value": m / ce_s},
-                    "degree_relabel_ms": rl_s * 1e3,
-                    "baderd": {"ms_per_step": (rl_s + bd_s) * 1e3, "value": m / (rl_s + bd_s),
-                               "count_ms": bd_s * 1e3, "k_percent": round(100.0 * rbd.e0 / m, 2),
-                               "levels": rbd.levels, "phase_ms": dict(rbd.ms)},
-                    "ced": {"ms_per_step": (rl_s + ced_s) * 1e3, "value": m / (rl_s + ced_s),
-                            "count_ms": ced_s * 1e3}}
-        print(f"# cover-edge (Alg. 3): {ce_s * 1e3:.3f} ms; relabel {rl_s * 1e3:.3f} ms; "
-              f"BaderD count {bd_s * 1e3:.3f} ms (k {variants['baderd']['k_percent']} %); CED count {ced_s * 1e3:.3f} ms",
-              file=sys.stderr, flush=True)
-        del rp2, col2
-
-    learned = None
-    if not (args.no_learned or args.main_only):
-        # learned schedule: profile this graph (each bucket group under each
-        # strategy in turn), train the cost network on the profile, let it
-        # propose a table, keep the classes of change that measure faster
-        # (all untimed), then time the same steps with the resulting table
-        from paper_2309_09064_amd import sched
-        t_l0 = time.perf_counter()
-        proposed, net, ds, losses = sched.learn_schedule([(rp, col)], steps=3000, lr=1e-2, verify=False)
-        table, vinfo = sched.verify_schedule([(rp, col)], proposed)
-        t_l1 = time.perf_counter()
-        lcounter = tc.Counter(n, nnz, tc.Options(timing=True, sched_table=table))
-        lstep_s, lres = timed_steps(lcounter, rp, col, args.steps, args.warmup)
-        assert all(x.T == T for x in lres), "learned schedule changed the count"
-        lms = phase_means(lres)
-        learned = {"value": m / lstep_s, "ms_per_step": lstep_s * 1e3, "phase_ms": lms,
-                   "strategy_items": lres[-1].strategy_items, "train_rows": int(len(ds.c)),
-                   "final_loss": float(losses[-1]), "profile_and_train_s": t_l1 - t_l0,
-                   "proposed_isect_ms": vinfo["proposed_ms"], "heuristic_isect_ms": vinfo["heuristic_ms"],
-                   "reverted_classes": [list(x) for x in vinfo["reverted"]],
-                   "trained_on": "this graph's own context profile; the network's table, then each class of "
-                                 "change kept only where the measured pass is faster"}
-        print(f"# learned schedule: {lstep_s * 1e3:.3f} ms/step; phase ms {lms}; network's table "
-              f"{vinfo['proposed_ms']:.3f} ms vs heuristic {vinfo['heuristic_ms']:.3f} ms (isect), "
-              f"reverted {vinfo['reverted']}", file=sys.stderr, flush=True)
+    log(f"timed: {args.steps} steps, {step_s * 1e3:.3f} ms/step, T={T}; phase ms {ms}")
+    exact = exact_vs_golden(f"kronecker{args.scale}", n, m, r) if args.seed == 1 else None
 
     lev, _ = tc.bfs_levels(rp, col)
-    rp_h, col_h, lev_h = rp.cpu().numpy(), col.cpu().numpy(), lev.cpu().numpy()
-    balg = b_alg(rp_h, col_h, lev_h)
+    balg = b_alg(rp, col, lev)
+    # the library's own element count gives the same figure: 4 B per probe
+    # element, the owner lists (every vertex's N1 and N0+ once), the records
+    balg_lib = 4 * r.probes + 4 * (nnz - r.e0) + 8 * r.e0 + 8 * n
+    assert balg == balg_lib, (balg, balg_lib)
+    del lev
+    torch.cuda.empty_cache()
     achieved = balg / (ms["isect"] * 1e-3) / 1e9
-    default_workload = args.scale == 20 and args.seed == 1
+    default_workload = args.scale == 24 and args.seed == 1
     traffic = read_traffic(kernel_source_hash()) if default_workload else None
-    print(f"# k_isect: B_alg={balg / 1e9:.3f} GB in {ms['isect']:.3f} ms -> {achieved:.0f} GB/s; "
-          f"counter traffic {traffic}", file=sys.stderr, flush=True)
+    log(f"k_isect: B_alg={balg / 1e9:.3f} GB in {ms['isect']:.3f} ms -> {achieved:.0f} GB/s; traffic {traffic}")
+
+    learned = None
+    secondary = {}
+    tables = None
+    if not args.no_learned:
+        proposed, verified, linfo = learned_tables(tc, torch, args.train_steps)
+        tables = [("network_table", proposed), ("verified_table", verified)]
+        legs = schedule_legs(tc, torch, n, rp, col, tables, args.steps, args.warmup, T)
+        gain = {k: step_s * 1e3 / v["ms_per_step"] for k, v in legs.items()}
+        learned = {**legs, **linfo, "speedup_vs_heuristic": gain,
+                   "target_met": any(g > 1.0 for g in gain.values())}
+        log(f"learned: {json.dumps({k: v['ms_per_step'] for k, v in legs.items()})} ms/step vs heuristic "
+            f"{step_s * 1e3:.3f}")
+
+    if not args.no_secondary:
+        secondary = secondary_legs(tc, torch, args, tables)
 
     cpu = None
-    exact = None
     if not args.no_cpu:
-        import oracle
-        g = oracle.as_csr(n, rp_h.astype(np.int64), col_h)
-        t2 = time.perf_counter()
-        olev, _ = oracle.bfs_levels(g)
-        ores = oracle.alg4(g, olev)
-        t3 = time.perf_counter()
-        exact = (ores.T == T) and (ores.T0 == r.T0) and (ores.T1 == r.T1)
-        cpu = {"value": m / (t3 - t2), "unit": "input edges/s", "cores": 1, "kind": "oracle",
-               "sample": f"the whole graph, one run of the oracle's serial BFS levels + Alg. 4 "
-                         f"(C, gcc -O2, one thread): {t3 - t2:.2f} s"}
+        cpu = cpu_baseline(rp, col, CPU_SECONDS)
+        log(f"cpu baseline: {cpu['sample']}")
+        if not args.no_secondary:
+            n20, rp20, col20 = make_graph(tc, torch, "kronecker", 20, 1)
+            cpu["alg4_serial_kronecker20"] = cpu_alg4_context(n20, rp20, col20)
+            del rp20, col20
 
     out = {
         "metric": METRIC,
@@ -298,14 +369,72 @@ def main():
                    "n": n, "m": m, "triangles": T, "T0": r.T0, "T1": r.T1, "e0": r.e0,
                    "k_percent": round(100.0 * r.e0 / m, 2), "levels": r.levels, "counts_bit_exact": exact,
                    "phase_ms": ms, "items": r.items, "strategy_items": r.strategy_items,
-                   "learned_schedule": learned, "forward_hashed_same_kernels": forward_hashed,
-                   "per_vertex_and_edge": local, "paper_variants": variants},
+                   "learned_schedule": learned, "secondary": secondary},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_isect",
                      "bytes_per_launch": balg, "ms_per_launch": ms["isect"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def secondary_legs(tc, torch, args, tables):
+    out = {}
+    # Chung-Lu 2^22 (power law): heuristic, and the learned tables
+    n, rp, col = make_graph(tc, torch, "chunglu", 22, 1)
+    m = col.numel() // 2
+    c = tc.Counter(n, col.numel(), tc.Options(timing=True))
+    st, res = timed_steps(c, rp, col, args.steps, args.warmup)
+    r = res[-1]
+    cl = {"workload": "chung-lu n=2^22, gamma 2.1, mean degree 32, max expected degree 2^17, seed 1",
+          "value": m / st, "ms_per_step": st * 1e3, "phase_ms": phase_means(res), "m": m, "triangles": r.T,
+          "counts_bit_exact": exact_vs_golden("chunglu22", n, m, r)}
+    if tables is not None:
+        legs = schedule_legs(tc, torch, n, rp, col, tables, args.steps, args.warmup, r.T)
+        cl["learned_schedule"] = {**legs, "speedup_vs_heuristic": {k: st * 1e3 / v["ms_per_step"]
+                                                                   for k, v in legs.items()}}
+    out["chunglu22"] = cl
+    log(f"chung-lu 2^22: {st * 1e3:.3f} ms/step")
+    del rp, col
+    torch.cuda.empty_cache()
+
+    # Kronecker scale 20: the heuristic step and the paper's comparison legs
+    n, rp, col = make_graph(tc, torch, "kronecker", 20, 1)
+    m = col.numel() // 2
+    c = tc.Counter(n, col.numel(), tc.Options(timing=True))
+    st, res = timed_steps(c, rp, col, args.steps, args.warmup)
+    r = res[-1]
+    T = r.T
+    k20 = {"workload": "kronecker scale 20 edgefactor 16, seed 1", "value": m / st, "ms_per_step": st * 1e3,
+           "phase_ms": phase_means(res), "m": m, "triangles": T,
+           "counts_bit_exact": exact_vs_golden("kronecker20", n, m, r)}
+    # the same kernels with every edge horizontal (L = 0): plain forward-hashed
+    # counting of the whole graph, no BFS (the paper's FH comparison)
+    zero = torch.zeros(n, dtype=torch.int32, device="cuda")
+    fs, fres = timed_steps(tc.Counter(n, col.numel(), tc.Options(timing=True)), rp, col, args.steps, args.warmup,
+                           levels=zero)
+    assert all(x.T == T for x in fres), "forward-hashed count differs"
+    k20["forward_hashed_same_kernels"] = {"value": m / fs, "ms_per_step": fs * 1e3, "phase_ms": phase_means(fres)}
+    for name, fn in (("vertex_triangles", tc.vertex_triangles), ("edge_support", tc.edge_support)):
+        x_s, (_, rx) = time_calls(lambda: fn(rp, col), args.steps, args.warmup)
+        assert rx.T == T, f"{name} count differs"
+        k20[name] = {"value": m / x_s, "ms_per_step": x_s * 1e3}
+    ce_s, rce = time_calls(lambda: tc.count_cover_edge(rp, col), args.steps, args.warmup)
+    rl_s, (rp2, col2, _) = time_calls(lambda: tc.relabel_by_degree(rp, col), args.steps, args.warmup)
+    bd_s, rbd = time_calls(lambda: tc.count(rp2, col2), args.steps, args.warmup)
+    ced_s, rced = time_calls(lambda: tc.count_cover_edge(rp2, col2), args.steps, args.warmup)
+    assert rce.T == T and rbd.T == T and rced.T == T, "a variant's count differs"
+    k20["paper_variants"] = {
+        "cover_edge_alg3": {"ms_per_step": ce_s * 1e3, "value": m / ce_s},
+        "degree_relabel_ms": rl_s * 1e3,
+        "baderd": {"ms_per_step": (rl_s + bd_s) * 1e3, "value": m / (rl_s + bd_s), "count_ms": bd_s * 1e3,
+                   "k_percent": round(100.0 * rbd.e0 / m, 2)},
+        "ced": {"ms_per_step": (rl_s + ced_s) * 1e3, "value": m / (rl_s + ced_s), "count_ms": ced_s * 1e3}}
+    out["kronecker20"] = k20
+    log(f"kronecker 20: {st * 1e3:.3f} ms/step; forward-hashed {fs * 1e3:.3f}; cover edge {ce_s * 1e3:.3f}")
+    del rp, col, rp2, col2, zero
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

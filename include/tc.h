@@ -26,7 +26,10 @@
  *  - Scratch memory comes only from the caller's workspace (ws, ws_bytes);
  *    query its size with the matching *_ws function.  Entry points allocate
  *    no device memory, so every auxiliary structure is released when the
- *    caller frees the workspace.  ws must be 256-byte aligned.
+ *    caller frees the workspace.  ws must be 256-byte aligned.  The one
+ *    library-held buffer is a 4 KB pinned host mailbox per calling thread,
+ *    created on the thread's first call, reused by all its later calls (no
+ *    allocation per call) and released by tc_thread_release().
  *  - stream: a hipStream_t passed as void*; NULL means the default stream.
  *    Work is enqueued on that stream.  Entry points that return a host value
  *    (nnz, a count) synchronise that stream before returning.
@@ -128,6 +131,10 @@ typedef struct tc_options {
                                  otherwise).  A hash strategy in a bucket
                                  whose owners exceed that table's capacity
                                  is replaced as with force_strategy.         */
+    int64_t batch_group_entries; /* batched counts: most vertices and most
+                                 CSR entries one internal group of graphs
+                                 may hold (a larger graph gets a group of
+                                 its own); 0 = 2^31 - 1024, the int32 limit  */
 } tc_options;
 
 /* Per-call statistics (host struct, all optional). */
@@ -156,6 +163,13 @@ const char *tc_strerror(int code);
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int tc_version(void);
+
+/* Releases the calling thread's pinned 4 KB result mailbox (see the
+ * conventions above); the thread's next call creates it again.  Call it
+ * before a worker thread ends, or before process exit to leave nothing
+ * allocated.  No call of this thread may be in flight.  Returns TC_OK or
+ * TC_ERR_HIP. */
+int tc_thread_release(void);
 
 /* ------------------------------------------------------------ CSR build */
 
@@ -217,25 +231,80 @@ uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_
                   size_t ws_bytes, void *stream);
 
 /*
- * Many graphs in one call.  The batch is one CSR over the disjoint union of
- * its graphs, vertex ids global: graph g owns the vertex range
- * [h_vtx_off[g], h_vtx_off[g+1]) and its rows hold only its own vertices.
- * Every phase runs once over the union (one persistent intersection launch
- * drains a single work queue for all graphs); a component never spans two
- * graphs, so each graph's levels, T0 and T1 are those it has on its own.
- *   graphs     number of graphs (>= 0)
- *   h_vtx_off  host int64[graphs + 1]: 0 = off[0] <= off[1] <= ... <=
- *              off[graphs] = n (empty graphs allowed)
- *   d_counts   device uint64[graphs], output: triangles of each graph
- * Returns the total over all graphs, or TC_COUNT_ERROR.  TC_ERR_ARG for bad
- * offsets; with TC_VALIDATE, TC_ERR_INVALID_CSR also when an edge joins two
- * graphs.  Synchronises.
+ * Many graphs in one call (the batched configuration: many graphs of uneven
+ * size, each counted as by tc_count on its own).  Every graph g is its own
+ * simple CSR with LOCAL int32 ids, packed one after another:
+ *   h_vtx_off   host int64[graphs + 1]: 0 = off[0] <= ... ; graph g has
+ *               n_g = h_vtx_off[g+1] - h_vtx_off[g] vertices
+ *   h_edge_off  host int64[graphs + 1]: 0 = off[0] <= ... ; graph g has
+ *               nnz_g = h_edge_off[g+1] - h_edge_off[g] CSR entries
+ *   d_row_ptr   device int32[h_vtx_off[graphs] + graphs]: graph g's n_g + 1
+ *               row pointers start at d_row_ptr[h_vtx_off[g] + g], run from
+ *               0 to nnz_g, and index its own entries
+ *   d_col_idx   device int32[h_edge_off[graphs]]: graph g's entries at
+ *               d_col_idx[h_edge_off[g] ...], ids in [0, n_g)
+ *   d_levels    device int32 per packed vertex (h_vtx_off[graphs]), or NULL:
+ *               computed per graph as by tc_bfs_levels
+ *   d_counts    device uint64[graphs], output: triangles of each graph
+ * Each graph must fit int32 CSR (n_g and nnz_g below 2^31 - 1024); the batch
+ * as a whole need not: it is processed in groups of consecutive graphs whose
+ * union fits (opt->batch_group_entries).  Per group, one pass: ids rebased to
+ * the group (an id outside its graph is clamped into it; TC_VALIDATE reports
+ * it), BFS levels with one workgroup per graph, the partition, and one
+ * persistent intersection launch that drains the work of all the group's
+ * graphs, each hit added to its graph's count.  A component never spans two
+ * graphs, so each graph's levels, T0 and T1 are those it has alone.  The
+ * workspace (tc_count_batched_ws, which needs the offsets) holds a rebased
+ * copy of the largest group's CSR besides tc_count's buffers.
+ * Returns the total over all graphs, or TC_COUNT_ERROR: TC_ERR_ARG for bad
+ * offsets, TC_ERR_OVERFLOW for a graph beyond int32, and with TC_VALIDATE
+ * TC_ERR_INVALID_CSR for malformed rows or ids.  stats, when given, sums the
+ * groups (levels: the largest level count of any graph).  Synchronises.
  */
-int tc_count_batched_ws(int32_t graphs, int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_bytes);
-uint64_t tc_count_batched(int32_t graphs, const int64_t *h_vtx_off, int32_t n, int64_t nnz,
+int tc_count_batched_ws(int32_t graphs, const int64_t *h_vtx_off, const int64_t *h_edge_off, const tc_options *opt,
+                        size_t *h_ws_bytes);
+uint64_t tc_count_batched(int32_t graphs, const int64_t *h_vtx_off, const int64_t *h_edge_off,
                           const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
                           const tc_options *opt, uint64_t *d_counts, tc_stats *stats, void *ws, size_t ws_bytes,
                           void *stream);
+
+/*
+ * BFS levels of every graph of a packed batch (layout and workspace as for
+ * tc_count_batched), each graph as by tc_bfs_levels on its own: every
+ * component searched from its smallest local id (Algorithm 4, first loop).
+ * One workgroup per graph, largest graphs first.
+ *   d_levels        device int32[h_vtx_off[graphs]], output (packed like the
+ *                   vertices)
+ *   h_levels_count  host, optional: the largest level count of any graph
+ * Local ids must lie within their graph (not checked here; an id outside is
+ * clamped into it).  Synchronises.
+ */
+int tc_bfs_levels_batched(int32_t graphs, const int64_t *h_vtx_off, const int64_t *h_edge_off,
+                          const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t *d_levels,
+                          int32_t *h_levels_count, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The same batch as one captured graph of device work, replayed at will:
+ * tc_batch_plan_create enqueues nothing on its own but records the whole
+ * pipeline of tc_count_batched (levels computed, no host read anywhere in
+ * it) into a HIP graph bound to the given buffers; tc_batch_plan_launch
+ * replays it on `stream`, asynchronously, and leaves the per-graph counts in
+ * d_counts when the stream reaches that point.  The buffers (row_ptr,
+ * col_idx, d_counts, ws) must stay allocated and unchanged in size while the
+ * plan lives; their contents may change between launches (same offsets).
+ * Launches of one plan must not overlap.  The plan object is host memory
+ * owned by the caller through tc_batch_plan_destroy.  Options as for
+ * tc_count_batched except TC_TIMING and TC_VALIDATE (TC_ERR_ARG: both read
+ * results on the host).  Workspace: tc_count_batched_ws.  create
+ * synchronises `stream` (it uploads the offsets); launch must run on the
+ * device that was current at create (TC_ERR_ARG otherwise).
+ */
+typedef struct tc_batch_plan tc_batch_plan;
+int tc_batch_plan_create(int32_t graphs, const int64_t *h_vtx_off, const int64_t *h_edge_off,
+                         const int32_t *d_row_ptr, const int32_t *d_col_idx, const tc_options *opt,
+                         uint64_t *d_counts, void *ws, size_t ws_bytes, void *stream, tc_batch_plan **h_plan);
+int tc_batch_plan_launch(tc_batch_plan *plan, void *stream);
+int tc_batch_plan_destroy(tc_batch_plan *plan);
 
 /*
  * The strategy every bucket gets from tc_count under opt for a graph of n

@@ -14,7 +14,7 @@ Counting" (arXiv 2309.09064):
 * :func:`alg4`               T0 = triangles inside G0, T1 = triangles with one
                              horizontal edge (the two sums of Alg. 4), by merges
 * :func:`count_emd`          direction-oriented sorted-merge edge iterator
-* :func:`count_emd_rows`     the same over a sample of rows, on host threads
+* :func:`count_emd_entries`  the same over a sample of edges, on host threads
 * :func:`alg3`               cover-edge count (Alg. 3)
 * :func:`vertex_triangles`   per-vertex triangle counts
 * :func:`vertex_triangles_at`  the same for sampled vertices, by another definition
@@ -70,8 +70,8 @@ def _load():
         lib.orc_alg4.restype = ctypes.c_int
         lib.orc_count_emd.argtypes = [ctypes.c_int64, _i64, _i32]
         lib.orc_count_emd.restype = ctypes.c_uint64
-        lib.orc_count_emd_rows.argtypes = [ctypes.c_int64, _i64, _i32, ctypes.c_int64, _i64, ctypes.c_int]
-        lib.orc_count_emd_rows.restype = ctypes.c_uint64
+        lib.orc_count_emd_entries.argtypes = [ctypes.c_int64, _i64, _i32, ctypes.c_int64, _i64, ctypes.c_int]
+        lib.orc_count_emd_entries.restype = ctypes.c_uint64
         lib.orc_alg3.argtypes = [ctypes.c_int64, _i64, _i32, _i32]
         lib.orc_alg3.restype = ctypes.c_uint64
         lib.orc_vertex_triangles.argtypes = [ctypes.c_int64, _i64, _i32, _u64]
@@ -193,15 +193,15 @@ def count_emd(g: CSR) -> int:
     return int(_load().orc_count_emd(g.n, g.row_ptr, _col_or_dummy(g)))
 
 
-def count_emd_rows(g: CSR, rows, threads: int = 1) -> int:
-    """Triangles u < v < w whose smallest vertex u is in ``rows``, by the same
-    sorted-merge edge iterator, the rows shared among ``threads`` host
-    threads.  All rows give T."""
-    us = np.ascontiguousarray(rows, dtype=np.int64)
-    if us.size and (us.min() < 0 or us.max() >= g.n):
-        raise ValueError("row out of range")
-    return int(_load().orc_count_emd_rows(g.n, g.row_ptr, _col_or_dummy(g), us.size,
-                                          us if us.size else np.zeros(1, np.int64), int(threads)))
+def count_emd_entries(g: CSR, entries, threads: int = 1) -> int:
+    """Triangles u < v < w whose edge uv has its entry (u, v) in ``entries``
+    (CSR entry indices), by the same sorted-merge edge iterator, the entries
+    shared among ``threads`` host threads.  All entries give T."""
+    es = np.ascontiguousarray(entries, dtype=np.int64)
+    if es.size and (es.min() < 0 or es.max() >= g.nnz):
+        raise ValueError("entry out of range")
+    return int(_load().orc_count_emd_entries(g.n, g.row_ptr, _col_or_dummy(g), es.size,
+                                             es if es.size else np.zeros(1, np.int64), int(threads)))
 
 
 def alg3(g: CSR, level: np.ndarray | None = None) -> int:

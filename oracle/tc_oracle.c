@@ -5,8 +5,9 @@
  * benchmark's CPU-baseline leg may load this library.  It shares no code with
  * the GPU library: no headers, kernels, helpers or tables.
  *
- * Plain, serial, obviously-correct C (one routine, orc_count_emd_rows, shares
- * its rows among OpenMP threads to time the definition on every host core).
+ * Plain, serial, obviously-correct C (one routine, orc_count_emd_entries,
+ * shares its edges among OpenMP threads to time the definition on every host
+ * core).
  * Every routine names the passage of
  * Bader, "Fast Triangle Counting" (arXiv 2309.09064) that it follows.  Row
  * pointers are int64 here; the Python wrapper converts.
@@ -248,28 +249,34 @@ uint64_t orc_count_emd(int64_t n, const int64_t *row_ptr, const int32_t *col)
 }
 
 /*
- * The same count restricted to the rows u listed in us[0..k) (ascending or
- * not): the triangles whose smallest vertex is one of them.  The rows are
- * shared among `threads` OpenMP threads (1 = serial), so a sample of rows
- * times the definition on every host core; the whole range of u gives T.
+ * The same count restricted to the CSR entries listed in es[0..k): an entry
+ * e = (u, v) with u < v adds the common neighbours w > v of u and v, so each
+ * triangle u < v < w is counted at the entry of its edge uv.  Entries with
+ * v < u add nothing (each undirected edge does its work at one of its two
+ * entries).  The entries are shared among `threads` OpenMP threads (1 =
+ * serial), so a sample of edges times the definition on every host core;
+ * the whole range of entries gives T.  The row u of an entry is found by
+ * binary search in row_ptr.
  */
-uint64_t orc_count_emd_rows(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t k, const int64_t *us,
-                            int threads)
+uint64_t orc_count_emd_entries(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t k, const int64_t *es,
+                               int threads)
 {
-    (void)n;
     uint64_t T = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : T) num_threads(threads)
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : T) num_threads(threads)
     for (int64_t i = 0; i < k; ++i) {
-        int64_t u = us[i];
-        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
-            int64_t v = col[j];
-            if (v <= u) continue;
-            int64_t a = row_ptr[u], ae = row_ptr[u + 1], b = row_ptr[v], be = row_ptr[v + 1];
-            while (a < ae && b < be) {
-                if (col[a] < col[b]) ++a;
-                else if (col[a] > col[b]) ++b;
-                else { if (col[a] > v) ++T; ++a; ++b; }
-            }
+        int64_t e = es[i];
+        int64_t lo = 0, hi = n - 1;           /* last row u with row_ptr[u] <= e */
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo + 1) / 2;
+            if (row_ptr[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        int64_t u = lo, v = col[e];
+        if (v <= u) continue;
+        int64_t a = row_ptr[u], ae = row_ptr[u + 1], b = row_ptr[v], be = row_ptr[v + 1];
+        while (a < ae && b < be) {
+            if (col[a] < col[b]) ++a;
+            else if (col[a] > col[b]) ++b;
+            else { if (col[a] > v) ++T; ++a; ++b; }
         }
     }
     return T;

@@ -18,7 +18,7 @@ from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_BUCKETS, TC_NUM_STRAT
                     TC_STRAT_WG_HASH, TC_TIMING, TC_VALIDATE)
 
 __all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count", "count_profile", "workspace",
-           "count_batched", "pack_csr", "schedule_table", "vertex_triangles", "edge_support",
+           "count_batched", "pack_csr", "Batch", "BatchPlan", "batch_workspace_bytes", "bfs_levels_batched", "schedule_table", "vertex_triangles", "edge_support",
            "relabel_by_degree", "count_cover_edge",
            "Counter", "CountResult", "new_profile",
            "STRATEGY_NAMES", "TC_STRAT_AUTO", "TC_STRAT_WAVE_HASH", "TC_STRAT_WG_HASH", "TC_STRAT_BSEARCH",
@@ -73,6 +73,7 @@ class Options:
     wave_max_owner: int = 0
     merge_max_owner: int = 0            # 0 = default (7), -1 = never
     sched_table: torch.Tensor | None = None   # int32[TC_NUM_BUCKETS] on the device: selects TC_SCHED_TABLE
+    batch_group_entries: int = 0        # batched counts: vertices / entries per internal group; 0 = int32 limit
 
     def to_c(self):
         o = _capi.tc_options()
@@ -92,6 +93,7 @@ class Options:
         o.grid_blocks = self.grid_blocks
         o.wave_max_owner = self.wave_max_owner
         o.merge_max_owner = self.merge_max_owner
+        o.batch_group_entries = self.batch_group_entries
         return o
 
 
@@ -252,50 +254,158 @@ def _result(T, st) -> CountResult:
         strategy_items={STRATEGY_NAMES[k]: int(st.strategy_items[k]) for k in range(TC_NUM_STRATEGIES)})
 
 
-def pack_csr(graphs):
-    """Union CSR of several device CSRs [(row_ptr, col), ...]: global ids,
-    plus the host int64 vertex offsets ``vtx_off`` (len(graphs) + 1)."""
+@dataclass
+class Batch:
+    """A packed batch of graphs, each a CSR with local ids (see
+    ``tc_count_batched`` in include/tc.h): graph g's n_g + 1 row pointers
+    start at ``row_ptr[vtx_off[g] + g]``, its entries at
+    ``col[edge_off[g]]``."""
+    row_ptr: torch.Tensor     # int32 device, vtx_off[-1] + graphs entries
+    col: torch.Tensor         # int32 device, edge_off[-1] entries (local ids)
+    vtx_off: "object"         # numpy int64[graphs + 1]
+    edge_off: "object"        # numpy int64[graphs + 1]
+
+    @property
+    def graphs(self) -> int:
+        return len(self.vtx_off) - 1
+
+    @classmethod
+    def from_union(cls, row_ptr: torch.Tensor, col: torch.Tensor, vtx_off) -> "Batch":
+        """Layout conversion (torch ops on the device, no counting): a CSR
+        over the disjoint union with global ids, graph g owning the vertices
+        [vtx_off[g], vtx_off[g+1]), becomes the packed per-graph CSRs with
+        local ids.  Rows must hold only their own graph's vertices."""
+        import numpy as np
+        voff = np.ascontiguousarray(vtx_off, dtype=np.int64)
+        G = len(voff) - 1
+        dev = row_ptr.device
+        voff_t = torch.from_numpy(voff).to(dev)
+        rp64 = row_ptr.to(torch.int64)
+        eoff_t = rp64[voff_t]
+        n_g = voff_t[1:] - voff_t[:-1]
+        slot_g = torch.repeat_interleave(torch.arange(G, device=dev), n_g + 1)
+        slot_v = torch.arange(slot_g.numel(), device=dev) - slot_g      # vertex of each row-pointer slot
+        rp_packed = (rp64[slot_v] - eoff_t[slot_g]).to(torch.int32)
+        ent_g = torch.repeat_interleave(torch.arange(G, device=dev), eoff_t[1:] - eoff_t[:-1])
+        col_local = (col.to(torch.int64) - voff_t[ent_g]).to(torch.int32)
+        return cls(rp_packed.contiguous(), col_local.contiguous(), voff, eoff_t.cpu().numpy().astype(np.int64))
+
+
+def pack_csr(graphs) -> Batch:
+    """Packs device CSRs [(row_ptr, col), ...] (local ids kept) into a Batch."""
     import numpy as np
     sizes = [int(rp.numel()) - 1 for rp, _ in graphs]
     nnzs = [int(c.numel()) for _, c in graphs]
     voff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     eoff = np.concatenate([[0], np.cumsum(nnzs)]).astype(np.int64)
-    if voff[-1] >= 2 ** 31 or eoff[-1] >= 2 ** 31:
-        raise ValueError("the union does not fit an int32 CSR")
     dev = graphs[0][0].device if graphs else torch.device("cuda", torch.cuda.current_device())
-    rps = [rp[:-1] + int(eoff[g]) for g, (rp, _) in enumerate(graphs)]
-    cols = [c + int(voff[g]) for g, (_, c) in enumerate(graphs)]
-    row_ptr = torch.cat(rps + [torch.tensor([int(eoff[-1])], dtype=torch.int32, device=dev)])
-    col = torch.cat(cols) if cols else torch.zeros(0, dtype=torch.int32, device=dev)
-    return row_ptr.to(torch.int32).contiguous(), col.to(torch.int32).contiguous(), voff
+    row_ptr = torch.cat([rp.to(torch.int32) for rp, _ in graphs]) if graphs else torch.zeros(0, dtype=torch.int32,
+                                                                                               device=dev)
+    col = torch.cat([c.to(torch.int32) for _, c in graphs]) if graphs else torch.zeros(0, dtype=torch.int32,
+                                                                                       device=dev)
+    return Batch(row_ptr.contiguous(), col.contiguous(), voff, eoff)
 
 
-def count_batched(row_ptr: torch.Tensor, col: torch.Tensor, vtx_off, levels: torch.Tensor | None = None,
-                  options: Options | None = None, stream=None):
-    """Per-graph triangle counts of a packed batch (see :func:`pack_csr`).
-    Returns (counts: int64 tensor viewing the uint64 counts, CountResult of
-    the whole union)."""
+def _offsets(batch: Batch):
     import numpy as np
-    _require_i32_cuda(row_ptr, "row_ptr")
-    _require_i32_cuda(col, "col")
-    if levels is not None:
-        _require_i32_cuda(levels, "levels")
-    off = np.ascontiguousarray(vtx_off, dtype=np.int64)
-    graphs = len(off) - 1
-    n, nnz = row_ptr.numel() - 1, col.numel()
-    lib = _capi.load()
+    voff = np.ascontiguousarray(batch.vtx_off, dtype=np.int64)
+    eoff = np.ascontiguousarray(batch.edge_off, dtype=np.int64)
+    if voff.shape != eoff.shape or voff.ndim != 1 or len(voff) < 1:
+        raise ValueError("vtx_off and edge_off: int64 arrays of graphs + 1 entries")
+    return voff, eoff
+
+
+def batch_workspace_bytes(batch: Batch, options: Options | None = None) -> int:
+    voff, eoff = _offsets(batch)
     opt = (options or Options()).to_c()
     need = ctypes.c_size_t()
-    _check(lib.tc_count_batched_ws(graphs, n, nnz, ctypes.byref(opt), ctypes.byref(need)), "tc_count_batched_ws")
-    ws = workspace(need.value, row_ptr.device)
-    counts = torch.empty(max(graphs, 1), dtype=torch.int64, device=row_ptr.device)
+    _check(_capi.load().tc_count_batched_ws(len(voff) - 1, voff.ctypes.data_as(ctypes.c_void_p),
+                                            eoff.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opt),
+                                            ctypes.byref(need)), "tc_count_batched_ws")
+    return need.value
+
+
+def count_batched(batch: Batch, levels: torch.Tensor | None = None, options: Options | None = None, stream=None,
+                  ws: torch.Tensor | None = None):
+    """Per-graph triangle counts of a packed batch (tc_count_batched).
+    Returns (counts: int64 tensor viewing the uint64 counts, CountResult of
+    the whole batch)."""
+    _require_i32_cuda(batch.row_ptr, "row_ptr")
+    _require_i32_cuda(batch.col, "col")
+    if levels is not None:
+        _require_i32_cuda(levels, "levels")
+    voff, eoff = _offsets(batch)
+    graphs = len(voff) - 1
+    lib = _capi.load()
+    opt = (options or Options()).to_c()
+    need = batch_workspace_bytes(batch, options)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, batch.row_ptr.device)
+    counts = torch.empty(max(graphs, 1), dtype=torch.int64, device=batch.row_ptr.device)
     st = _capi.tc_stats()
-    T = lib.tc_count_batched(graphs, off.ctypes.data_as(ctypes.c_void_p), n, nnz, _ptr(row_ptr), _ptr(col),
-                             _ptr(levels), ctypes.byref(opt), _ptr(counts), ctypes.byref(st), _ptr(ws),
-                             need.value, _stream(stream))
+    T = lib.tc_count_batched(graphs, voff.ctypes.data_as(ctypes.c_void_p), eoff.ctypes.data_as(ctypes.c_void_p),
+                             _ptr(batch.row_ptr), _ptr(batch.col), _ptr(levels), ctypes.byref(opt), _ptr(counts),
+                             ctypes.byref(st), _ptr(ws), need, _stream(stream))
     if T == TC_COUNT_ERROR:
         raise TCError(lib.tc_last_error(), "tc_count_batched")
     return counts[:graphs], _result(T, st)
+
+
+def bfs_levels_batched(batch: Batch, stream=None):
+    """BFS levels of every graph of the batch, packed like its vertices
+    (tc_bfs_levels_batched); returns (levels, largest level count)."""
+    _require_i32_cuda(batch.row_ptr, "row_ptr")
+    _require_i32_cuda(batch.col, "col")
+    voff, eoff = _offsets(batch)
+    need = batch_workspace_bytes(batch)
+    ws = workspace(need, batch.row_ptr.device)
+    lev = torch.empty(max(int(voff[-1]), 1), dtype=torch.int32, device=batch.row_ptr.device)
+    nl = ctypes.c_int32()
+    _check(_capi.load().tc_bfs_levels_batched(len(voff) - 1, voff.ctypes.data_as(ctypes.c_void_p),
+                                              eoff.ctypes.data_as(ctypes.c_void_p), _ptr(batch.row_ptr),
+                                              _ptr(batch.col), _ptr(lev), ctypes.byref(nl), _ptr(ws), need,
+                                              _stream(stream)), "tc_bfs_levels_batched")
+    return lev[:int(voff[-1])], nl.value
+
+
+class BatchPlan:
+    """The batch's whole pipeline captured once into a HIP graph
+    (tc_batch_plan_create) and replayed by :meth:`launch`
+    (tc_batch_plan_launch).  Holds the workspace and the counts buffer."""
+
+    def __init__(self, batch: Batch, options: Options | None = None, stream=None):
+        _require_i32_cuda(batch.row_ptr, "row_ptr")
+        _require_i32_cuda(batch.col, "col")
+        self.batch = batch
+        voff, eoff = _offsets(batch)
+        self.graphs = len(voff) - 1
+        self._opt = (options or Options()).to_c()
+        need = batch_workspace_bytes(batch, options)
+        self.ws = workspace(need, batch.row_ptr.device)
+        self.counts = torch.zeros(max(self.graphs, 1), dtype=torch.int64, device=batch.row_ptr.device)
+        self._plan = ctypes.c_void_p()
+        lib = _capi.load()
+        _check(lib.tc_batch_plan_create(self.graphs, voff.ctypes.data_as(ctypes.c_void_p),
+                                        eoff.ctypes.data_as(ctypes.c_void_p), _ptr(batch.row_ptr), _ptr(batch.col),
+                                        ctypes.byref(self._opt), _ptr(self.counts), _ptr(self.ws), need,
+                                        _stream(stream), ctypes.byref(self._plan)), "tc_batch_plan_create")
+
+    def launch(self, stream=None):
+        """Replays the pipeline on ``stream`` (asynchronous); the counts are
+        in ``self.counts[:graphs]`` once the stream reaches this point."""
+        _check(_capi.load().tc_batch_plan_launch(self._plan, _stream(stream)), "tc_batch_plan_launch")
+        return self.counts[:self.graphs]
+
+    def close(self):
+        if self._plan:
+            _check(_capi.load().tc_batch_plan_destroy(self._plan), "tc_batch_plan_destroy")
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def vertex_triangles(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor | None = None,

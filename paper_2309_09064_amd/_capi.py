@@ -51,6 +51,7 @@ class tc_options(ctypes.Structure):
         ("wave_max_owner", ctypes.c_int32),
         ("merge_max_owner", ctypes.c_int32),
         ("sched_table", ctypes.c_void_p),
+        ("batch_group_entries", ctypes.c_int64),
     ]
 
 
@@ -87,6 +88,7 @@ _SIGNATURES = {
     "tc_last_error": (ctypes.c_int, []),
     "tc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tc_version": (ctypes.c_int, []),
+    "tc_thread_release": (ctypes.c_int, []),
     "tc_build_csr_ws": (ctypes.c_int, [_i32, _i64, _P(_sz)]),
     "tc_build_csr": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _i64, _P(_i64), _vp, _sz, _vp]),
     "tc_bfs_levels_ws": (ctypes.c_int, [_i32, _i64, _P(_sz)]),
@@ -104,9 +106,14 @@ _SIGNATURES = {
     "tc_relabel_degree": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "tc_count_cover_edge": (ctypes.c_uint64, [_i32, _i64, _vp, _vp, _vp, _P(tc_options), _P(tc_stats), _vp, _sz,
                                               _vp]),
-    "tc_count_batched_ws": (ctypes.c_int, [_i32, _i32, _i64, _P(tc_options), _P(_sz)]),
-    "tc_count_batched": (ctypes.c_uint64, [_i32, _vp, _i32, _i64, _vp, _vp, _vp, _P(tc_options), _vp, _P(tc_stats),
-                                           _vp, _sz, _vp]),
+    "tc_count_batched_ws": (ctypes.c_int, [_i32, _vp, _vp, _P(tc_options), _P(_sz)]),
+    "tc_count_batched": (ctypes.c_uint64, [_i32, _vp, _vp, _vp, _vp, _vp, _P(tc_options), _vp, _P(tc_stats), _vp,
+                                           _sz, _vp]),
+    "tc_batch_plan_create": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _P(tc_options), _vp, _vp, _sz, _vp,
+                                            _P(_vp)]),
+    "tc_batch_plan_launch": (ctypes.c_int, [_vp, _vp]),
+    "tc_bfs_levels_batched": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, _P(_i32), _vp, _sz, _vp]),
+    "tc_batch_plan_destroy": (ctypes.c_int, [_vp]),
     "tc_schedule_table": (ctypes.c_int, [_i32, _i64, _P(tc_options), _vp, _vp]),
     "tc_mlp_param_count": (ctypes.c_int, [_i32, _i32, _P(_i64)]),
     "tc_mlp_init": (ctypes.c_int, [_vp, _i32, _i32, _u64, _vp]),

@@ -8,7 +8,7 @@
 //  2. only if vertices are left unvisited, their roots are found as
 //     connected components whose labels converge to the minimum id (links
 //     always hook the larger root under the smaller; the sampling-then-
-//     finish order of Sutton, Ben-Nun and Bar-Yossef's Afforest), restricted
+//     finish order of Sutton, Ben-Nun and Bar-Noy's Afforest), restricted
 //     to those vertices, and one multi-source BFS runs from all of them.
 // Hop distances are unique, so the result does not depend on the order of
 // the parallel work.

@@ -48,6 +48,13 @@ __global__ void k_mail_i32(const int32_t *src, uint64_t *dst) {
 }
 }  // namespace
 
+int mailbox_release() {
+    if (!t_mail.host) return TC_OK;
+    const hipError_t e = hipHostFree(t_mail.host);
+    t_mail = Mailbox{};
+    return e == hipSuccess ? TC_OK : TC_ERR_HIP;
+}
+
 int mailbox(Mailbox *out) {
     if (!t_mail.host) {
         void *h = nullptr;
@@ -73,9 +80,9 @@ int mail_i32(const int32_t *src, uint64_t *dst, hipStream_t s) {
     return TC_OK;
 }
 
-namespace {
-
 // ---------------------------------------------------------------- validation
+
+namespace {
 
 // bit 0: row_ptr not monotone / wrong ends; bit 1: column out of range;
 // bit 2: row not strictly ascending (duplicate or unsorted); bit 3: self-loop;
@@ -112,6 +119,8 @@ __global__ void k_validate(int32_t n, int64_t nnz, const int32_t *__restrict__ r
     }
 }
 
+}  // namespace
+
 int validate_device(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, const int32_t *lev,
                     int32_t *scratch, hipStream_t s) {
     TC_HIP_TRY(hipMemsetAsync(scratch, 0, sizeof(int32_t), s));
@@ -127,6 +136,8 @@ int validate_device(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *co
     if (n == 0 && nnz != 0) bad |= 1;
     return bad ? TC_ERR_INVALID_CSR : TC_OK;
 }
+
+namespace {
 
 // ---------------------------------------------------------------- options
 
@@ -172,71 +183,24 @@ int check_graph_args(int32_t n, int64_t nnz, const void *rp, const void *col) {
     return TC_OK;
 }
 
-int check_ws(void *ws, size_t ws_bytes, size_t need) {
-    if (need > ws_bytes) return TC_ERR_WORKSPACE;
-    if (need > 0 && !ws) return TC_ERR_WORKSPACE;
-    if (((uintptr_t)ws & 255) != 0) return TC_ERR_WORKSPACE;
-    return TC_OK;
-}
+int check_ws(void *ws, size_t ws_bytes, size_t need) { return check_workspace(ws, ws_bytes, need); }
 
 int fail(int code) {
     set_error(code);
     return code;
 }
 
-// ---------------------------------------------------------------- tc_count layout
+}  // namespace
 
-// ---------------------------------------------------------------- batches
-
-// gid[v] = the graph whose vertex range [off[g], off[g+1]) holds v.
-__global__ void k_batch_gid(int32_t graphs, const int64_t *__restrict__ off, int32_t n, int32_t *__restrict__ gid) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int32_t lo = 0, hi = graphs - 1;   // last g with off[g] <= v
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= v) lo = mid; else hi = mid - 1;
-    }
-    gid[v] = lo;
+int check_workspace(void *ws, size_t ws_bytes, size_t need) {
+    if (need > ws_bytes) return TC_ERR_WORKSPACE;
+    if (need > 0 && !ws) return TC_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return TC_ERR_WORKSPACE;
+    return TC_OK;
 }
 
-// bad |= 1 when an edge joins two graphs of the batch.
-__global__ void k_batch_check(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                              const int32_t *__restrict__ gid, int32_t *__restrict__ bad) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
-    const int32_t gx = gid[x];
-    for (int32_t e = rp[x]; e < rp[x + 1]; ++e) {
-        const int32_t y = col[e];
-        if (y < 0 || y >= n || gid[y] != gx) {
-            atomicOr(bad, 1);
-            return;
-        }
-    }
-}
-
-struct BatchPlan {
-    int64_t *off;
-    int32_t *gid;
-};
-
-BatchPlan carve_batch(Carver &c, int32_t graphs, int32_t n) {
-    BatchPlan B;
-    B.off = c.take<int64_t>((size_t)graphs + 1);
-    B.gid = c.take<int32_t>(n > 0 ? n : 1);
-    return B;
-}
-
-struct CountPlan {
-    int32_t *levels;
-    PartBufs pb;
-    void *scratch;
-    size_t scratch_bytes;
-    int32_t *flag;
-};
-
-CountPlan carve_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels, bool edge_pos = false) {
-    CountPlan P;
+CountPlanBufs carve_count_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels, bool edge_pos) {
+    CountPlanBufs P;
     const int64_t nn = n > 0 ? n : 1;
     const int64_t nz = nnz > 0 ? nnz : 1;
     P.levels = own_levels ? c.take<int32_t>(nn) : nullptr;
@@ -267,8 +231,6 @@ CountPlan carve_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels, bool ed
     return P;
 }
 
-}  // namespace
-
 int options_cfg(const tc_options *opt, CountCfg *cfg, int *flags) { return make_cfg(opt, cfg, flags); }
 
 }  // namespace tc
@@ -294,7 +256,9 @@ const char *tc_strerror(int code) {
     }
 }
 
-int tc_version(void) { return 10000; }
+int tc_version(void) { return 10100; }
+
+int tc_thread_release(void) { return fail(mailbox_release()); }
 
 int tc_build_csr_ws(int32_t n, int64_t m_tuples, size_t *h_ws_bytes) {
     if (!h_ws_bytes || n < 0 || m_tuples < 0) return fail(TC_ERR_ARG);
@@ -414,32 +378,17 @@ int tc_count_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_byte
     rc = make_cfg(opt, &cfg, &flags);
     if (rc != TC_OK) return fail(rc);
     Carver c(nullptr, 0);
-    carve_plan(c, n, nnz, true);
+    carve_count_plan(c, n, nnz, true, false);
     *h_ws_bytes = c.used();
     return fail(TC_OK);
 }
 
-struct BatchArgs {
-    int32_t graphs;
-    const int64_t *h_off;
-    uint64_t *d_counts;
-};
-
 static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                     const int32_t *d_levels, const tc_options *opt, tc_stats *stats, uint64_t *d_prof, void *ws,
-                    size_t ws_bytes, void *stream, const BatchArgs *batch = nullptr,
+                    size_t ws_bytes, void *stream,
                     uint64_t *d_tv = nullptr, bool edge = false, uint32_t *d_sup = nullptr, bool cover = false) {
     int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
     if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
-    if (batch) {   // offsets: 0 = off[0] <= off[1] <= ... <= off[graphs] = n
-        if (batch->graphs < 0 || !batch->h_off || (batch->graphs > 0 && !batch->d_counts)) {
-            fail(TC_ERR_ARG);
-            return TC_COUNT_ERROR;
-        }
-        bool ok = batch->h_off[0] == 0 && batch->h_off[batch->graphs] == n;
-        for (int32_t g = 0; ok && g < batch->graphs; ++g) ok = batch->h_off[g] <= batch->h_off[g + 1];
-        if (!ok || (batch->graphs == 0 && n != 0)) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
-    }
     CountCfg cfg;
     int flags;
     rc = make_cfg(opt, &cfg, &flags);
@@ -460,8 +409,7 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
     size_t need = 0;
     {
         Carver c(nullptr, 0);
-        carve_plan(c, n, nnz, true, edge);
-        if (batch) carve_batch(c, batch->graphs, n);
+        carve_count_plan(c, n, nnz, true, edge);
         need = c.used();
     }
     rc = check_ws(ws, ws_bytes, need);
@@ -470,58 +418,25 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
     rc = device_info(&di);
     if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (batch && batch->graphs > 0 &&
-        hipMemsetAsync(batch->d_counts, 0, sizeof(uint64_t) * (size_t)batch->graphs, s) != hipSuccess) {
-        fail(TC_ERR_HIP);
-        return TC_COUNT_ERROR;
-    }
     if (n == 0) {   // no vertices, no triangles
         if (stats) memset(stats, 0, sizeof(*stats));
         fail(TC_OK);
         return 0;
     }
     Carver c(ws, ws_bytes);
-    CountPlan P = carve_plan(c, n, nnz, true, edge);
+    CountPlanBufs P = carve_count_plan(c, n, nnz, true, edge);
     if (flags & TC_VALIDATE) {
         rc = validate_device(n, nnz, d_row_ptr, d_col_idx, d_levels, P.flag, s);
         if (rc != TC_OK) { fail(rc); return TC_COUNT_ERROR; }
     }
-    if (batch) {
-        const BatchPlan B = carve_batch(c, batch->graphs, n);
-        if (hipMemcpyAsync(B.off, batch->h_off, sizeof(int64_t) * ((size_t)batch->graphs + 1), hipMemcpyHostToDevice,
-                           s) != hipSuccess) {
-            fail(TC_ERR_HIP);
-            return TC_COUNT_ERROR;
-        }
-        const unsigned gb = (unsigned)(((int64_t)n + 255) / 256);
-        hipLaunchKernelGGL(k_batch_gid, dim3(gb), dim3(256), 0, s, batch->graphs, B.off, n, B.gid);
-        if (hipGetLastError() != hipSuccess) { fail(TC_ERR_HIP); return TC_COUNT_ERROR; }
-        if (flags & TC_VALIDATE) {
-            int32_t bad = 0;
-            if (hipMemsetAsync(P.flag, 0, sizeof(int32_t), s) != hipSuccess) { fail(TC_ERR_HIP); return TC_COUNT_ERROR; }
-            hipLaunchKernelGGL(k_batch_check, dim3(gb), dim3(256), 0, s, n, d_row_ptr, d_col_idx, B.gid, P.flag);
-            if (hipGetLastError() != hipSuccess ||
-                hipMemcpyAsync(&bad, P.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess) {
-                fail(TC_ERR_HIP);
-                return TC_COUNT_ERROR;
-            }
-            if (bad) { fail(TC_ERR_INVALID_CSR); return TC_COUNT_ERROR; }
-        }
-        cfg.gid = B.gid;
-        cfg.batch_counts = reinterpret_cast<unsigned long long *>(batch->d_counts);
-    }
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     const bool timing = (flags & TC_TIMING) != 0;
+    EventSet ev;   // destroyed on every return
     auto fail_ev = [&](int code) {
-        for (auto &e : ev) if (e) (void)hipEventDestroy(e);
         fail(code);
         return TC_COUNT_ERROR;
     };
     if (timing) {
-        for (auto &e : ev)
-            if (hipEventCreate(&e) != hipSuccess) return fail_ev(TC_ERR_HIP);
-        if (hipEventRecord(ev[0], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
+        if (ev.create(3) != TC_OK || hipEventRecord(ev.e[0], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
     }
     BfsOut bo;
     const int32_t *lev = d_levels;
@@ -530,7 +445,7 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
         if (rc != TC_OK) return fail_ev(rc);
         lev = P.levels;
     }
-    if (timing && hipEventRecord(ev[1], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
+    if (timing && hipEventRecord(ev.e[1], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
     rc = partition_run(n, nnz, d_row_ptr, d_col_idx, lev, P.pb, P.scratch, P.scratch_bytes, s);
     if (rc != TC_OK) return fail_ev(rc);
     PartBufs pb = P.pb;
@@ -539,7 +454,7 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
         if (rc != TC_OK) return fail_ev(rc);
         cfg.cover_lev = lev;
     }
-    if (timing && hipEventRecord(ev[2], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
+    if (timing && hipEventRecord(ev.e[2], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
     CountOut co;
     rc = count_run(n, nnz, pb, cfg, &co, P.scratch, P.scratch_bytes, s);
     if (rc != TC_OK) return fail_ev(rc);
@@ -556,13 +471,12 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
         stats->bfs_rounds = bo.rounds;
         for (int k = 0; k < TC_NUM_STRATEGIES; ++k) stats->strategy_items[k] = co.strategy_items[k];
         if (timing) {
-            (void)hipEventElapsedTime(&stats->ms_bfs, ev[0], ev[1]);
-            (void)hipEventElapsedTime(&stats->ms_partition, ev[1], ev[2]);
+            (void)hipEventElapsedTime(&stats->ms_bfs, ev.e[0], ev.e[1]);
+            (void)hipEventElapsedTime(&stats->ms_partition, ev.e[1], ev.e[2]);
             stats->ms_bucket = co.ms_bucket;
             stats->ms_isect = co.ms_isect;
         }
     }
-    for (auto &e : ev) if (e) (void)hipEventDestroy(e);
     fail(TC_OK);
     return co.T0 + co.T1;
 }
@@ -570,28 +484,6 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
 uint64_t tc_count(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
                   const tc_options *opt, tc_stats *stats, void *ws, size_t ws_bytes, void *stream) {
     return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream);
-}
-
-int tc_count_batched_ws(int32_t graphs, int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_bytes) {
-    if (!h_ws_bytes || graphs < 0) return fail(TC_ERR_ARG);
-    int rc = check_graph_args(n, nnz, (const void *)1, (const void *)1);
-    if (rc != TC_OK) return fail(rc);
-    CountCfg cfg;
-    int flags;
-    rc = make_cfg(opt, &cfg, &flags);
-    if (rc != TC_OK) return fail(rc);
-    Carver c(nullptr, 0);
-    carve_plan(c, n, nnz, true);
-    carve_batch(c, graphs, n);
-    *h_ws_bytes = c.used();
-    return fail(TC_OK);
-}
-
-uint64_t tc_count_batched(int32_t graphs, const int64_t *h_vtx_off, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
-                          const int32_t *d_col_idx, const int32_t *d_levels, const tc_options *opt,
-                          uint64_t *d_counts, tc_stats *stats, void *ws, size_t ws_bytes, void *stream) {
-    const BatchArgs b{graphs, h_vtx_off, d_counts};
-    return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, &b);
 }
 
 int tc_schedule_table(int32_t n, int64_t nnz, const tc_options *opt, int32_t *d_table, void *stream) {
@@ -613,8 +505,7 @@ uint64_t tc_vertex_triangles(int32_t n, int64_t nnz, const int32_t *d_row_ptr, c
                              const int32_t *d_levels, const tc_options *opt, uint64_t *d_tv, tc_stats *stats,
                              void *ws, size_t ws_bytes, void *stream) {
     if (!d_tv && n > 0) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
-    return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, nullptr,
-                      d_tv);
+    return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, d_tv);
 }
 
 int tc_edge_support_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_ws_bytes) {
@@ -626,7 +517,7 @@ int tc_edge_support_ws(int32_t n, int64_t nnz, const tc_options *opt, size_t *h_
     rc = make_cfg(opt, &cfg, &flags);
     if (rc != TC_OK) return fail(rc);
     Carver c(nullptr, 0);
-    carve_plan(c, n, nnz, true, true);
+    carve_count_plan(c, n, nnz, true, true);
     *h_ws_bytes = c.used();
     return fail(TC_OK);
 }
@@ -636,14 +527,14 @@ uint64_t tc_edge_support(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const
                          size_t ws_bytes, void *stream) {
     if (!d_sup && nnz > 0) { fail(TC_ERR_ARG); return TC_COUNT_ERROR; }
     return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, nullptr,
-                      nullptr, true, d_sup);
+                      true, d_sup);
 }
 
 uint64_t tc_count_cover_edge(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                              const int32_t *d_levels, const tc_options *opt, tc_stats *stats, void *ws,
                              size_t ws_bytes, void *stream) {
     return count_impl(n, nnz, d_row_ptr, d_col_idx, d_levels, opt, stats, nullptr, ws, ws_bytes, stream, nullptr,
-                      nullptr, false, nullptr, true);
+                      false, nullptr, true);
 }
 
 int tc_relabel_degree_ws(int32_t n, int64_t nnz, size_t *h_ws_bytes) {

@@ -20,6 +20,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <mutex>
+
 #include "tc_internal.hpp"
 
 namespace tc {
@@ -1508,6 +1510,83 @@ int schedule_table_run(int32_t n, int64_t nnz, const CountCfg &cfg, int32_t *tab
     return TC_OK;
 }
 
+namespace {
+
+// The largest dynamic LDS request and the blocks per CU of each
+// intersection kernel variant, per device: the attribute call and the
+// occupancy query run once per (device, kernel, LDS size), outside the
+// timed region of any call.
+struct LaunchCache {
+    int dev;
+    const void *kern;
+    size_t lds;
+    int per_cu;
+};
+std::mutex g_launch_mu;
+LaunchCache g_launch[64];
+int g_launch_n = 0;
+
+int isect_blocks_per_cu(const void *kern, size_t lds, int *per_cu) {
+    int dev = 0;
+    TC_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    for (int i = 0; i < g_launch_n; ++i)
+        if (g_launch[i].dev == dev && g_launch[i].kern == kern && g_launch[i].lds == lds) {
+            *per_cu = g_launch[i].per_cu;
+            return TC_OK;
+        }
+    TC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int pc = 1;
+    TC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, kIsectThreads, lds));
+    if (pc < 1) pc = 1;
+    if (g_launch_n < 64) g_launch[g_launch_n++] = LaunchCache{dev, kern, lds, pc};
+    *per_cu = pc;
+    return TC_OK;
+}
+
+// The intersection kernel variant, its table size and LDS bytes for cfg
+// (kern is NULL for an invalid mix of modes).
+struct IsectShape {
+    const void *kern = nullptr;
+    int table_ints = 0;
+    size_t lds_bytes = 0;
+};
+
+IsectShape isect_shape(const CountCfg &cfg) {
+    IsectShape sh;
+    const int wave_log2 = ilog2_host(cfg.wave_slots);
+    const int wg_log2 = ilog2_host(cfg.wg_slots);
+    const bool batch = cfg.gid != nullptr;
+    const bool vertex = cfg.tv != nullptr;
+    const bool edge = cfg.sup != nullptr;
+    const bool cover = cfg.cover_lev != nullptr;
+    if ((vertex || edge || cover) && (batch || cfg.prof)) return sh;
+    if ((int)vertex + (int)edge + (int)cover > 1) return sh;
+    sh.table_ints = 1 << wg_log2;
+    if ((kIsectWaves << wave_log2) > sh.table_ints) sh.table_ints = kIsectWaves << wave_log2;
+    sh.lds_bytes = (size_t)((edge || vertex ? 2 : 1) * sh.table_ints +
+                            kIsectWaves * (vertex || edge || cover ? kScratchIdsInts : kScratchInts)) *
+                   sizeof(int32_t);
+    sh.kern = cfg.prof ? (batch ? (const void *)k_isect<true, kModeBatch> : (const void *)k_isect<true, kModePlain>)
+              : vertex ? (const void *)k_isect<false, kModeVertex>
+              : edge   ? (const void *)k_isect<false, kModeEdge>
+              : cover  ? (const void *)k_isect<false, kModeCover>
+              : batch  ? (const void *)k_isect<false, kModeBatch>
+                       : (const void *)k_isect<false, kModePlain>;
+    return sh;
+}
+
+}  // namespace
+
+int count_prepare(int32_t n, int64_t nnz, const CountCfg &cfg) {
+    (void)nnz;
+    const IsectShape sh = isect_shape(cfg);
+    if (!sh.kern) return TC_ERR_ARG;
+    int per_cu = 1;
+    if (n > 0) TC_TRY(isect_blocks_per_cu(sh.kern, sh.lds_bytes, &per_cu));
+    return TC_OK;
+}
+
 int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, CountOut *out, void *ws,
               size_t ws_bytes, hipStream_t s) {
     Carver c(ws, ws_bytes);
@@ -1519,20 +1598,36 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     const int wg_log2 = ilog2_host(cfg.wg_slots);
     const SchedCfg sc = sched_cfg(n, nnz, cfg);
 
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    // mode checks and the launch shape come first: nothing below is timed
+    // that is not device work
+    const bool batch = cfg.gid != nullptr;
+    const bool vertex = cfg.tv != nullptr;
+    const bool edge = cfg.sup != nullptr;
+    const bool cover = cfg.cover_lev != nullptr;
+    if (edge && (!pb.pos0 || !pb.pos1 || !cfg.rp || !cfg.col)) return TC_ERR_ARG;
+    const IsectShape sh = isect_shape(cfg);
+    if (!sh.kern) return TC_ERR_ARG;
+    const int table_ints = sh.table_ints;
+    const size_t lds_bytes = sh.lds_bytes;
+    int per_cu = 1;
+    if (n > 0) TC_TRY(isect_blocks_per_cu(sh.kern, lds_bytes, &per_cu));
+    if (getenv("TC_LOG")) fprintf(stderr, "libtc: k_isect %d blocks/CU, %zu B LDS\n", per_cu, lds_bytes);
+
+    EventSet ev;
     if (cfg.timing) {
-        for (auto &e : ev) TC_HIP_TRY(hipEventCreate(&e));
-        TC_HIP_TRY(hipEventRecord(ev[0], s));
+        TC_TRY(ev.create(3));
+        TC_HIP_TRY(hipEventRecord(ev.e[0], s));
     }
     const int64_t nn = n > 0 ? n : 1;
-    TC_HIP_TRY(hipMemsetAsync(L.cnt, 0, sizeof(int32_t) * 2 * nn, s));
-    TC_HIP_TRY(hipMemsetAsync(L.work, 0, sizeof(unsigned long long) * 2 * nn, s));
-    TC_HIP_TRY(hipMemsetAsync(L.bucket_items, 0, sizeof(int32_t) * (kBuckets + 1), s));
-    TC_HIP_TRY(hipMemsetAsync(L.bucket_cur, 0, sizeof(int32_t) * kBuckets, s));
-    TC_HIP_TRY(hipMemsetAsync(L.q, 0, sizeof(int32_t) * kQueueBlockInts, s));
-    TC_HIP_TRY(hipMemsetAsync(L.stats, 0, sizeof(unsigned long long) * 16, s));
-    if (cfg.tv && n > 0) TC_HIP_TRY(hipMemsetAsync(cfg.tv, 0, sizeof(unsigned long long) * (size_t)n, s));
-    if (cfg.sup && nnz > 0) TC_HIP_TRY(hipMemsetAsync(cfg.sup, 0, sizeof(uint32_t) * (size_t)nnz, s));
+    // zeroed by fill kernels (a captured graph records no memset nodes)
+    TC_TRY(fill_u32(L.cnt, 0, 2 * nn, s));
+    TC_TRY(fill_u32(L.work, 0, 4 * nn, s));
+    TC_TRY(fill_u32(L.bucket_items, 0, kBuckets + 1, s));
+    TC_TRY(fill_u32(L.bucket_cur, 0, kBuckets, s));
+    TC_TRY(fill_u32(L.q, 0, kQueueBlockInts, s));
+    TC_TRY(fill_u32(L.stats, 0, 32, s));
+    if (cfg.tv && n > 0) TC_TRY(fill_u32(cfg.tv, 0, 2 * (int64_t)n, s));
+    if (cfg.sup && nnz > 0) TC_TRY(fill_u32(cfg.sup, 0, nnz, s));
     const unsigned gp = (unsigned)di.cus * 8;
     if (n > 0) {
         hipLaunchKernelGGL(k_own, dim3(gp), dim3(kThreads), 0, s, n, pb.e0x2, pb.rp0, pb.c0, pb.up0, pb.rp1, pb.vrec, L.cnt,
@@ -1548,32 +1643,8 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
                            L.work, sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats, nullptr);
         TC_HIP_TRY(hipGetLastError());
     }
-    if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev[1], s));
+    if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev.e[1], s));
     if (n > 0) {
-        int table_ints = 1 << wg_log2;
-        if ((kIsectWaves << wave_log2) > table_ints) table_ints = kIsectWaves << wave_log2;
-        const bool batch = cfg.gid != nullptr;
-        const bool vertex = cfg.tv != nullptr;
-        const bool edge = cfg.sup != nullptr;
-        const bool cover = cfg.cover_lev != nullptr;
-        if ((vertex || edge || cover) && (batch || cfg.prof)) return TC_ERR_ARG;
-        if ((int)vertex + (int)edge + (int)cover > 1) return TC_ERR_ARG;
-        if (edge && (!pb.pos0 || !pb.pos1 || !cfg.rp || !cfg.col)) return TC_ERR_ARG;
-        const size_t lds_bytes = (size_t)((edge || vertex ? 2 : 1) * table_ints +
-                                          kIsectWaves * (vertex || edge || cover ? kScratchIdsInts : kScratchInts)) *
-                                 sizeof(int32_t);
-        const void *kern = cfg.prof ? (batch ? (const void *)k_isect<true, kModeBatch>
-                                             : (const void *)k_isect<true, kModePlain>)
-                                    : vertex ? (const void *)k_isect<false, kModeVertex>
-                                    : edge   ? (const void *)k_isect<false, kModeEdge>
-                                    : cover  ? (const void *)k_isect<false, kModeCover>
-                                    : batch  ? (const void *)k_isect<false, kModeBatch>
-                                             : (const void *)k_isect<false, kModePlain>;
-        TC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
-        int per_cu = 1;
-        TC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kIsectThreads, lds_bytes));
-        if (per_cu < 1) per_cu = 1;
-        if (getenv("TC_LOG")) fprintf(stderr, "libtc: k_isect %d blocks/CU, %zu B LDS\n", per_cu, lds_bytes);
         const unsigned gi = cfg.grid_blocks > 0 ? (unsigned)cfg.grid_blocks : (unsigned)(di.cus * per_cu);
         Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1, pb.vrec, pb.pos0, pb.pos1};
         const Sink sk{cfg.gid, cfg.batch_counts, cfg.tv, cfg.sup, cfg.cover_lev};
@@ -1604,7 +1675,8 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         hipLaunchKernelGGL(k_edge_mirror, dim3(gp), dim3(kThreads), 0, s, n, nnz, cfg.rp, cfg.col, cfg.sup);
         TC_HIP_TRY(hipGetLastError());
     }
-    if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev[2], s));
+    if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev.e[2], s));
+    if (!cfg.sync) return TC_OK;   // results stay on the device (captured pipelines)
     Mailbox mb;
     TC_TRY(mailbox(&mb));
     TC_TRY(mail_u64(reinterpret_cast<const uint64_t *>(L.stats), mb.dev, 16, s));
@@ -1625,12 +1697,10 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         }
         out->items = items;
         if (cfg.timing) {
-            TC_HIP_TRY(hipEventElapsedTime(&out->ms_bucket, ev[0], ev[1]));
-            TC_HIP_TRY(hipEventElapsedTime(&out->ms_isect, ev[1], ev[2]));
+            TC_HIP_TRY(hipEventElapsedTime(&out->ms_bucket, ev.e[0], ev.e[1]));
+            TC_HIP_TRY(hipEventElapsedTime(&out->ms_isect, ev.e[1], ev.e[2]));
         }
     }
-    if (cfg.timing)
-        for (auto &e : ev) (void)hipEventDestroy(e);
     return TC_OK;
 }
 

@@ -55,6 +55,20 @@ struct Carver {
     bool fits() const { return used() <= cap; }
 };
 
+// HIP events released on every exit path of the function that holds them.
+struct EventSet {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    int create(int count) {
+        for (int i = 0; i < count && i < 4; ++i)
+            if (hipEventCreate(&e[i]) != hipSuccess) return TC_ERR_HIP;
+        return TC_OK;
+    }
+    ~EventSet() {
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
 // ------------------------------------------------------------------ device info
 
 struct DeviceInfo {
@@ -66,14 +80,16 @@ int device_info(DeviceInfo *out);
 // ------------------------------------------------------------------ mailbox
 
 // A 4 KB pinned host buffer, mapped into the device address space, private
-// to the calling host thread (allocated on its first use and kept until the
-// process ends).  Kernels write small results there; the host reads them
-// after synchronising the stream, without a device-to-host copy.
+// to the calling host thread: allocated on the thread's first call, reused
+// by every later one, released by tc_thread_release (or at process end).
+// Kernels write small results there; the host reads them after
+// synchronising the stream, without a device-to-host copy.
 struct Mailbox {
     uint64_t *host = nullptr;
     uint64_t *dev = nullptr;
 };
 int mailbox(Mailbox *out);
+int mailbox_release();
 // dst[i] = src[i] for i < count (count <= 64), one tiny kernel.
 int mail_u64(const uint64_t *src, uint64_t *dst, int count, hipStream_t s);
 int mail_i32(const int32_t *src, uint64_t *dst, hipStream_t s);
@@ -130,7 +146,11 @@ __device__ __forceinline__ void tile_rows(const P *rp, int64_t nrows, int64_t t0
     __syncthreads();
 }
 
-// ------------------------------------------------------------------ scan
+// ------------------------------------------------------------------ fill and scan
+
+// p[i] = value for the first `count` 32-bit words: a kernel, so that it may
+// be recorded into a captured graph (where memset nodes are avoided).
+int fill_u32(void *p, uint32_t value, int64_t count, hipStream_t s);
 
 // Exclusive prefix sum of n values (int32 or int64 input) into int32 or int64
 // output of n+1 entries (out[n] = total).  Three-level reduce-then-scan.
@@ -221,7 +241,32 @@ struct CountCfg {
     const int32_t *rp = nullptr, *col = nullptr;   // the input CSR (per-edge support only)
     const int32_t *cover_lev = nullptr;   // cover-edge count (over a cover_view_run view): the levels, or NULL
     bool timing = false;
+    bool sync = true;   // false: enqueue only; no host read, no synchronisation (out is not filled)
 };
+// The intersection kernel's launch shape for cfg, resolved once per device
+// before any stream capture (count_run then finds it cached).
+int count_prepare(int32_t n, int64_t nnz, const CountCfg &cfg);
+
+// ------------------------------------------------------------------ shared by the entry points
+
+// The buffers one count over n vertices and nnz entries takes from a
+// workspace: levels (own_levels), the partition's lists and records (with
+// the per-entry maps of per-edge support when edge_pos), a flag block and
+// the scratch shared by the BFS, partition and counting phases.
+struct CountPlanBufs {
+    int32_t *levels;
+    PartBufs pb;
+    void *scratch;
+    size_t scratch_bytes;
+    int32_t *flag;
+};
+CountPlanBufs carve_count_plan(Carver &c, int32_t n, int64_t nnz, bool own_levels, bool edge_pos);
+// TC_ERR_WORKSPACE unless ws holds `need` bytes and is 256-byte aligned.
+int check_workspace(void *ws, size_t ws_bytes, size_t need);
+// TC_VALIDATE's device check of a CSR (and levels, when non-NULL) through
+// one int of scratch; synchronises the stream.
+int validate_device(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, const int32_t *lev,
+                    int32_t *scratch, hipStream_t s);
 // Probe elements per wavefront item when the options leave it at 0: 16384
 // below 2^23 input entries, 32768 below 2^24, 65536 from there on.
 int default_chunk_work(int64_t nnz);

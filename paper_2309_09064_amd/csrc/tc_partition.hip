@@ -328,8 +328,8 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
     Carver c(ws, ws_bytes);
     PartLayout L = carve_part(c, n, nnz);
     if (!c.fits()) return TC_ERR_WORKSPACE;
-    TC_HIP_TRY(hipMemsetAsync(pb.d0, 0, sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
-    TC_HIP_TRY(hipMemsetAsync(pb.up0, 0, sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
+    TC_TRY(fill_u32(pb.d0, 0, n > 0 ? n : 1, s));
+    TC_TRY(fill_u32(pb.up0, 0, n > 0 ? n : 1, s));
     const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
     if (nnz > 0) {
         hipLaunchKernelGGL(k_part_vld, dim3(grid_for(n, 256)), dim3(256), 0, s, n, rp, lev, L.vld);

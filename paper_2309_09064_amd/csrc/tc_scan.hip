@@ -71,6 +71,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const Tin *in, int64_t 
 
 int64_t nblocks(int64_t n) { return (n + kTile - 1) / kTile; }
 
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 template <class Tin, class Tout>
 int scan_impl(const Tin *in, Tout *out, int64_t n, int64_t *ws, hipStream_t s) {
     if (n <= kTile) {
@@ -101,6 +106,15 @@ size_t scan_ws_bytes(int64_t n) {
         n = nb;
     }
     return total + 256;
+}
+
+int fill_u32(void *p, uint32_t value, int64_t count, hipStream_t s) {
+    if (count <= 0) return TC_OK;
+    int64_t g = (count + kThreads - 1) / kThreads;
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(kThreads), 0, s, static_cast<uint32_t *>(p), value, count);
+    TC_HIP_TRY(hipGetLastError());
+    return TC_OK;
 }
 
 int scan_exclusive_i32_to_i32(const int32_t *in, int32_t *out, int64_t n, void *ws, hipStream_t s) {

@@ -164,23 +164,78 @@ def test_mlp_args_rejected_before_device(lib):
     assert lib.tc_mlp_forward(fake, 32, 4, fake, -1, fake, None) == _capi.TC_ERR_ARG
 
 
-@pytest.mark.parametrize("off,n", [([1, 5, 10], 10), ([0, 6, 5], 5), ([0, 5, 9], 10), ([0], 3)])
-def test_batch_offsets_rejected_before_device(lib, off, n):
-    fake = ctypes.c_void_p(0x1000)
-    o = (ctypes.c_int64 * len(off))(*off)
-    T = lib.tc_count_batched(len(off) - 1, o, n, 20, fake, fake, None, None, fake, None, fake, 1 << 30, None)
-    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_ARG
+def _i64s(v):
+    return (ctypes.c_int64 * len(v))(*v)
 
 
-def test_batch_needs_counts_buffer(lib):
+# bad offsets: not starting at 0, decreasing, edges on an empty graph, a
+# graph beyond int32 (overflow)
+@pytest.mark.parametrize("voff,eoff,code", [
+    ([1, 5, 10], [0, 8, 20], _capi.TC_ERR_ARG),
+    ([0, 5, 10], [2, 8, 20], _capi.TC_ERR_ARG),
+    ([0, 6, 5], [0, 8, 20], _capi.TC_ERR_ARG),
+    ([0, 5, 10], [0, 9, 7], _capi.TC_ERR_ARG),
+    ([0, 0, 10], [0, 4, 20], _capi.TC_ERR_ARG),
+    ([0, 5, 5 + (1 << 31)], [0, 8, 20], _capi.TC_ERR_OVERFLOW),
+    ([0, 5, 10], [0, 8, 8 + (1 << 31)], _capi.TC_ERR_OVERFLOW),
+])
+def test_batch_offsets_rejected_before_device(lib, voff, eoff, code):
     fake = ctypes.c_void_p(0x1000)
-    o = (ctypes.c_int64 * 3)(0, 4, 10)
-    T = lib.tc_count_batched(2, o, 10, 20, fake, fake, None, None, None, None, fake, 1 << 30, None)
+    T = lib.tc_count_batched(len(voff) - 1, _i64s(voff), _i64s(eoff), fake, fake, None, None, fake, None, fake,
+                             1 << 40, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == code
+    sz = ctypes.c_size_t()
+    assert lib.tc_count_batched_ws(len(voff) - 1, _i64s(voff), _i64s(eoff), None, ctypes.byref(sz)) == code
+    plan = ctypes.c_void_p()
+    assert lib.tc_batch_plan_create(len(voff) - 1, _i64s(voff), _i64s(eoff), fake, fake, None, fake, fake, 1 << 40,
+                                    None, ctypes.byref(plan)) == code
+    assert not plan.value
+
+
+def test_batch_needs_counts_buffer_and_workspace(lib):
+    fake = ctypes.c_void_p(0x1000)
+    voff, eoff = _i64s([0, 4, 10]), _i64s([0, 8, 20])
+    T = lib.tc_count_batched(2, voff, eoff, fake, fake, None, None, None, None, fake, 1 << 30, None)
     assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_ARG
     sz, sz1 = ctypes.c_size_t(), ctypes.c_size_t()
-    assert lib.tc_count_batched_ws(2, 10, 20, None, ctypes.byref(sz)) == _capi.TC_OK
+    assert lib.tc_count_batched_ws(2, voff, eoff, None, ctypes.byref(sz)) == _capi.TC_OK
     assert lib.tc_count_ws(10, 20, None, ctypes.byref(sz1)) == _capi.TC_OK
-    assert sz.value > sz1.value
+    assert sz.value > sz1.value   # the rebased copy of the group CSR and the BFS scratch
+    T = lib.tc_count_batched(2, voff, eoff, fake, fake, None, None, fake, None, fake, 256, None)
+    assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_WORKSPACE
+
+
+def test_batch_groups_shrink_the_workspace(lib):
+    # cutting the batch into groups sizes the workspace for the largest group
+    voff = _i64s([0] + [1000 * (i + 1) for i in range(64)])
+    eoff = _i64s([0] + [20000 * (i + 1) for i in range(64)])
+    whole, grouped = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.tc_count_batched_ws(64, voff, eoff, None, ctypes.byref(whole)) == _capi.TC_OK
+    opt = _capi.tc_options()
+    opt.batch_group_entries = 40000
+    assert lib.tc_count_batched_ws(64, voff, eoff, ctypes.byref(opt), ctypes.byref(grouped)) == _capi.TC_OK
+    assert grouped.value * 8 < whole.value
+    opt.batch_group_entries = -1
+    assert lib.tc_count_batched_ws(64, voff, eoff, ctypes.byref(opt), ctypes.byref(grouped)) == _capi.TC_ERR_ARG
+
+
+def test_batch_plan_arguments(lib):
+    fake = ctypes.c_void_p(0x1000)
+    voff, eoff = _i64s([0, 4, 10]), _i64s([0, 8, 20])
+    plan = ctypes.c_void_p()
+    for flags in (_capi.TC_TIMING, _capi.TC_VALIDATE):   # both read results on the host
+        opt = _capi.tc_options()
+        opt.flags = flags
+        assert lib.tc_batch_plan_create(2, voff, eoff, fake, fake, ctypes.byref(opt), fake, fake, 1 << 30, None,
+                                        ctypes.byref(plan)) == _capi.TC_ERR_ARG
+    assert lib.tc_batch_plan_create(2, voff, eoff, fake, fake, None, fake, fake, 1 << 30, None, None) == \
+        _capi.TC_ERR_ARG
+    assert lib.tc_batch_plan_create(2, voff, eoff, fake, fake, None, None, fake, 1 << 30, None,
+                                    ctypes.byref(plan)) == _capi.TC_ERR_ARG
+    assert lib.tc_batch_plan_create(2, voff, eoff, fake, fake, None, fake, fake, 64, None,
+                                    ctypes.byref(plan)) == _capi.TC_ERR_WORKSPACE
+    assert lib.tc_batch_plan_launch(None, None) == _capi.TC_ERR_ARG
+    assert lib.tc_batch_plan_destroy(None) == _capi.TC_OK
 
 
 def test_vertex_triangles_needs_an_output_before_device(lib):

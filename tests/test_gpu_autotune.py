@@ -47,8 +47,12 @@ def test_tuned_batch_counts_exact(tc, tmp_path):
     for i in range(12):
         n, s, d = graphgen.kronecker(8 + i % 5, seed=50 + i)
         gs.append(oracle.build_csr(n, s, d))
-    rp, col, off = tc.pack_csr([(dev(g.row_ptr), dev(g.col)) for g in gs])
-    opts, _ = autotune.tune(rp, col, space={"chunk_work": [4096, 16384], "wave_slots": [512, 2048],
-                                            "wg_slots": [32768], "grid_blocks": [0]}, repeats=1)
-    counts, _ = tc.count_batched(rp, col, off, options=opts)
+    # tuned on the disjoint union (one graph with global ids), applied to the
+    # packed batch
+    voff = np.concatenate([[0], np.cumsum([g.n for g in gs])]).astype(np.int64)
+    urp = np.concatenate([[0], np.cumsum(np.concatenate([np.diff(g.row_ptr) for g in gs]))])
+    ucol = np.concatenate([g.col.astype(np.int64) + voff[i] for i, g in enumerate(gs)])
+    opts, _ = autotune.tune(dev(urp), dev(ucol), space={"chunk_work": [4096, 16384], "wave_slots": [512, 2048],
+                                                        "wg_slots": [32768], "grid_blocks": [0]}, repeats=1)
+    counts, _ = tc.count_batched(tc.pack_csr([(dev(g.row_ptr), dev(g.col)) for g in gs]), options=opts)
     assert counts.cpu().tolist() == [oracle.alg4(g).T for g in gs]

@@ -1,11 +1,17 @@
-"""GPU parity of the batched count: per-graph counts of a packed batch equal
-the oracle's count of each graph on its own, for small mixed batches (every
-graph checked, empty members included) and for the full 4096-graph batch of
-Erdos-Renyi and Kronecker members (a sample of graphs checked one by one,
-the largest among them, plus the total)."""
+"""GPU parity of the batched count (tc_count_batched, tc_batch_plan_*):
+per-graph counts of a packed batch, each graph a CSR with local ids, equal
+the oracle's count of each graph on its own.  Small mixed batches check
+every graph (empty members included), under every strategy, with given
+levels, in several internal groups, and through a captured plan replayed
+several times with eager work between the replays; the full 4096-graph batch
+of Erdos-Renyi and Kronecker members checks all 4096 counts against the
+oracle's stored counts (tests/golden/batch_counts.txt, written by
+tests/golden/make_batch_counts.py, which calls the oracle only), both by the
+eager call and by plan replays."""
 from __future__ import annotations
 
 import concurrent.futures as cf
+import os
 import time
 
 import numpy as np
@@ -17,6 +23,8 @@ from _graphs import complete, csr_from_edges, cycle, gnp, petersen, random_tree,
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_counts.txt")
 
 
 @pytest.fixture(scope="module")
@@ -53,93 +61,242 @@ def small_batch(seed):
     return [gs[i] for i in order]
 
 
+def want_counts(gs):
+    return np.array([oracle.alg4(g).T if g.n else 0 for g in gs], dtype=np.int64)
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_small_batch_every_graph(tc, seed):
     gs = small_batch(seed)
-    rp, col, off = tc.pack_csr([to_gpu(g) for g in gs])
-    counts, res = tc.count_batched(rp, col, off, options=tc.Options(validate=True))
-    want = np.array([oracle.alg4(g).T if g.n else 0 for g in gs], dtype=np.int64)
+    b = tc.pack_csr([to_gpu(g) for g in gs])
+    counts, res = tc.count_batched(b, options=tc.Options(validate=True))
+    want = want_counts(gs)
     assert np.array_equal(counts.cpu().numpy(), want)
     assert res.T == int(want.sum())
+    # T0 and T1 depend on the levels: the per-graph BFS keeps the serial roots
+    refs = [oracle.alg4(g) for g in gs if g.n]
+    assert (res.T0, res.T1, res.e0) == (sum(r.T0 for r in refs), sum(r.T1 for r in refs), sum(r.E0 for r in refs))
+
+
+@pytest.mark.parametrize("seed,cap", [(1, 0), (2, 0), (9, 700)])
+def test_batched_levels_every_vertex(tc, seed, cap):
+    gs = small_batch(seed)
+    b = tc.pack_csr([to_gpu(g) for g in gs])
+    lev, nl = tc.bfs_levels_batched(b)
+    want = np.concatenate([oracle.bfs_levels(g)[0] for g in gs if g.n])
+    assert np.array_equal(lev.cpu().numpy(), want)
+    assert nl == max(int(oracle.bfs_levels(g)[0].max()) + 1 for g in gs if g.n)
+
+
+def test_batched_levels_many_components(tc):
+    # a graph of many small components and isolated vertices, a long path
+    # (one level per vertex) and a star, side by side
+    rng = np.random.default_rng(3)
+    parts = []
+    for i in range(300):
+        k = int(rng.integers(1, 6))
+        parts.append([(3 * i + a, 3 * i + b) for a in range(k % 3) for b in range(a + 1, 3)])
+    comps = csr_from_edges(900 + 50, [e for p in parts for e in p])
+    path = csr_from_edges(1500, [(i, i + 1) for i in range(1499)])
+    star = csr_from_edges(2000, [(0, i) for i in range(1, 2000)])
+    gs = [comps, path, star, gnp(3000, 0.002, 5)]
+    b = tc.pack_csr([to_gpu(g) for g in gs])
+    lev, nl = tc.bfs_levels_batched(b)
+    want = np.concatenate([oracle.bfs_levels(g)[0] for g in gs])
+    assert np.array_equal(lev.cpu().numpy(), want)
+    assert nl == 1500
+    counts, _ = tc.count_batched(b)
+    assert np.array_equal(counts.cpu().numpy(), want_counts(gs))
 
 
 @pytest.mark.parametrize("force", [0, 1, 2, 3])
 def test_batch_strategy_invariance(tc, force):
     gs = small_batch(3)
-    rp, col, off = tc.pack_csr([to_gpu(g) for g in gs])
-    counts, _ = tc.count_batched(rp, col, off, options=tc.Options(force_strategy=force))
-    want = np.array([oracle.alg4(g).T if g.n else 0 for g in gs], dtype=np.int64)
-    assert np.array_equal(counts.cpu().numpy(), want)
+    b = tc.pack_csr([to_gpu(g) for g in gs])
+    counts, _ = tc.count_batched(b, options=tc.Options(force_strategy=force))
+    assert np.array_equal(counts.cpu().numpy(), want_counts(gs))
 
 
-def test_batch_with_given_levels_and_repeat(tc):
+def test_batch_levels_match_single_graph_levels(tc):
+    # given levels: each graph's own BFS levels, packed; same counts, and the
+    # batch's own BFS gives the same levels count as the largest graph's
     gs = small_batch(4)
-    rp, col, off = tc.pack_csr([to_gpu(g) for g in gs])
-    lev, _ = tc.bfs_levels(rp, col)
-    a, _ = tc.count_batched(rp, col, off, levels=lev)
-    b, _ = tc.count_batched(rp, col, off)
-    assert torch.equal(a, b)
+    b = tc.pack_csr([to_gpu(g) for g in gs])
+    levs = []
+    deepest = 1
+    for g in gs:
+        if g.n == 0:
+            continue
+        rp, col = to_gpu(g)
+        lev, nl = tc.bfs_levels(rp, col)
+        olev, _ = oracle.bfs_levels(g)
+        assert np.array_equal(lev.cpu().numpy(), olev)
+        levs.append(lev)
+        deepest = max(deepest, nl)
+    packed = torch.cat(levs)
+    a, ra = tc.count_batched(b, levels=packed, options=tc.Options(validate=True))
+    c, rc = tc.count_batched(b)
+    assert torch.equal(a, c)
+    assert np.array_equal(a.cpu().numpy(), want_counts(gs))
+    assert rc.levels == deepest and (ra.T0, ra.T1) == (rc.T0, rc.T1)
 
 
 def test_batch_all_empty_and_single(tc):
-    rp, col, off = tc.pack_csr([to_gpu(csr_from_edges(0, [])), to_gpu(csr_from_edges(3, []))])
-    counts, res = tc.count_batched(rp, col, off)
+    b = tc.pack_csr([to_gpu(csr_from_edges(0, [])), to_gpu(csr_from_edges(3, []))])
+    counts, res = tc.count_batched(b)
     assert counts.cpu().tolist() == [0, 0] and res.T == 0
-    g = complete(9)
-    rp, col, off = tc.pack_csr([to_gpu(g)])
-    counts, res = tc.count_batched(rp, col, off)
+    b = tc.pack_csr([to_gpu(complete(9))])
+    counts, res = tc.count_batched(b)
     assert counts.cpu().tolist() == [84] and res.T == 84
 
 
-def test_batch_validate_rejects_cross_edges(tc):
-    g = complete(10)
-    rp, col = to_gpu(g)
+def test_batch_validate_rejects_ids_outside_their_graph(tc):
+    # a local id beyond its graph's vertices: reported with validation, and
+    # clamped into the graph without it (no access outside the buffers)
+    b = tc.pack_csr([to_gpu(complete(5)), to_gpu(complete(4))])
+    col = b.col.clone()
+    col[3] = 7
+    bad = tc.Batch(b.row_ptr, col, b.vtx_off, b.edge_off)
     with pytest.raises(tc.TCError) as e:
-        tc.count_batched(rp, col, np.array([0, 5, 10]), options=tc.Options(validate=True))
+        tc.count_batched(bad, options=tc.Options(validate=True))
     assert e.value.code == -8
+    counts, _ = tc.count_batched(bad)
+    assert counts.numel() == 2
+    rp = b.row_ptr.clone()
+    rp[1] = 9   # row pointers of graph 0 no longer ascending
+    with pytest.raises(tc.TCError) as e:
+        tc.count_batched(tc.Batch(rp, b.col, b.vtx_off, b.edge_off), options=tc.Options(validate=True))
+    assert e.value.code == -8
+
+
+@pytest.mark.parametrize("cap", [1, 500, 4000])
+def test_batch_in_groups(tc, cap):
+    # groups of at most `cap` vertices and entries (a larger graph alone in
+    # its group) give the same counts as one group
+    gs = small_batch(5)
+    b = tc.pack_csr([to_gpu(g) for g in gs])
+    counts, res = tc.count_batched(b, options=tc.Options(batch_group_entries=cap))
+    want = want_counts(gs)
+    assert np.array_equal(counts.cpu().numpy(), want)
+    assert res.T == int(want.sum())
+
+
+def test_batch_from_union(tc):
+    gs = small_batch(6)
+    sizes = [g.n for g in gs]
+    voff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    src = np.concatenate([np.repeat(np.arange(g.n), np.diff(g.row_ptr)) + voff[i] for i, g in enumerate(gs)])
+    dst = np.concatenate([g.col.astype(np.int64) + voff[i] for i, g in enumerate(gs)])
+    rp, col = tc.build_csr(int(voff[-1]), dev(src), dev(dst))
+    b = tc.Batch.from_union(rp, col, voff)
+    ref = tc.pack_csr([to_gpu(g) for g in gs])
+    assert torch.equal(b.row_ptr, ref.row_ptr) and torch.equal(b.col, ref.col)
+    assert np.array_equal(b.edge_off, ref.edge_off)
+
+
+def test_batch_plan_replays(tc):
+    # the captured pipeline replayed three times, eager work (another count,
+    # a device copy and a synchronisation) between the replays; every replay
+    # equals the oracle's counts; a second plan over new buffer contents
+    gs = small_batch(7)
+    b = tc.pack_csr([to_gpu(g) for g in gs])
+    want = want_counts(gs)
+    plan = tc.BatchPlan(b, tc.Options(batch_group_entries=3000))
+    other = small_batch(8)
+    ob = tc.pack_csr([to_gpu(g) for g in other])
+    for i in range(3):
+        got = plan.launch().clone()
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want), i
+        oc, _ = tc.count_batched(ob)
+        assert np.array_equal(oc.cpu().numpy(), want_counts(other))
+        junk = torch.arange(1 << 20, device="cuda", dtype=torch.int32) * 3
+        torch.cuda.synchronize()
+        del junk
+    plan.close()
 
 
 # ---------------------------------------------------------------- full batch
 
-def _member(mem):
-    n, s, d = graphgen.batch_member_tuples(mem)
-    return n, s, d
+def _golden():
+    out = []
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                i, kind, n, m, T = line.split()
+                out.append((kind, int(n), int(m), int(T)))
+    return out
 
 
 @pytest.fixture(scope="module")
-def full_batch():
+def full_batch(tc):
     t0 = time.time()
     rec = graphgen.batch_recipe(4096, seed=0)
     with cf.ThreadPoolExecutor(16) as ex:
-        parts = list(ex.map(_member, rec))
+        parts = list(ex.map(graphgen.batch_member_tuples, rec))
     sizes = np.array([p[0] for p in parts], dtype=np.int64)
-    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    src = np.concatenate([p[1] + np.int32(off[i]) for i, p in enumerate(parts)])
-    dst = np.concatenate([p[2] + np.int32(off[i]) for i, p in enumerate(parts)])
-    print(f"\nbatch: {len(rec)} graphs, {int(off[-1])} vertices, {len(src)} tuples, "
-          f"generated in {time.time() - t0:.1f} s", flush=True)
-    return rec, parts, off, src, dst
+    voff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    src = torch.from_numpy(np.concatenate([p[1] + np.int32(voff[i]) for i, p in enumerate(parts)])).cuda()
+    dst = torch.from_numpy(np.concatenate([p[2] + np.int32(voff[i]) for i, p in enumerate(parts)])).cuda()
+    del parts
+    rp, col = tc.build_csr(int(voff[-1]), src, dst)
+    del src, dst
+    b = tc.Batch.from_union(rp, col, voff)
+    del rp, col
+    print(f"\nbatch: {len(rec)} graphs, {int(voff[-1])} vertices, {b.col.numel() // 2} edges, "
+          f"ready in {time.time() - t0:.1f} s", flush=True)
+    yield rec, b
+    del b
+    torch.cuda.empty_cache()
 
 
-def test_full_batch_sampled(tc, full_batch):
-    rec, parts, off, src, dst = full_batch
-    n = int(off[-1])
-    rp, col = tc.build_csr(n, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
+def test_full_batch_every_graph(tc, full_batch):
+    rec, b = full_batch
+    gold = _golden()
+    assert len(gold) == 4096
+    assert [k for k, *_ in gold] == [r.kind for r in rec]
+    assert np.array_equal(np.diff(b.vtx_off), [n for _, n, _, _ in gold])
+    assert np.array_equal(np.diff(b.edge_off), [2 * m for _, _, m, _ in gold])
+    want = np.array([T for *_, T in gold], dtype=np.int64)
     t0 = time.time()
-    counts, res = tc.count_batched(rp, col, off)
-    torch.cuda.synchronize()
-    print(f"batched count: m={col.numel() // 2}, T={res.T}, {time.time() - t0:.3f} s", flush=True)
-    counts = counts.cpu().numpy()
-    assert int(counts.sum()) == res.T
-    # every 16th graph plus the eight largest of each half, each against the oracle on its own
-    sizes = np.diff(off)
-    pick = set(range(0, 4096, 16))
-    pick |= set(np.argsort(-sizes[:2048])[:8].tolist()) | set((2048 + np.argsort(-sizes[2048:])[:8]).tolist())
+    counts, res = tc.count_batched(b)
+    print(f"eager batched count: T={res.T}, {time.time() - t0:.3f} s", flush=True)
+    got = counts.cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert len(bad) == 0, f"{len(bad)} of 4096 graphs differ, first {bad[:5]}"
+    assert res.T == int(want.sum())
 
-    def want(i):
-        nn, s, d = parts[i]
-        return i, oracle.alg4(oracle.build_csr(nn, s, d)).T
+
+def test_full_batch_levels_sampled(tc, full_batch):
+    # the batched BFS levels of every 64th graph and the largest ones,
+    # element by element against the oracle's serial BFS
+    rec, b = full_batch
+    lev, _ = tc.bfs_levels_batched(b)
+    lev = lev.cpu().numpy()
+    sizes = np.diff(b.edge_off)
+    pick = sorted(set(range(0, 4096, 64)) | set(np.argsort(-sizes)[:8].tolist()))
+
+    def check(i):
+        n, s, d = graphgen.batch_member_tuples(rec[i])
+        g = oracle.build_csr(n, s, d)
+        olev, _ = oracle.bfs_levels(g)
+        return i, bool(np.array_equal(lev[b.vtx_off[i]:b.vtx_off[i + 1]], olev))
 
     with cf.ThreadPoolExecutor(16) as ex:
-        for i, t in ex.map(want, sorted(pick)):
-            assert counts[i] == t, (i, rec[i], counts[i], t)
+        for i, ok in ex.map(check, pick):
+            assert ok, (i, rec[i])
+
+
+def test_full_batch_plan_every_graph(tc, full_batch):
+    rec, b = full_batch
+    want = np.array([T for *_, T in _golden()], dtype=np.int64)
+    t0 = time.time()
+    plan = tc.BatchPlan(b)
+    t1 = time.time()
+    for i in range(2):
+        counts = plan.launch().clone()
+        torch.cuda.synchronize()
+        got = counts.cpu().numpy()
+        assert np.array_equal(got, want), (i, np.nonzero(got != want)[0][:5])
+    print(f"plan: capture {t1 - t0:.3f} s, replays equal the oracle", flush=True)
+    plan.close()

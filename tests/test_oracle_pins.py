@@ -466,34 +466,36 @@ def test_relabel_degree_star_and_ties():
     _check_relabel(csr_from_edges(4, []))
 
 
-# ---------------------------------------------------------------- row-sampled edge iterator
+# ---------------------------------------------------------------- edge-sampled edge iterator
 
 @pytest.mark.parametrize("n", [4, 7, 12])
-def test_emd_rows_complete_graph(n):
-    # in K_n the triangles whose smallest vertex is u number C(n - 1 - u, 2)
+def test_emd_entries_complete_graph(n):
+    # in K_n the entry (u, v), u < v, closes a triangle with every w > v
     g = complete(n)
-    for u in range(n):
-        assert oracle.count_emd_rows(g, [u]) == choose(n - 1 - u, 2)
-    assert oracle.count_emd_rows(g, np.arange(n), threads=3) == choose(n, 3)
+    for e in range(g.nnz):
+        u = int(np.searchsorted(g.row_ptr, e, side="right")) - 1
+        v = int(g.col[e])
+        assert oracle.count_emd_entries(g, [e]) == (n - 1 - v if v > u else 0)
+    assert oracle.count_emd_entries(g, np.arange(g.nnz), threads=3) == choose(n, 3)
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
-def test_emd_rows_partition_sums_to_brute_force(seed):
+def test_emd_entries_partition_sums_to_brute_force(seed):
     g = gnp(30, 0.3, seed)
     want = brute_force(g)
     rng = np.random.default_rng(seed)
-    part = rng.integers(0, 3, g.n)
-    parts = [oracle.count_emd_rows(g, np.nonzero(part == k)[0], threads=k + 1) for k in range(3)]
+    part = rng.integers(0, 3, g.nnz)
+    parts = [oracle.count_emd_entries(g, np.nonzero(part == k)[0], threads=k + 1) for k in range(3)]
     assert sum(parts) == want
-    assert oracle.count_emd_rows(g, [], threads=2) == 0
+    assert oracle.count_emd_entries(g, [], threads=2) == 0
 
 
-def test_emd_rows_threads_agree(kron12):
+def test_emd_entries_threads_agree(kron12):
     g = kron12
-    rows = np.arange(0, g.n, 7)
-    one = oracle.count_emd_rows(g, rows, threads=1)
-    assert oracle.count_emd_rows(g, rows, threads=4) == one
-    assert oracle.count_emd_rows(g, np.arange(g.n), threads=4) == oracle.count_emd(g)
+    es = np.arange(0, g.nnz, 7)
+    one = oracle.count_emd_entries(g, es, threads=1)
+    assert oracle.count_emd_entries(g, es, threads=4) == one
+    assert oracle.count_emd_entries(g, np.arange(g.nnz), threads=4) == oracle.count_emd(g)
 
 
 @pytest.mark.parametrize("seed", range(6))
