@@ -18,7 +18,9 @@ Beside it (in `config`):
     measurement on those training graphs;
   * secondary -- Chung-Lu 2^22 (power law, gamma 2.1, mean degree 32) under
     both schedules; Kronecker scale 20 with the forward-hashed, per-vertex,
-    per-edge and Algorithm 3 / degree-relabel legs; the 4096-graph batch.
+    per-edge and Algorithm 3 / degree-relabel legs; the 4096-graph batch
+    (tiles tuned on the union; the eager batched call and the replays of
+    its captured plan, all 4096 counts checked against the oracle's).
 
 `roofline` describes the intersection kernel (k_isect) on the headline
 graph: its algorithmic bytes B_alg per launch over its mean duration, taken
@@ -53,6 +55,9 @@ METRIC = "input edges/s + % HBM peak, plain vs learned-scheduled, counts bit-exa
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_isect_kronecker_s24_traffic.txt")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "large_counts.txt")
+BATCH_GOLDEN = os.path.join(ROOT, "tests", "golden", "batch_counts.txt")
+BATCH_TUNE_SPACE = {"chunk_work": [16384, 32768, 65536], "wave_slots": [1024, 2048], "wg_slots": [16384, 32768],
+                    "grid_blocks": [0]}
 KERNEL_SOURCES = ("paper_2309_09064_amd/csrc/tc_count.hip", "paper_2309_09064_amd/csrc/tc_internal.hpp")
 COPY_PROBE_BYTES = 1 << 30
 CPU_SLICE = 1024          # a CPU-baseline slice is every 1024th CSR entry
@@ -434,7 +439,72 @@ def secondary_legs(tc, torch, args, tables):
     log(f"kronecker 20: {st * 1e3:.3f} ms/step; forward-hashed {fs * 1e3:.3f}; cover edge {ce_s * 1e3:.3f}")
     del rp, col, rp2, col2, zero
     torch.cuda.empty_cache()
+    out["batch4096"] = batch_leg(tc, torch, args)
     return out
+
+
+def batch_golden():
+    counts = []
+    with open(BATCH_GOLDEN) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                counts.append(int(line.split()[4]))
+    return np.array(counts, dtype=np.int64)
+
+
+def batch_leg(tc, torch, args):
+    """The 4096-graph batch (half Erdos-Renyi, half Kronecker scale 8-16):
+    tiles tuned on the disjoint union, then the eager batched call and the
+    captured plan's replays, every count checked against the oracle's."""
+    import concurrent.futures as cf
+    import graphgen
+    from paper_2309_09064_amd import autotune
+    t0 = time.perf_counter()
+    rec = graphgen.batch_recipe(4096, seed=0)
+    with cf.ThreadPoolExecutor(16) as ex:
+        parts = list(ex.map(graphgen.batch_member_tuples, rec))
+    voff = np.concatenate([[0], np.cumsum([p[0] for p in parts])]).astype(np.int64)
+    src = torch.from_numpy(np.concatenate([p[1] + np.int32(voff[i]) for i, p in enumerate(parts)])).cuda()
+    dst = torch.from_numpy(np.concatenate([p[2] + np.int32(voff[i]) for i, p in enumerate(parts)])).cuda()
+    del parts
+    rp, col = tc.build_csr(int(voff[-1]), src, dst)
+    del src, dst
+    batch = tc.Batch.from_union(rp, col, voff)
+    m = col.numel() // 2
+    t_ready = time.perf_counter() - t0
+    opts, rep = autotune.tune(rp, col, space=BATCH_TUNE_SPACE, repeats=1)
+    opts.timing = False
+    del rp, col
+    torch.cuda.empty_cache()
+    want = batch_golden()
+    ws = tc.workspace(tc.batch_workspace_bytes(batch, opts))
+    e_s, (counts, res) = time_calls(lambda: tc.count_batched(batch, options=opts, ws=ws), args.steps, args.warmup)
+    eager_exact = bool(np.array_equal(counts.cpu().numpy(), want))
+    del ws
+    torch.cuda.empty_cache()
+    t1 = time.perf_counter()
+    plan = tc.BatchPlan(batch, opts)
+    capture_s = time.perf_counter() - t1
+    for _ in range(max(args.warmup, 1)):
+        plan.launch()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        got = plan.launch()
+    torch.cuda.synchronize()
+    r_s = (time.perf_counter() - t2) / args.steps
+    replay_exact = bool(np.array_equal(got.cpu().numpy(), want))
+    plan.close()
+    log(f"batch: {len(rec)} graphs, m={m}: eager {e_s * 1e3:.2f} ms, captured replay {r_s * 1e3:.2f} ms "
+        f"(capture {capture_s:.3f} s); counts exact {eager_exact and replay_exact}")
+    return {"workload": "4096 graphs: 2048 Erdos-Renyi G(n, p), n log-uniform in [64, 65536], mean degree "
+                        "U[8, 64]; 2048 Kronecker, scale U{8..16}, edgefactor 16; member i seeded 1000 + i",
+            "graphs": len(rec), "vertices": int(voff[-1]), "m": m, "triangles": int(want.sum()),
+            "counts_bit_exact": eager_exact and replay_exact, "graphs_checked": int(len(want)),
+            "tuned": {k: getattr(opts, k) for k in autotune.TUNED_FIELDS}, "tune_report": rep,
+            "eager": {"value": m / e_s, "ms_per_step": e_s * 1e3},
+            "captured_replay": {"value": m / r_s, "ms_per_step": r_s * 1e3, "capture_s": capture_s},
+            "prepare_s": t_ready}
 
 
 if __name__ == "__main__":

@@ -125,7 +125,7 @@ typedef struct tc_options {
     int32_t merge_max_owner;  /* heuristic: owner lists up to this size (at
                                  most 31) take the lane merge (one lane per
                                  item of at most 32 partners); 0 = default
-                                 7, -1 = never                               */
+                                 15, -1 = never                              */
     const int32_t *sched_table; /* device int32[TC_NUM_BUCKETS] strategies,
                                  read when schedule == TC_SCHED_TABLE (NULL
                                  otherwise).  A hash strategy in a bucket
@@ -135,6 +135,10 @@ typedef struct tc_options {
                                  CSR entries one internal group of graphs
                                  may hold (a larger graph gets a group of
                                  its own); 0 = 2^31 - 1024, the int32 limit  */
+    int32_t wg_slice_max;     /* workgroup hash: longest owner list held whole
+                                 in one table (power of 2, 64..wg_slots/2);
+                                 longer lists are cut into value-range slices
+                                 of at most this many; 0 = wg_slots / 4      */
 } tc_options;
 
 /* Per-call statistics (host struct, all optional). */

@@ -52,6 +52,7 @@ class tc_options(ctypes.Structure):
         ("merge_max_owner", ctypes.c_int32),
         ("sched_table", ctypes.c_void_p),
         ("batch_group_entries", ctypes.c_int64),
+        ("wg_slice_max", ctypes.c_int32),
     ]
 
 

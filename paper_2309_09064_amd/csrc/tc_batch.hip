@@ -429,6 +429,52 @@ int enqueue_levels(const BatchShape &sh, const BatchLayout &L, const int32_t *d_
     return TC_OK;
 }
 
+__global__ void k_single_graph(int32_t n, int64_t *voff, int32_t *order) {
+    if (threadIdx.x == 0) {
+        voff[0] = 0;
+        voff[1] = n;
+        order[0] = 0;
+    }
+}
+
+}  // namespace
+
+// Levels of one graph by the one-workgroup BFS kernel: no host read, no
+// device-wide barrier (the no-allocation count computes its levels so).
+size_t bfs_single_ws_bytes(int32_t n) {
+    Carver c(nullptr, 0);
+    const int64_t nv = n > 0 ? n : 1;
+    c.take<int64_t>(2);
+    c.take<int32_t>(1);
+    c.take<int32_t>(nv);
+    c.take<int32_t>(nv);
+    c.take<int32_t>(nv + 2);
+    c.take<int32_t>(64);
+    return c.used();
+}
+
+int bfs_single_run(int32_t n, const int32_t *rp, const int32_t *col, int32_t *lev, void *ws, size_t ws_bytes,
+                   hipStream_t s) {
+    if (n <= 0) return TC_OK;
+    Carver c(ws, ws_bytes);
+    const int64_t nv = n;
+    int64_t *voff = c.take<int64_t>(2);
+    int32_t *order = c.take<int32_t>(1);
+    int32_t *fa = c.take<int32_t>(nv);
+    int32_t *fb = c.take<int32_t>(nv);
+    int32_t *pre = c.take<int32_t>(nv + 2);
+    int32_t *flag = c.take<int32_t>(64);
+    if (!c.fits()) return TC_ERR_WORKSPACE;
+    hipLaunchKernelGGL(k_single_graph, dim3(1), dim3(64), 0, s, n, voff, order);
+    TC_TRY(fill_u32(flag, 0, 64, s));
+    hipLaunchKernelGGL(k_bfs_batch, dim3(1), dim3(kBfsThreads), 0, s, 1, order, 0, (int64_t)0, voff, rp, col, lev, fa,
+                       fb, pre, flag);
+    TC_HIP_TRY(hipGetLastError());
+    return TC_OK;
+}
+
+namespace {
+
 int batch_cfg(const tc_options *opt, CountCfg *cfg, int *flags) {
     TC_TRY(options_cfg(opt, cfg, flags));
     if (cfg->schedule == TC_SCHED_TABLE && !cfg->table) return TC_ERR_ARG;

@@ -164,6 +164,10 @@ int make_cfg(const tc_options *opt, CountCfg *cfg, int *flags) {
         c.wave_max_owner = opt->wave_max_owner;
         if (opt->merge_max_owner < -1 || opt->merge_max_owner > 31) return TC_ERR_ARG;
         c.merge_max_owner = opt->merge_max_owner;
+        if (opt->wg_slice_max && (!is_pow2(opt->wg_slice_max) || opt->wg_slice_max < 64 ||
+                                  opt->wg_slice_max > c.wg_slots / 2))
+            return TC_ERR_ARG;
+        c.wg_slice_max = opt->wg_slice_max;
         if (opt->flags & ~(TC_VALIDATE | TC_TIMING)) return TC_ERR_ARG;
         *flags = opt->flags;
     }

@@ -38,10 +38,11 @@ constexpr int kMinPartnersPerWgItem = 4096; // workgroup items
 constexpr int kWgItemWaves = 4 * kIsectWaves; // a workgroup item holds this many wavefront items of work
 constexpr int32_t kEmpty = -1;
 constexpr int32_t kNoKey = -2;   // window padding: never stored, never equal to kEmpty
-// A workgroup table (2^wg_log2 slots) holds at most 2^(wg_log2 - kWgCapShift)
-// owner elements (load 1/8: linear probing stays short); longer owner lists
-// are cut into value-range slices.
-constexpr int kWgCapShift = 3;
+// By default a workgroup table (2^wg_log2 slots) holds at most 2^(wg_log2 -
+// kWgCapShift) owner elements (load 1/4: fewer slices than at 1/8, still
+// short probe sequences; measured faster on Kronecker scale 22 and Chung-Lu
+// 2^20); longer owner lists are cut into value-range slices.
+constexpr int kWgCapShift = 2;
 // Claim counters of the intersection pass: kClaimStreams streams (one per
 // XCD), each with a wavefront-item and a lane-group counter in its own
 // 128-byte line after the first kQueueInts ints of the queue block.
@@ -134,19 +135,23 @@ __device__ __forceinline__ int32_t owner_slices(int32_t sx, int cap_log2) {
 // ---------------------------------------------------------------- ownership
 
 // Per owner and kind: number of owned partners and their total list length.
+// Per c0 entry (x, y) it also writes one ownership byte (bit k: x owns the
+// edge for kind k): the intersection pass reads it coalesced and gathers a
+// partner's record only where the edge is owned, half the positions.
 __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__restrict__ e0x2p,
                                                    const int32_t *__restrict__ rp0,
                                                    const int32_t *__restrict__ c0, const int32_t *__restrict__ up0,
                                                    const int32_t *__restrict__ rp1, const int4 *__restrict__ vrec,
-                                                   int32_t *__restrict__ cnt, unsigned long long *__restrict__ work) {
-    __shared__ int64_t rows[2];
+                                                   int32_t *__restrict__ cnt, unsigned long long *__restrict__ work,
+                                                   uint8_t *__restrict__ own,
+                                                   const int32_t *__restrict__ tlo, const int32_t *__restrict__ thi) {
     __shared__ int32_t acc_n[2][kOwnRowsMax];
     __shared__ unsigned long long acc_w[2][kOwnRowsMax];
     const int64_t e0x2 = *e0x2p;
     constexpr int64_t kTile = (int64_t)kThreads * kRun;
+    static_assert(kTile == kTileEntries, "a tile of this pass is a tile of the tile table");
     for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < e0x2; t0 += (int64_t)gridDim.x * kTile) {
-        tile_rows(rp0, n, t0, t0 + kTile < e0x2 ? t0 + kTile : e0x2, rows);
-        const int64_t r_lo = rows[0], r_hi = rows[1];
+        const int64_t r_lo = tlo[t0 / kTile], r_hi = thi[t0 / kTile];
         const int64_t nr = r_hi - r_lo + 1;
         const bool local = nr <= kOwnRowsMax;   // count in LDS, flush once per row
         if (local)
@@ -178,14 +183,12 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
             // the run's partners and their list sizes, issued before the
             // row walk (two memory latencies per thread, not per entry)
             int32_t y[kRun];
-            int2 sy[kRun];
+            int4 ry[kRun];
+            uint8_t ob[kRun] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
             for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? c0[e0 + k] : 0;
 #pragma unroll
-            for (int k = 0; k < kRun; ++k) {
-                const int4 ry = e0 + k < e1 ? vrec[y[k]] : make_int4(0, 0, 0, 0);
-                sy[k] = make_int2(ry.y, ry.w);
-            }
+            for (int k = 0; k < kRun; ++k) ry[k] = e0 + k < e1 ? vrec[y[k]] : make_int4(0, 0, 0, 0);
 #pragma unroll
             for (int k = 0; k < kRun; ++k) {
                 const int64_t e = e0 + k;
@@ -197,10 +200,21 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
                     s0x = up0[x];
                     s1x = rp1[x + 1] - rp1[x];
                 }
-                if (owns(s0x, sy[k].x, (int32_t)x, y[k])) { ++n0; w0 += (unsigned)sy[k].x; }
-                if (owns(s1x, sy[k].y, (int32_t)x, y[k])) { ++n1; w1 += (unsigned)sy[k].y; }
+                const bool o0 = owns(s0x, ry[k].y, (int32_t)x, y[k]);
+                const bool o1 = owns(s1x, ry[k].w, (int32_t)x, y[k]);
+                if (o0) { ++n0; w0 += (unsigned)ry[k].y; }
+                if (o1) { ++n1; w1 += (unsigned)ry[k].w; }
+                ob[k] = (uint8_t)((o0 ? 1 : 0) | (o1 ? 2 : 0));
             }
             flush();
+            if (e1 - e0 == kRun) {   // e0 is a multiple of 8: one 8-byte store
+                uint64_t word = 0;
+#pragma unroll
+                for (int k = 0; k < kRun; ++k) word |= (uint64_t)ob[k] << (8 * k);
+                *reinterpret_cast<uint64_t *>(own + e0) = word;
+            } else {
+                for (int64_t e = e0; e < e1; ++e) own[e] = ob[e - e0];
+            }
         }
         __syncthreads();
         if (local) {
@@ -600,7 +614,9 @@ __device__ __forceinline__ uint32_t merge_count(const int32_t *a, int32_t la, co
 struct Graph {
     const int32_t *rp0, *c0, *up0, *rp1, *c1;
     const int4 *vrec;   // per vertex {rp0, |N0+|, rp1, |N1|}
+    const uint8_t *own;   // per c0 entry: bit k set when the row's vertex owns the edge for kind k
     const int32_t *pos0, *pos1;   // per-edge counts: input entry of every c0 / c1 entry
+    int wide;           // the list arrays reach 2^30 entries: element byte offsets need 64 bits
 };
 
 // Elements per lane per window step, and the per-wavefront LDS scratch used
@@ -640,91 +656,112 @@ __device__ __forceinline__ bool cover_counts(int32_t lw, int32_t lx, int32_t w, 
 }
 
 // Partner information for the c0 position p of owner x: is the edge owned
-// for this kind, which vertex is the partner, and where is its list.
-__device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t x, int32_t sx, int32_t p, int32_t je,
-                                           int32_t &sy, int32_t &yb, int32_t &y) {
+// for this kind (the ownership pass's byte, read coalesced), which vertex is
+// the partner, and where is its list (one record, gathered only when owned).
+__device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t p, int32_t je, int32_t &sy,
+                                           int32_t &yb, int32_t &y) {
     sy = 0;
     yb = 0;
     y = 0;
     if (p >= je) return false;
     y = g.c0[p];
-    const int4 r = g.vrec[y];   // one 16-byte record for either kind
+    if (!((g.own[p] >> kind) & 1)) return false;
+    const int4 r = g.vrec[y];
     sy = kind == 0 ? r.y : r.w;
     yb = kind == 0 ? r.x : r.z;
-    return owns(sx, sy, x, y);
+    return true;
 }
 
 // Partner lists at least this long stream through stream_long.
 constexpr int32_t kLongList = kWave;
 
-// Streams lists of at least 64 elements as one virtual array, 64 * kPer
-// elements per step like stream_chunk, without its LDS markers: a row of 64
-// consecutive positions then spans at most two lists, so a lane finds its
-// list by one compare against the next list's start.  The cursor (current
-// list, next list) is uniform and lives in scalar registers, read from the
-// owning lanes with readlane.  m: lanes holding a list; len / yb: the list's
+// Element `at` of a list array: with 32-bit byte offsets (arrays below 2^30
+// entries) the load takes the array's scalar base plus one 32-bit offset, so
+// the address costs one instruction; `wide` arrays use 64-bit offsets.
+template <bool kWideIdx>
+__device__ __forceinline__ int32_t list_elem(const int32_t *lists, int32_t at) {
+    if constexpr (kWideIdx)
+        return lists[at];
+    else
+        return *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(lists) + ((uint32_t)at << 2));
+}
+
+// Streams lists of at least 64 elements, a row of 64 consecutive elements of
+// one list at a time (lane l takes element 64 r + l of the list's row r), kPer
+// rows per window, kPer loads in flight per lane.  A row never spans two
+// lists, so its address is the row's scalar base plus the lane (clamped to
+// the list's last element in a partial row, which is then masked before its
+// lookups by a uniform branch).  The lists are taken in lane order of m;
+// the cursor (next row's base, elements left in the list) is uniform and
+// lives in scalar registers.  m: lanes holding a list; len / yb: the list's
 // length (0 off m) and offset in `lists`.
-template <class Count>
-__device__ __forceinline__ uint32_t stream_long(const int32_t *lists, uint64_t m, int32_t len, int32_t yb,
+template <bool kWideIdx, class Count>
+__device__ __forceinline__ uint32_t stream_rows(const int32_t *lists, uint64_t m, int32_t len, int32_t yb,
                                                 Count count) {
     const int l = lane_id();
-    const int32_t incl = wave_incl_scan(len);
-    const int32_t start = incl - len;
-    const int32_t total = __shfl(incl, kWave - 1, kWave);
-    const int32_t offv = yb - start;   // position p of this lane's list is lists[offv + p]
+    // rows of the batch: the loop runs until every row has been probed (a
+    // scalar, so that the loop's branches stay uniform)
+    int32_t left = __builtin_amdgcn_readfirstlane(wave_sum((len + kWave - 1) >> 6));
     uint64_t rest = m;
     const int first = (int)__builtin_ctzll(rest);
     rest &= rest - 1;
-    int32_t c_off = __builtin_amdgcn_readlane(offv, first);
-    int32_t n_start = INT32_MAX, n_off = 0;
-    auto next = [&]() {
-        if (rest) {
-            const int nl = (int)__builtin_ctzll(rest);
-            rest &= rest - 1;
-            n_start = __builtin_amdgcn_readlane(start, nl);
-            n_off = __builtin_amdgcn_readlane(offv, nl);
-        } else {
-            n_start = INT32_MAX;
-            n_off = 0;
-        }
-    };
-    next();
-    constexpr int32_t kStep = kPer * kWave;
-    // rows must be visited in increasing order: the cursor only moves forward.
-    // Positions past the end are clamped into the last list and masked later.
-    // Only a step that reaches past the end clamps positions and masks keys
-    // (a uniform branch): full steps skip four VALU instructions per key.
-    auto gather = [&](int32_t base, int32_t (&v)[kPer]) {
-        const bool whole = base + kStep <= total;
+    int32_t s_off = __builtin_amdgcn_readlane(yb, first);
+    int32_t s_rem = __builtin_amdgcn_readlane(len, first);
+    const int32_t s_safe = s_off;   // rows past the last list re-read the first list's first row
+    // the next row: its base and how many of its lanes hold elements (<= 0:
+    // past the last list); a row that ends a list moves the cursor on
+    auto gather = [&](int32_t (&v)[kPer], int32_t (&lim)[kPer]) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            const int32_t row = base + u * kWave;
-            while (n_start <= row) {
-                c_off = n_off;
-                next();
+            if (s_rem <= 0 && rest) {
+                const int nl = (int)__builtin_ctzll(rest);
+                rest &= rest - 1;
+                s_off = __builtin_amdgcn_readlane(yb, nl);
+                s_rem = __builtin_amdgcn_readlane(len, nl);
             }
-            const int32_t pos = row + l;
-            const int32_t off = pos >= n_start ? n_off : c_off;
-            if (whole) v[u] = lists[off + pos];
-            else v[u] = lists[off + min(pos, total - 1)];
+            lim[u] = s_rem;
+            // lanes past a list's end re-read its last element (a line the
+            // row fetches anyway); rows past the last list re-read the first
+            const int32_t base = s_rem > 0 ? s_off : s_safe;
+            const int32_t last = s_rem > 0 && s_rem < kWave ? s_rem - 1 : kWave - 1;
+            v[u] = list_elem<kWideIdx>(lists, base + min(l, last));
+            s_off += kWave;
+            s_rem -= kWave;
         }
     };
+    // the lanes of a partial or spent row become padding keys (uniform test)
+    auto masked = [&](int32_t (&v)[kPer], const int32_t (&lim)[kPer]) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (lim[u] < kWave) v[u] = l < lim[u] ? v[u] : kNoKey;
+    };
+    // software pipeline, two windows in ping-pong registers: the next
+    // window's loads are issued (unconditionally, past the end at valid
+    // addresses) before this window's lookups, so their latency overlaps the
+    // LDS probes and every wait covers one window's loads
     uint32_t hits = 0;
-    int32_t va[kPer];
-    gather(0, va);
-    for (int32_t base = 0;; base += kStep) {
-        int32_t vb[kPer];
-        gather(base + kStep, vb);
-        if (base + kStep > total) {
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) va[u] = base + u * kWave + l < total ? va[u] : kNoKey;
-        }
+    int32_t va[kPer], la[kPer], vb[kPer], lb[kPer];
+    gather(va, la);
+    for (;;) {
+        gather(vb, lb);
+        masked(va, la);
         hits += count(va);
-        if (base + kStep >= total) break;
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) va[u] = vb[u];
+        left -= kPer;
+        if (left <= 0) break;
+        gather(va, la);
+        masked(vb, lb);
+        hits += count(vb);
+        left -= kPer;
+        if (left <= 0) break;
     }
     return hits;
+}
+
+template <class Count>
+__device__ __forceinline__ uint32_t stream_long(const int32_t *lists, uint64_t m, int32_t len, int32_t yb, bool wide,
+                                                Count count) {
+    if (wide) return stream_rows<true>(lists, m, len, yb, count);
+    return stream_rows<false>(lists, m, len, yb, count);
 }
 
 // Streams the owned partner lists among the 64 c0 positions starting at p0
@@ -749,7 +786,7 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     static_assert(kPer == 8, "a lane reads its window markers as one 64-bit word");
     const int l = lane_id();
     int32_t sy, yb, yid;
-    bool mine = partner_at(g, kind, x, sx, p0 + l, je, sy, yb, yid);
+    bool mine = partner_at(g, kind, p0 + l, je, sy, yb, yid);
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     if (sliced && mine) {
         const int32_t b = lower_idx(lists + yb, sy, lo);
@@ -762,7 +799,7 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     if constexpr (kRec == kRecNone) {   // long lists take the marker-free path
         const bool lng = mine && sy >= kLongList;
         const uint64_t ml = __ballot(lng);
-        if (ml) long_hits = stream_long(lists, ml, lng ? sy : 0, yb, count);
+        if (ml) long_hits = stream_long(lists, ml, lng ? sy : 0, yb, g.wide != 0, count);
         mine = mine && !lng;
     }
     const uint64_t m = __ballot(mine);
@@ -887,7 +924,7 @@ __device__ __forceinline__ uint32_t lane_reg_item(const Graph &g, int kind, int3
     uint32_t hits = 0;
     for (int32_t p = jb; p < je; ++p) {
         int32_t sy, yb, y;
-        if (!partner_at(g, kind, x, sx, p, je, sy, yb, y)) continue;   // owned: sx >= sy >= 1
+        if (!partner_at(g, kind, p, je, sy, yb, y)) continue;   // owned: sx >= sy >= 1
         const int32_t *b = lists + yb;
         int32_t bv[kRegOwner];
 #pragma unroll
@@ -914,7 +951,7 @@ __device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, in
     uint32_t hits = 0;
     for (int32_t p = jb; p < je; ++p) {
         int32_t sy, yb, y;
-        if (!partner_at(g, kind, x, sx, p, je, sy, yb, y)) continue;   // owned: sx >= sy >= 1
+        if (!partner_at(g, kind, p, je, sy, yb, y)) continue;   // owned: sx >= sy >= 1
         const int32_t *b = lists + yb;
         int32_t i = 0, j = 0, ai = a[0], bj = b[0];
         const uint32_t h0 = hits;
@@ -952,7 +989,7 @@ template <int kMode>
 __device__ __forceinline__ uint32_t merge_chunk(const Graph &g, int kind, int32_t x, int32_t sx, const int32_t *a,
                                                 int32_t p0, int32_t je, const Sink &sk) {
     int32_t sy, yb, yid;
-    const bool mine = partner_at(g, kind, x, sx, p0 + lane_id(), je, sy, yb, yid);
+    const bool mine = partner_at(g, kind, p0 + lane_id(), je, sy, yb, yid);
     uint64_t m = __ballot(mine);
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     uint32_t hits = 0;
@@ -1160,6 +1197,7 @@ __device__ __forceinline__ int table_log2(int32_t sx, int max_log2) {
 template <bool kProf, int kMode>
 __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__restrict__ items,
                                                           int32_t *__restrict__ q, int wg_log2, int wave_log2,
+                                                          int wg_cap_log2,
                                                           int table_ints, unsigned long long *__restrict__ tri,
                                                           unsigned long long *__restrict__ prof, Sink sk) {
     extern __shared__ int32_t lds[];
@@ -1212,7 +1250,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
         const int32_t sx = list_size(kind, g.up0, g.rp1, x);
         // the owner slice of this item: positions [a_lo, a_hi), values [lo, hi)
-        const int32_t nsl = owner_slices(sx, wg_log2 - kWgCapShift);
+        const int32_t nsl = owner_slices(sx, wg_cap_log2);
         const int32_t si = (int32_t)((uint32_t)item.code >> kSliceShift);
         const int32_t a_lo = (int32_t)((int64_t)sx * si / nsl), a_hi = (int32_t)((int64_t)sx * (si + 1) / nsl);
         const bool sliced = nsl > 1;
@@ -1358,6 +1396,17 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
     }
 }
 
+// {T, T0, T1, |E0|} from the pass's sums, into a caller's device buffer.
+__global__ void k_result(const unsigned long long *__restrict__ stats, const int64_t *__restrict__ e0x2,
+                         unsigned long long *__restrict__ out) {
+    if (threadIdx.x == 0) {
+        out[0] = stats[8] + stats[9];
+        out[1] = stats[8];
+        out[2] = stats[9];
+        out[3] = (unsigned long long)(*e0x2 / 2);
+    }
+}
+
 // Per-edge counts land at either of an edge's two input entries; this pass
 // adds the two and writes the sum to both.  The entry (u, v) with u < v finds
 // its reverse (v, u) by binary search in row v, so each edge is handled by
@@ -1410,6 +1459,8 @@ unsigned grid_for(int64_t work, int threads, int64_t cap) {
 }
 
 struct CountLayout {
+    uint8_t *own;   // per c0 entry ownership bits (k_own)
+    int32_t *tlo, *thi;   // tile table of the N0 lists (k_own)
     int32_t *cnt;
     unsigned long long *work;
     int32_t *bucket_items, *bucket_off, *bucket_cur, *q;
@@ -1441,6 +1492,9 @@ int64_t item_capacity(int32_t n, int64_t nnz) {
 CountLayout carve_count(Carver &c, int32_t n, int64_t nnz) {
     CountLayout L;
     const int64_t nn = n > 0 ? n : 1;
+    L.own = c.take<uint8_t>(nnz > 0 ? nnz : 1);
+    L.tlo = c.take<int32_t>(tiles_of(nnz));
+    L.thi = c.take<int32_t>(tiles_of(nnz));
     L.cnt = c.take<int32_t>(2 * nn);
     L.work = c.take<unsigned long long>(2 * nn);
     L.bucket_items = c.take<int32_t>(kBuckets + 1);
@@ -1484,8 +1538,8 @@ static SchedCfg sched_cfg(int32_t n, int64_t nnz, const CountCfg &cfg) {
     sc.table = cfg.table;
     sc.force = cfg.force;
     sc.wave_ob_max = wave_log2 - 2;
-    sc.wg_ob_max = wg_log2 - kWgCapShift - 1;
-    sc.wg_cap_log2 = wg_log2 - kWgCapShift;
+    sc.wg_cap_log2 = cfg.wg_slice_max > 0 ? ilog2_host(cfg.wg_slice_max) : wg_log2 - kWgCapShift;
+    sc.wg_ob_max = sc.wg_cap_log2 - 1;
     {   // slicing needs at most 2^18 slices per owner list (list length <= min(n - 1, nnz))
         const int64_t longest = (int64_t)n - 1 < nnz ? (int64_t)n - 1 : nnz;
         sc.wg_slicing = longest <= ((int64_t)1 << (kMaxSlicesLog2 + sc.wg_cap_log2)) ? 1 : 0;
@@ -1493,7 +1547,7 @@ static SchedCfg sched_cfg(int32_t n, int64_t nnz, const CountCfg &cfg) {
     // heuristic default: wavefront tables up to a quarter full (linear
     // probing lengthens quickly above that; the feasibility limit is half)
     sc.heur_wave_ob = cfg.wave_max_owner > 0 ? ilog2_host(cfg.wave_max_owner) : wave_log2 - 3;
-    sc.heur_merge_ob = cfg.merge_max_owner < 0 ? -1 : ilog2_host(cfg.merge_max_owner > 0 ? cfg.merge_max_owner : 7);
+    sc.heur_merge_ob = cfg.merge_max_owner < 0 ? -1 : ilog2_host(cfg.merge_max_owner > 0 ? cfg.merge_max_owner : 15);
     if (sc.heur_merge_ob > kLaneMergeOb) sc.heur_merge_ob = kLaneMergeOb;
     sc.chunk_work = cfg.chunk_work > 0 ? cfg.chunk_work : default_chunk_work(nnz);
     return sc;
@@ -1630,8 +1684,9 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     if (cfg.sup && nnz > 0) TC_TRY(fill_u32(cfg.sup, 0, nnz, s));
     const unsigned gp = (unsigned)di.cus * 8;
     if (n > 0) {
+        TC_TRY(tile_table_run(n, pb.rp0, L.tlo, L.thi, s));
         hipLaunchKernelGGL(k_own, dim3(gp), dim3(kThreads), 0, s, n, pb.e0x2, pb.rp0, pb.c0, pb.up0, pb.rp1, pb.vrec, L.cnt,
-                           L.work);
+                           L.work, L.own, L.tlo, L.thi);
         TC_HIP_TRY(hipGetLastError());
         const unsigned gu = grid_for(2 * (int64_t)n, kItemThreads * kUnitsPerThread, (int64_t)1 << 30);
         hipLaunchKernelGGL((k_items<0>), dim3(gu), dim3(kItemThreads), 0, s, n, pb.rp0, pb.up0, pb.rp1, L.cnt,
@@ -1646,29 +1701,32 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev.e[1], s));
     if (n > 0) {
         const unsigned gi = cfg.grid_blocks > 0 ? (unsigned)cfg.grid_blocks : (unsigned)(di.cus * per_cu);
-        Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1, pb.vrec, pb.pos0, pb.pos1};
+        // byte offsets of list elements fit 32 bits below 2^30 entries (with
+        // the padding)
+        const int wide = nnz + 2 * kListPad + 1024 >= (int64_t(1) << 30) ? 1 : 0;
+        Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1, pb.vrec, L.own, pb.pos0, pb.pos1, wide};
         const Sink sk{cfg.gid, cfg.batch_counts, cfg.tv, cfg.sup, cfg.cover_lev};
         if (cfg.prof && batch)
             hipLaunchKernelGGL((k_isect<true, kModeBatch>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
-                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof, sk);
+                               L.q, wg_log2, wave_log2, sc.wg_cap_log2, table_ints, L.stats + 8, cfg.prof, sk);
         else if (cfg.prof)
             hipLaunchKernelGGL((k_isect<true, kModePlain>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
-                               L.q, wg_log2, wave_log2, table_ints, L.stats + 8, cfg.prof, sk);
+                               L.q, wg_log2, wave_log2, sc.wg_cap_log2, table_ints, L.stats + 8, cfg.prof, sk);
         else if (vertex)
             hipLaunchKernelGGL((k_isect<false, kModeVertex>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
-                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
+                               L.items, L.q, wg_log2, wave_log2, sc.wg_cap_log2, table_ints, L.stats + 8, nullptr, sk);
         else if (edge)
             hipLaunchKernelGGL((k_isect<false, kModeEdge>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
-                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
+                               L.items, L.q, wg_log2, wave_log2, sc.wg_cap_log2, table_ints, L.stats + 8, nullptr, sk);
         else if (cover)
             hipLaunchKernelGGL((k_isect<false, kModeCover>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
-                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
+                               L.items, L.q, wg_log2, wave_log2, sc.wg_cap_log2, table_ints, L.stats + 8, nullptr, sk);
         else if (batch)
             hipLaunchKernelGGL((k_isect<false, kModeBatch>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
-                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
+                               L.items, L.q, wg_log2, wave_log2, sc.wg_cap_log2, table_ints, L.stats + 8, nullptr, sk);
         else
             hipLaunchKernelGGL((k_isect<false, kModePlain>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g,
-                               L.items, L.q, wg_log2, wave_log2, table_ints, L.stats + 8, nullptr, sk);
+                               L.items, L.q, wg_log2, wave_log2, sc.wg_cap_log2, table_ints, L.stats + 8, nullptr, sk);
         TC_HIP_TRY(hipGetLastError());
     }
     if (cfg.sup && nnz > 0) {
@@ -1676,6 +1734,10 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         TC_HIP_TRY(hipGetLastError());
     }
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev.e[2], s));
+    if (cfg.result) {
+        hipLaunchKernelGGL(k_result, dim3(1), dim3(64), 0, s, L.stats, pb.e0x2, cfg.result);
+        TC_HIP_TRY(hipGetLastError());
+    }
     if (!cfg.sync) return TC_OK;   // results stay on the device (captured pipelines)
     Mailbox mb;
     TC_TRY(mailbox(&mb));

@@ -146,6 +146,18 @@ __device__ __forceinline__ void tile_rows(const P *rp, int64_t nrows, int64_t t0
     __syncthreads();
 }
 
+// ------------------------------------------------------------------ tiles of entries
+
+// Row passes work on tiles of kTileEntries consecutive CSR entries.  The
+// tile table holds, per tile, the rows of its first and last entry, so a
+// block finds its rows with two loads instead of a binary search over the
+// row pointers (at Kronecker scale 24 that search was 24 dependent loads
+// into a 67 MB array per tile).  tlo / thi: int32[tiles(total)].
+constexpr int kTileEntries = 2048;
+__host__ __device__ constexpr int64_t tiles_of(int64_t entries) { return (entries + kTileEntries - 1) / kTileEntries + 1; }
+// Fills the table of the rows 0..n-1 of rp (entries 0..rp[n]), on the device.
+int tile_table_run(int32_t n, const int32_t *rp, int32_t *tlo, int32_t *thi, hipStream_t s);
+
 // ------------------------------------------------------------------ fill and scan
 
 // p[i] = value for the first `count` 32-bit words: a kernel, so that it may
@@ -191,8 +203,7 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
             void *ws, size_t ws_bytes, hipStream_t s);
 
 // Partition into N0 (rank-split rows) and N1
-// Padding (ints) on both sides of the N0/N1 list arrays that the
-// intersection kernel reads in 8-element runs.
+// Padding (ints) on both sides of the N0/N1 list arrays.
 constexpr int kListPad = 16;
 
 struct PartBufs {
@@ -231,6 +242,7 @@ struct CountCfg {
     int chunk_work = 0;   // 0: by input size (default_chunk_work)
     int grid_blocks = 0;
     int wave_max_owner = 0;
+    int wg_slice_max = 0;   // longest owner slice of a workgroup table; 0: wg_slots / 4
     int merge_max_owner = 0;
     const int32_t *table = nullptr;   // device per-bucket strategies (schedule)
     unsigned long long *prof = nullptr;   // device per-(bucket, strategy) profile, or NULL
@@ -242,10 +254,17 @@ struct CountCfg {
     const int32_t *cover_lev = nullptr;   // cover-edge count (over a cover_view_run view): the levels, or NULL
     bool timing = false;
     bool sync = true;   // false: enqueue only; no host read, no synchronisation (out is not filled)
+    unsigned long long *result = nullptr;   // device uint64[4] or NULL: receives {T, T0, T1, |E0|} on the stream
 };
 // The intersection kernel's launch shape for cfg, resolved once per device
 // before any stream capture (count_run then finds it cached).
 int count_prepare(int32_t n, int64_t nnz, const CountCfg &cfg);
+
+// Levels of one graph by a single workgroup (no host read): scratch of
+// bfs_single_ws_bytes(n).
+size_t bfs_single_ws_bytes(int32_t n);
+int bfs_single_run(int32_t n, const int32_t *rp, const int32_t *col, int32_t *lev, void *ws, size_t ws_bytes,
+                   hipStream_t s);
 
 // ------------------------------------------------------------------ shared by the entry points
 

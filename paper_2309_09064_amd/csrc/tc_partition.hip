@@ -25,6 +25,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRun = 8;
 constexpr int kBlockEntries = kThreads * kRun;
+static_assert(kBlockEntries == kTileEntries, "a block is one tile of the tile table");
 constexpr int kWaves = kThreads / kWave;
 constexpr int kTileRowsMax = 1024;   // rows a tile may span and still count in LDS
 
@@ -60,17 +61,17 @@ __device__ __forceinline__ bool rank_above_rec(uint32_t dyp, int32_t y, int32_t 
 __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
                                                          const uint32_t *__restrict__ vld,
+                                                         const int32_t *__restrict__ tlo,
+                                                         const int32_t *__restrict__ thi,
                                                          uint8_t *__restrict__ flags, int32_t *__restrict__ d0,
                                                          int32_t *__restrict__ up0, int32_t *__restrict__ bh,
                                                          int32_t *__restrict__ bu) {
     __shared__ int32_t sh[kWaves], su[kWaves];
-    __shared__ int64_t rows[2];
     __shared__ int32_t acc_h[kTileRowsMax], acc_u[kTileRowsMax];
     __shared__ int32_t s_rp[kTileRowsMax + 1];
     __shared__ uint8_t s_lv[kTileRowsMax];
     const int64_t t0 = (int64_t)blockIdx.x * kBlockEntries;
-    tile_rows(rp, n, t0, t0 + kBlockEntries < nnz ? t0 + kBlockEntries : nnz, rows);
-    const int64_t r_lo = rows[0], r_hi = rows[1];
+    const int64_t r_lo = tlo[blockIdx.x], r_hi = thi[blockIdx.x];
     const int64_t nr = r_hi - r_lo + 1;
     // rows of the tile are counted in LDS; only the two boundary rows can be
     // shared with other tiles.  Their row pointers and levels are staged in
@@ -200,6 +201,8 @@ __global__ void k_part_rp1(int32_t n, const int32_t *__restrict__ rp, const int3
 template <bool kPos>
 __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ col,
+                                                            const int32_t *__restrict__ tlo,
+                                                            const int32_t *__restrict__ thi,
                                                             const uint8_t *__restrict__ flags,
                                                             const int32_t *__restrict__ bh_off,
                                                             const int32_t *__restrict__ bu_off,
@@ -208,14 +211,12 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
                                                             int32_t *__restrict__ c0, int32_t *__restrict__ c1,
                                                             int32_t *__restrict__ pos0, int32_t *__restrict__ pos1) {
     __shared__ int64_t wsum[kWaves];
-    __shared__ int64_t rows[2];
     __shared__ int32_t s_rp[kTileRowsMax + 1], s_ub[kTileRowsMax], s_lb[kTileRowsMax];
     const int64_t t0 = (int64_t)blockIdx.x * kBlockEntries;
-    tile_rows(rp, n, t0, t0 + kBlockEntries < nnz ? t0 + kBlockEntries : nnz, rows);
     // the tile's row pointers and per-row targets staged in LDS (made
     // visible by the scan's barrier below): the walk across row boundaries
     // then waits on LDS, not on dependent global loads
-    const int64_t r_lo = rows[0], r_hi = rows[1];
+    const int64_t r_lo = tlo[blockIdx.x], r_hi = thi[blockIdx.x];
     const int64_t nr = r_hi - r_lo + 1;
     const bool local = nr <= kTileRowsMax;
     if (local) {
@@ -290,6 +291,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
 }
 
 struct PartLayout {
+    int32_t *tlo, *thi;   // tile table of the input CSR
     uint32_t *vld;
     uint8_t *flags;
     int32_t *bh, *bu;
@@ -299,6 +301,8 @@ struct PartLayout {
 PartLayout carve_part(Carver &c, int32_t n, int64_t nnz) {
     PartLayout L;
     const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
+    L.tlo = c.take<int32_t>(tiles_of(nnz));
+    L.thi = c.take<int32_t>(tiles_of(nnz));
     L.vld = c.take<uint32_t>(n > 0 ? n : 1);
     L.flags = c.take<uint8_t>(nnz > 0 ? nnz : 1);
     L.bh = c.take<int32_t>(nblk + 1);
@@ -332,9 +336,10 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
     TC_TRY(fill_u32(pb.up0, 0, n > 0 ? n : 1, s));
     const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
     if (nnz > 0) {
+        TC_TRY(tile_table_run(n, rp, L.tlo, L.thi, s));
         hipLaunchKernelGGL(k_part_vld, dim3(grid_for(n, 256)), dim3(256), 0, s, n, rp, lev, L.vld);
-        hipLaunchKernelGGL(k_part_mark, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, L.vld, L.flags,
-                           pb.d0, pb.up0, L.bh, L.bu);
+        hipLaunchKernelGGL(k_part_mark, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, L.vld, L.tlo,
+                           L.thi, L.flags, pb.d0, pb.up0, L.bh, L.bu);
         TC_HIP_TRY(hipGetLastError());
     }
     TC_TRY(scan_exclusive_i32_to_i32(pb.d0, pb.rp0, n, L.scan, s));
@@ -351,10 +356,10 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
         TC_TRY(scan_exclusive_i32_to_i32(L.bu, L.bu, nblk, L.scan, s));
         if (pb.pos0)
             hipLaunchKernelGGL(k_part_scatter<true>, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col,
-                               L.flags, L.bh, L.bu, pb.rp0, pb.rpu, pb.c0, pb.c1, pb.pos0, pb.pos1);
+                               L.tlo, L.thi, L.flags, L.bh, L.bu, pb.rp0, pb.rpu, pb.c0, pb.c1, pb.pos0, pb.pos1);
         else
             hipLaunchKernelGGL(k_part_scatter<false>, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col,
-                               L.flags, L.bh, L.bu, pb.rp0, pb.rpu, pb.c0, pb.c1, nullptr, nullptr);
+                               L.tlo, L.thi, L.flags, L.bh, L.bu, pb.rp0, pb.rpu, pb.c0, pb.c1, nullptr, nullptr);
         TC_HIP_TRY(hipGetLastError());
     }
     return TC_OK;

@@ -108,6 +108,33 @@ size_t scan_ws_bytes(int64_t n) {
     return total + 256;
 }
 
+// For every non-empty row x: the tiles whose first entry, or whose last
+// entry, lies in the row get x as their first, or last, row.  Every entry
+// belongs to one row, so each tile is written once for each end.
+__global__ void k_tile_table(int32_t n, const int32_t *__restrict__ rp, int32_t *__restrict__ tlo,
+                             int32_t *__restrict__ thi) {
+    const int64_t total = rp[n];
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = rp[x], b = rp[x + 1];
+        if (b <= a) continue;
+        for (int64_t t = a / kTileEntries; t <= (b - 1) / kTileEntries; ++t) {
+            const int64_t first = t * kTileEntries;
+            const int64_t last = ((t + 1) * kTileEntries < total ? (t + 1) * kTileEntries : total) - 1;
+            if (first >= a) tlo[t] = (int32_t)x;
+            if (last < b) thi[t] = (int32_t)x;
+        }
+    }
+}
+
+int tile_table_run(int32_t n, const int32_t *rp, int32_t *tlo, int32_t *thi, hipStream_t s) {
+    if (n <= 0) return TC_OK;
+    int64_t g = ((int64_t)n + kThreads - 1) / kThreads;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_tile_table, dim3((unsigned)g), dim3(kThreads), 0, s, n, rp, tlo, thi);
+    TC_HIP_TRY(hipGetLastError());
+    return TC_OK;
+}
+
 int fill_u32(void *p, uint32_t value, int64_t count, hipStream_t s) {
     if (count <= 0) return TC_OK;
     int64_t g = (count + kThreads - 1) / kThreads;

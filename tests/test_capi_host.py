@@ -79,7 +79,8 @@ def test_bad_sizes_rejected(lib):
 @pytest.mark.parametrize("field,value", [("schedule", 7), ("force_strategy", 9), ("force_strategy", -2),
                                          ("wave_slots", 100), ("wave_slots", 8192), ("wg_slots", 512),
                                          ("wg_slots", 65536), ("chunk_work", -1), ("flags", 4),
-                                         ("merge_max_owner", -2), ("merge_max_owner", 32)])
+                                         ("merge_max_owner", -2), ("merge_max_owner", 32), ("wg_slice_max", 100),
+                                         ("wg_slice_max", 32), ("wg_slice_max", 32768)])
 def test_bad_options_rejected(lib, field, value):
     opt = _capi.tc_options()
     setattr(opt, field, value)
