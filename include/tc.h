@@ -60,7 +60,8 @@ enum tc_err {
     TC_ERR_WORKSPACE = -5,  /* workspace missing, too small or misaligned    */
     TC_ERR_HIP = -6,        /* a HIP runtime call failed                     */
     TC_ERR_NO_DEVICE = -7,  /* no gfx950 device visible                      */
-    TC_ERR_INVALID_CSR = -8 /* TC_VALIDATE found a malformed CSR / levels    */
+    TC_ERR_INVALID_CSR = -8, /* TC_VALIDATE found a malformed CSR / levels   */
+    TC_ERR_TOO_LARGE = -9   /* graph beyond tc_count_noalloc's fixed scratch */
 };
 
 #define TC_COUNT_ERROR UINT64_MAX
@@ -495,6 +496,31 @@ int tc_partition(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t
                  const int32_t *d_levels, int32_t *d_rp0, int32_t *d_c0, int32_t *d_up0,
                  int32_t *d_rp1, int32_t *d_c1, int64_t *h_e0, void *ws, size_t ws_bytes,
                  void *stream);
+
+/* ------------------------------------------------------------ no allocation */
+
+/*
+ * tc_count for callers that cannot allocate: code under graph capture, tight
+ * serving loops, harnesses that forbid allocation.  It allocates nothing and
+ * takes no workspace: its scratch is a fixed device array of 128 MiB that
+ * the library holds on every GPU it runs on until the process ends.  Graphs
+ * whose tc_count workspace (tc_count_ws) exceeds 128 MiB -- a Kronecker
+ * graph of scale 18 fits, one of scale 19 does not -- are rejected with
+ * TC_ERR_TOO_LARGE
+ * before any device work.  Levels, when not given, come from a BFS run by a
+ * single workgroup (the component loop of tc_bfs_levels, with no host read),
+ * so the call is asynchronous and reads nothing back:
+ *   d_result   device uint64[4], output: {T, T0, T1, |E0|} when the stream
+ *              reaches the end of the call's work
+ * Other arguments as for tc_count; TC_TIMING and TC_VALIDATE are rejected
+ * (TC_ERR_ARG: both read results on the host).  Every call on a GPU shares
+ * that GPU's scratch array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be ordered by the caller.  The scratch
+ * keeps the last call's contents; every buffer that must start at zero is
+ * cleared by the call's own kernels.
+ */
+int tc_count_noalloc(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                     const int32_t *d_levels, const tc_options *opt, uint64_t *d_result, void *stream);
 
 #ifdef __cplusplus
 }

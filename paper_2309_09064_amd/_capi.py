@@ -20,6 +20,7 @@ TC_ERR_WORKSPACE = -5
 TC_ERR_HIP = -6
 TC_ERR_NO_DEVICE = -7
 TC_ERR_INVALID_CSR = -8
+TC_ERR_TOO_LARGE = -9
 TC_COUNT_ERROR = (1 << 64) - 1
 
 TC_STRAT_AUTO = -1
@@ -116,6 +117,7 @@ _SIGNATURES = {
     "tc_bfs_levels_batched": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, _P(_i32), _vp, _sz, _vp]),
     "tc_batch_plan_destroy": (ctypes.c_int, [_vp]),
     "tc_schedule_table": (ctypes.c_int, [_i32, _i64, _P(tc_options), _vp, _vp]),
+    "tc_count_noalloc": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _P(tc_options), _vp, _vp]),
     "tc_mlp_param_count": (ctypes.c_int, [_i32, _i32, _P(_i64)]),
     "tc_mlp_init": (ctypes.c_int, [_vp, _i32, _i32, _u64, _vp]),
     "tc_mlp_forward": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp]),

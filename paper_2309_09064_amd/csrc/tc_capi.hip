@@ -256,6 +256,7 @@ const char *tc_strerror(int code) {
     case TC_ERR_HIP: return "HIP runtime error";
     case TC_ERR_NO_DEVICE: return "no gfx950 device";
     case TC_ERR_INVALID_CSR: return "malformed CSR or levels";
+    case TC_ERR_TOO_LARGE: return "graph exceeds the fixed scratch of the no-allocation count";
     default: return "unknown error";
     }
 }
