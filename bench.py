@@ -11,11 +11,12 @@ scale 24 (16.8 M vertices, 268 M generated edges), edgefactor 16, initiator
 schedule.  `value` = m / mean step time.
 
 Beside it (in `config`):
-  * learned_schedule -- the same steps under the cost network's strategy
-    table, the network trained on other graphs (Kronecker scale 22, seeds 2
-    and 3; Chung-Lu 2^20, seed 2) than the ones timed: the network's own
-    table, and the table after its classes of change were checked by
-    measurement on those training graphs;
+  * learned_schedule -- the same steps under the strategy table of the
+    stored cost network (paper_2309_09064_amd/sched_net.json), trained on
+    whole-pass measurements of other graphs (Kronecker scale 22, seeds 2 and
+    3; Chung-Lu 2^20, seed 2) than the ones timed; heuristic and learned
+    steps alternate, so drift hits both alike.  `python bench.py
+    --train-schedule PATH` measures and trains it anew;
   * secondary -- Chung-Lu 2^22 (power law, gamma 2.1, mean degree 32) under
     both schedules; Kronecker scale 20 with the forward-hashed, per-vertex,
     per-edge and Algorithm 3 / degree-relabel legs; the 4096-graph batch
@@ -63,6 +64,9 @@ COPY_PROBE_BYTES = 1 << 30
 CPU_SLICE = 1024          # a CPU-baseline slice is every 1024th CSR entry
 CPU_SECONDS = 15.0        # slices are run until this much time has passed
 TRAIN_GRAPHS = (("kronecker", 22, 2), ("kronecker", 22, 3), ("chunglu", 20, 2))
+SCHED_NET = os.path.join(ROOT, "paper_2309_09064_amd", "sched_net.json")
+SCHED_MARGIN = 1.0        # predicted gain (sgnlog2 ps per element) a change must exceed
+GAIN_NOISE = 0.01         # a learned table counts as faster only beyond this relative gain
 
 
 def kernel_source_hash():
@@ -132,14 +136,25 @@ def golden(name):
 
 
 def copy_probe(torch):
-    """A plain device copy of known size, for scaling the byte counters."""
+    """A plain device pass of known size (read 1 GiB, write 1 GiB) for scaling
+    the byte counters; its kernel (bitwise not over int32) runs nowhere else
+    in this program, so a profile names it unambiguously.  Returns the best
+    of the three passes in GB/s (bytes read + written over the HIP-event
+    time): the bandwidth a streaming kernel reaches on this device."""
     a = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.int32, device="cuda")
     b = torch.empty_like(a)
+    best = 0.0
     for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    print(f"# copy probe: 3 copies of {COPY_PROBE_BYTES} bytes", file=sys.stderr, flush=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.bitwise_not(a, out=b)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2 * COPY_PROBE_BYTES / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    print(f"# copy probe: 3 passes of {COPY_PROBE_BYTES} bytes read + written, best {best:.0f} GB/s",
+          file=sys.stderr, flush=True)
     del a, b
+    return best
 
 
 def log(msg):
@@ -195,9 +210,9 @@ def exact_vs_golden(name, n, m, r):
     return g == (n, m, r.T, r.T0, r.T1, r.e0)
 
 
-def learned_tables(tc, torch, steps):
-    """The cost network trained on the training graphs (none of them timed):
-    (network's table, verified table, info)."""
+def train_schedule(tc, torch, path, steps):
+    """Measure the training graphs bucket by bucket, train the network, and
+    store it with its training ranges and the measurements behind it."""
     from paper_2309_09064_amd import sched
     t0 = time.perf_counter()
     train = []
@@ -205,30 +220,73 @@ def learned_tables(tc, torch, steps):
         _, rp, col = make_graph(tc, torch, kind, size, seed)
         lev, _ = tc.bfs_levels(rp, col)
         train.append((rp, col, lev))
-    proposed, net, ds, losses = sched.learn_schedule(train, steps=steps, lr=1e-2, verify=False)
+    net, ms, losses, hull = sched.learn_marginal(train, steps=steps, log=log)
+    changes = [{"graph": int(g), "kind": int(x[2]), "ob": int(x[0]), "pb": int(x[1]), "strategy": int(c),
+                "delta_ms": round(float(d), 4), "spread_ms": round(float(sp), 4), "share": round(float(w), 4)}
+               for g, x, c, d, sp, w in zip(ms.graph, ms.X, ms.c, ms.delta_ms, ms.spread_ms, ms.w) if d != 0.0]
+    # the network's table (one table: it depends on the options only), then
+    # each class of change it makes is kept only where the training graphs'
+    # passes measure faster with it; the others are vetoed
+    rp0, col0, _ = train[0]
+    proposed = sched.learned_table(net, rp0.numel() - 1, col0.numel(), hull, SCHED_MARGIN)
+    heur = tc.schedule_table(rp0.numel() - 1, col0.numel()).cpu().numpy()
     verified, vinfo = sched.verify_schedule(train, proposed)
-    info = {"train_graphs": [f"{k} {'scale' if k == 'kronecker' else 'n = 2^'}{s}, seed {sd}"
+    veto = sorted(set(sched.changed_classes(heur, proposed.cpu().numpy())) -
+                  set(sched.changed_classes(heur, verified.cpu().numpy())))
+    final = sched.learned_table(net, rp0.numel() - 1, col0.numel(), hull, SCHED_MARGIN, veto=veto)
+    isect = {"heuristic": [sched.isect_ms([g], None) for g in train],
+             "network": [sched.isect_ms([g], proposed.cpu().numpy()) for g in train],
+             "learned": [sched.isect_ms([g], final.cpu().numpy()) for g in train]}
+    meta = {"train_graphs": [f"{k} {'scale' if k == 'kronecker' else 'n = 2^'}{s}, seed {sd}"
                              for k, s, sd in TRAIN_GRAPHS],
-            "train_rows": int(len(ds.c)), "final_loss": float(losses[-1]),
-            "train_isect_ms": {"heuristic": vinfo["heuristic_ms"], "network": vinfo["proposed_ms"],
-                               "verified": vinfo["ms"]},
-            "reverted_classes": [list(x) for x in vinfo["reverted"]],
-            "profile_train_verify_s": time.perf_counter() - t0}
-    del train
-    torch.cuda.empty_cache()
-    return proposed, verified, info
+            "target": "sign(t) log2(1 + |t|), t = pass-time change in ps per probe element",
+            "rows": int(len(ms.c)), "steps": steps, "final_loss": float(losses[-1]),
+            "train_heuristic_ms": ms.base_ms,
+            "train_buckets_changed": {"network": int((proposed.cpu().numpy() != heur).sum()),
+                                      "learned": int((final.cpu().numpy() != heur).sum())},
+            "train_isect_ms": isect,
+            "device": torch.cuda.get_device_name(0), "measured_changes": changes,
+            "seconds": round(time.perf_counter() - t0, 1)}
+    sched.save_net(path, net, hull, SCHED_MARGIN, meta, veto)
+    log(f"schedule network written to {path}: {meta['rows']} rows, loss {meta['final_loss']:.3f}, "
+        f"changed buckets on the training graphs {meta['train_buckets_changed']}")
 
 
-def schedule_legs(tc, torch, n, rp, col, tables, steps, warmup, T):
-    """Whole steps under each learned table; counts must equal T."""
-    m = col.numel() // 2
-    out = {}
-    for name, table in tables:
-        c = tc.Counter(n, col.numel(), tc.Options(timing=True, sched_table=table))
-        st, res = timed_steps(c, rp, col, steps, warmup)
-        assert all(x.T == T for x in res), f"{name} table changed the count"
-        out[name] = {"value": m / st, "ms_per_step": st * 1e3, "phase_ms": phase_means(res),
-                     "strategy_items": res[-1].strategy_items}
+def learned_leg(tc, torch, n, rp, col, T, steps, warmup):
+    """Heuristic and learned steps, alternating; counts must equal T."""
+    from paper_2309_09064_amd import sched
+    if not os.path.exists(SCHED_NET):
+        return {"error": f"{os.path.relpath(SCHED_NET, ROOT)} missing (bench.py --train-schedule writes it)"}
+    net, hull, margin, doc = sched.load_net(SCHED_NET)
+    nnz = col.numel()
+    veto = [tuple(c) for c in doc.get("veto", [])]
+    table = sched.learned_table(net, n, nnz, hull, margin, veto=veto)
+    heur = tc.schedule_table(n, nnz)
+    changed = int((table != heur).sum())
+    out = {"network": os.path.relpath(SCHED_NET, ROOT), "train_graphs": doc["train_graphs"],
+           "margin": margin, "vetoed_classes": [list(c) for c in veto], "buckets_changed": changed}
+    if changed == 0:
+        out.update({"speedup_vs_heuristic": 1.0, "identical_to_heuristic": True, "target_met": False})
+        return out
+    counters = {"heuristic": tc.Counter(n, nnz, tc.Options(timing=True)),
+                "learned": tc.Counter(n, nnz, tc.Options(timing=True, sched_table=table))}
+    for c in counters.values():
+        for _ in range(warmup):
+            c(rp, col)
+    wall = {k: [] for k in counters}
+    res = {k: [] for k in counters}
+    for _ in range(steps):
+        for k, c in counters.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = c(rp, col)
+            wall[k].append(time.perf_counter() - t0)
+            res[k].append(r)
+    for k in counters:
+        assert all(x.T == T for x in res[k]), f"{k} schedule changed the count"
+        out[k] = {"ms_per_step": 1e3 * float(np.mean(wall[k])), "phase_ms": phase_means(res[k])}
+    gain = out["heuristic"]["ms_per_step"] / out["learned"]["ms_per_step"]
+    out.update({"speedup_vs_heuristic": gain, "identical_to_heuristic": False, "target_met": gain > 1 + GAIN_NOISE})
     return out
 
 
@@ -285,8 +343,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the Chung-Lu, scale-20 and batch legs")
     ap.add_argument("--main-only", action="store_true",
                     help="time only the headline leg, so that a profile of the run holds its kernels alone")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="first run a plain 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--train-schedule", metavar="PATH",
+                    help="measure the training graphs, train the schedule network, write it to PATH and exit")
     ap.add_argument("--train-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -300,8 +358,12 @@ def main():
     import paper_2309_09064_amd as tc
 
     torch.cuda.set_device(0)
-    if args.copy_probe:
-        copy_probe(torch)
+    # a streaming pass of known size: the bandwidth a plain kernel reaches
+    # here, and the calibration of the byte counters in a profile of this run
+    stream_gbs = copy_probe(torch)
+    if args.train_schedule:
+        train_schedule(tc, torch, args.train_schedule, args.train_steps)
+        return
     n, rp, col = make_graph(tc, torch, "kronecker", args.scale, args.seed)
     nnz = col.numel()
     m = nnz // 2
@@ -333,19 +395,12 @@ def main():
 
     learned = None
     secondary = {}
-    tables = None
     if not args.no_learned:
-        proposed, verified, linfo = learned_tables(tc, torch, args.train_steps)
-        tables = [("network_table", proposed), ("verified_table", verified)]
-        legs = schedule_legs(tc, torch, n, rp, col, tables, args.steps, args.warmup, T)
-        gain = {k: step_s * 1e3 / v["ms_per_step"] for k, v in legs.items()}
-        learned = {**legs, **linfo, "speedup_vs_heuristic": gain,
-                   "target_met": any(g > 1.0 for g in gain.values())}
-        log(f"learned: {json.dumps({k: v['ms_per_step'] for k, v in legs.items()})} ms/step vs heuristic "
-            f"{step_s * 1e3:.3f}")
+        learned = learned_leg(tc, torch, n, rp, col, T, args.steps, args.warmup)
+        log(f"learned: {json.dumps({k: v for k, v in learned.items() if k not in ('train_graphs',)})}")
 
     if not args.no_secondary:
-        secondary = secondary_legs(tc, torch, args, tables)
+        secondary = secondary_legs(tc, torch, args)
 
     cpu = None
     if not args.no_cpu:
@@ -377,15 +432,16 @@ def main():
                    "learned_schedule": learned, "secondary": secondary},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_isect",
-                     "bytes_per_launch": balg, "ms_per_launch": ms["isect"]},
+                     "bytes_per_launch": balg, "ms_per_launch": ms["isect"],
+                     "device_stream_gbs": stream_gbs},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
-def secondary_legs(tc, torch, args, tables):
+def secondary_legs(tc, torch, args):
     out = {}
-    # Chung-Lu 2^22 (power law): heuristic, and the learned tables
+    # Chung-Lu 2^22 (power law): heuristic, and the learned table
     n, rp, col = make_graph(tc, torch, "chunglu", 22, 1)
     m = col.numel() // 2
     c = tc.Counter(n, col.numel(), tc.Options(timing=True))
@@ -394,10 +450,8 @@ def secondary_legs(tc, torch, args, tables):
     cl = {"workload": "chung-lu n=2^22, gamma 2.1, mean degree 32, max expected degree 2^17, seed 1",
           "value": m / st, "ms_per_step": st * 1e3, "phase_ms": phase_means(res), "m": m, "triangles": r.T,
           "counts_bit_exact": exact_vs_golden("chunglu22", n, m, r)}
-    if tables is not None:
-        legs = schedule_legs(tc, torch, n, rp, col, tables, args.steps, args.warmup, r.T)
-        cl["learned_schedule"] = {**legs, "speedup_vs_heuristic": {k: st * 1e3 / v["ms_per_step"]
-                                                                   for k, v in legs.items()}}
+    if not args.no_learned:
+        cl["learned_schedule"] = learned_leg(tc, torch, n, rp, col, r.T, args.steps, args.warmup)
     out["chunglu22"] = cl
     log(f"chung-lu 2^22: {st * 1e3:.3f} ms/step")
     del rp, col

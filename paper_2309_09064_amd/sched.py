@@ -257,5 +257,210 @@ def learn_schedule(graphs, options: Options | None = None, seed: int = 0, steps:
     return table, net, ds, losses
 
 
+def feasible(n: int, nnz: int, options: Options | None = None, device=None) -> np.ndarray:
+    """[TC_NUM_BUCKETS, TC_NUM_STRATEGIES] bool: strategy s can run bucket b
+    under ``options`` (the library maps an infeasible request to another
+    strategy, so s is feasible where forcing it leaves it in place)."""
+    base = {**(options or Options()).__dict__, "sched_table": None}
+    out = np.zeros((TC_NUM_BUCKETS, TC_NUM_STRATEGIES), dtype=bool)
+    for s in range(TC_NUM_STRATEGIES):
+        t = schedule_table(n, nnz, Options(**{**base, "force_strategy": s}), device).cpu().numpy()
+        out[:, s] = t == s
+    return out
+
+
+def bucket_elements(row_ptr, col, levels=None, options: Options | None = None) -> np.ndarray:
+    """Probe elements per bucket under the heuristic (float64[TC_NUM_BUCKETS])."""
+    base = {**(options or Options()).__dict__, "sched_table": None, "force_strategy": -1}
+    prof = new_profile(row_ptr.device)
+    Counter(row_ptr.numel() - 1, col.numel(), Options(**base), row_ptr.device)(row_ptr, col, levels, profile=prof)
+    return prof.cpu().numpy().astype(np.float64)[..., 1].sum(axis=1)
+
+
+@dataclass
+class MarginalSet:
+    X: np.ndarray         # [R, 3] float32 features (ob, pb, kind)
+    c: np.ndarray         # [R] int32 strategy
+    t: np.ndarray         # [R] float32 pass-time change per element (ps), 0 for the heuristic's choice
+    w: np.ndarray         # [R] float32 weight: the bucket's share of its graph's elements
+    bucket: np.ndarray    # [R] bucket id
+    graph: np.ndarray     # [R] index of the graph
+    delta_ms: np.ndarray  # [R] measured pass-time change (ms)
+    spread_ms: np.ndarray  # [R] half the inter-quartile range of the paired differences (ms)
+    base_ms: list         # per graph: median pass time under the heuristic (ms)
+
+
+def collect_marginal(graphs, options: Options | None = None, min_share: float = 0.002, pairs: int = 5,
+                     log=None) -> MarginalSet:
+    """Whole-pass cost of each strategy change, one bucket at a time.
+
+    Per graph and per bucket holding at least ``min_share`` of the probe
+    elements, every other feasible strategy replaces the heuristic's choice
+    for that bucket alone, and the bucketing plus intersection time (HIP
+    events) is measured in ``pairs`` (heuristic, changed) pairs run back to
+    back; the change's cost is the median paired difference.  A bucket's
+    items share the pass with every other bucket, so only the pass time says
+    what a change is worth: a strategy that spends fewer wave-ticks on a
+    bucket can still lengthen the pass (its items finish last, or it takes
+    memory bandwidth from the rest).  Training rows: the change per element
+    in picoseconds, and 0 for the heuristic's own choice."""
+    base = {**(options or Options()).__dict__, "timing": True, "force_strategy": -1}
+    rows = {k: [] for k in ("b", "c", "t", "w", "g", "d", "sp")}
+    base_ms = []
+    for gi, g in enumerate(graphs):
+        rp, col = g[0], g[1]
+        lev = g[2] if len(g) > 2 else None
+        n, nnz = rp.numel() - 1, col.numel()
+        heur = schedule_table(n, nnz, Options(**{**base, "sched_table": None}), rp.device)
+        heur_np = heur.cpu().numpy()
+        feas = feasible(n, nnz, Options(**{**base, "timing": False}), rp.device)
+        elems = bucket_elements(rp, col, lev, options)
+        share = elems / max(elems.sum(), 1.0)
+        table = heur.clone()
+        cnt = Counter(n, nnz, Options(**{**base, "sched_table": table}), rp.device)
+
+        def run(t_np):
+            table.copy_(torch.from_numpy(t_np))
+            r = cnt(rp, col, lev)
+            return r.ms["bucket"] + r.ms["isect"]
+
+        for _ in range(2):
+            run(heur_np)
+        hs = []
+        for b in np.nonzero(share >= min_share)[0]:
+            for s in np.nonzero(feas[b])[0]:
+                if s == heur_np[b]:
+                    continue
+                alt = heur_np.copy()
+                alt[b] = s
+                run(alt)                       # warm the changed shape
+                d = []
+                for _ in range(pairs):
+                    h = run(heur_np)
+                    a = run(alt)
+                    hs.append(h)
+                    d.append(a - h)
+                q1, med, q3 = np.percentile(d, [25, 50, 75])
+                for k, v in (("b", b), ("c", s), ("t", med * 1e9 / elems[b]), ("w", share[b]), ("g", gi),
+                             ("d", med), ("sp", 0.5 * (q3 - q1))):
+                    rows[k].append(v)
+            for k, v in (("b", b), ("c", heur_np[b]), ("t", 0.0), ("w", share[b]), ("g", gi), ("d", 0.0),
+                         ("sp", 0.0)):
+                rows[k].append(v)
+            if log:
+                log(f"graph {gi} bucket {b} share {share[b]:.3f} heur {heur_np[b]}: "
+                    + " ".join(f"{c}:{d:+.3f}" for c, d, bb in zip(rows['c'], rows['d'], rows['b'])
+                               if bb == b and c != heur_np[b]))
+        base_ms.append(float(np.median(hs)) if hs else float("nan"))
+    b = np.asarray(rows["b"], dtype=np.int64)
+    return MarginalSet(X=bucket_features(b), c=np.asarray(rows["c"], np.int32), t=np.asarray(rows["t"], np.float32),
+                       w=np.asarray(rows["w"], np.float32), bucket=b, graph=np.asarray(rows["g"], np.int32),
+                       delta_ms=np.asarray(rows["d"]), spread_ms=np.asarray(rows["sp"]), base_ms=base_ms)
+
+
+def sgnlog(t) -> np.ndarray:
+    """The marginal training target: sign(t) * log2(1 + |t|) of the pass-time
+    change t in picoseconds per element (changes span four decades; the
+    small ones near zero decide the schedule)."""
+    t = np.asarray(t, dtype=np.float64)
+    return (np.sign(t) * np.log2(1.0 + np.abs(t))).astype(np.float32)
+
+
+def feature_hull(X: np.ndarray) -> dict:
+    """Per kind, the owner- and partner-class ranges seen in training:
+    {kind: [ob_min, ob_max, pb_min, pb_max]}."""
+    X = np.asarray(X)
+    out = {}
+    for k in np.unique(X[:, 2]).astype(int):
+        m = X[:, 2] == k
+        out[int(k)] = [int(X[m, 0].min()), int(X[m, 0].max()), int(X[m, 1].min()), int(X[m, 1].max())]
+    return out
+
+
+def inside_hull(hull: dict) -> np.ndarray:
+    """bool[TC_NUM_BUCKETS]: the bucket's features lie in the training ranges."""
+    X = bucket_features(np.arange(TC_NUM_BUCKETS))
+    ins = np.zeros(TC_NUM_BUCKETS, dtype=bool)
+    for k, (o0, o1, p0, p1) in hull.items():
+        ins |= (X[:, 2] == int(k)) & (X[:, 0] >= o0) & (X[:, 0] <= o1) & (X[:, 1] >= p0) & (X[:, 1] <= p1)
+    return ins
+
+
+def select_table(cost: np.ndarray, feas: np.ndarray, heur: np.ndarray, inside: np.ndarray,
+                 margin: float) -> np.ndarray:
+    """Per bucket: the cheapest feasible strategy by the predicted cost when
+    the bucket lies inside the training ranges and the prediction beats the
+    heuristic's choice by more than ``margin``; else the heuristic's choice.
+    Ties go to the lower strategy number."""
+    c = np.where(feas, np.asarray(cost, dtype=np.float64), np.inf)
+    best = np.argmin(c, axis=1)
+    b = np.arange(c.shape[0])
+    gain = c[b, heur] - c[b, best]
+    return np.where(inside & (gain > margin), best, heur).astype(np.int32)
+
+
+def changed_classes(heur, table) -> list:
+    """The classes of change (heuristic strategy a -> table strategy b) of a table."""
+    h, t = np.asarray(heur), np.asarray(table)
+    return sorted({(int(a), int(b)) for a, b in zip(h, t) if a != b})
+
+
+def learned_table(net: "CostNet", n: int, nnz: int, hull: dict, margin: float, options: Options | None = None,
+                  device=None, veto=()) -> torch.Tensor:
+    """The table a trained marginal-cost network gives a graph of n vertices
+    and nnz entries under ``options`` (int32 device tensor).  Changes of a
+    class in ``veto`` ((heuristic strategy, proposed strategy) pairs, those
+    that measured slower on the training graphs) keep the heuristic's choice."""
+    base = {**(options or Options()).__dict__, "sched_table": None, "force_strategy": -1}
+    dev = device if device is not None else net.device
+    heur = schedule_table(n, nnz, Options(**base), dev).cpu().numpy()
+    feas = feasible(n, nnz, Options(**base), dev)
+    _, cost = net.schedule(Options(**base), with_cost=True)
+    t = select_table(cost.cpu().numpy(), feas, heur, inside_hull(hull), margin)
+    for a, b in veto:
+        t[(heur == a) & (t == b)] = a
+    return torch.from_numpy(t).to(dev)
+
+
+def learn_marginal(graphs, options: Options | None = None, seed: int = 0, steps: int = 3000, lr: float = 1e-2,
+                   min_share: float = 0.002, pairs: int = 5, log=None):
+    """Measure (``collect_marginal``), then train the network on sgnlog of
+    the per-element pass-time changes, each row weighed by its bucket's
+    share of the elements.  Returns (net, marginal set, losses, hull)."""
+    ms = collect_marginal(graphs, options, min_share, pairs, log)
+    if len(ms.c) == 0:
+        raise ValueError("no bucket holds min_share of the elements")
+    net = CostNet(seed=seed)
+    losses = net.train(ms.X, ms.c, sgnlog(ms.t), steps, lr=lr, w=ms.w)
+    return net, ms, losses, feature_hull(ms.X)
+
+
+def save_net(path: str, net: "CostNet", hull: dict, margin: float, meta: dict, veto=()):
+    """The trained network as JSON: parameters (float32 values, in the
+    library's order), training ranges, decision margin, vetoed classes of
+    change, and ``meta``."""
+    import json
+    doc = {"hidden": net.hidden, "k": net.k, "params": [float(x) for x in net.params.cpu().numpy()],
+           "hull": {str(k): v for k, v in hull.items()}, "margin": margin,
+           "veto": [list(map(int, c)) for c in veto], **meta}
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1)
+
+
+def load_net(path: str, device=None):
+    """(net, hull, margin, document) from a file written by ``save_net``;
+    the vetoed classes are ``document["veto"]``."""
+    import json
+    with open(path) as f:
+        doc = json.load(f)
+    net = CostNet(hidden=doc["hidden"], k=doc["k"], device=device)
+    p = torch.tensor(doc["params"], dtype=torch.float32)
+    if p.numel() != net.count:
+        raise ValueError(f"{path}: {p.numel()} parameters, the network has {net.count}")
+    net.params.copy_(p.to(net.device))
+    return net, {int(k): v for k, v in doc["hull"].items()}, float(doc["margin"]), doc
+
+
 __all__ = ["CostNet", "Dataset", "bucket_features", "collect_profile", "dataset", "isect_ms", "learn_schedule",
-           "verify_schedule", "TCError"]
+           "verify_schedule", "TCError", "MarginalSet", "collect_marginal", "feasible", "bucket_elements", "sgnlog", "feature_hull", "inside_hull",
+           "select_table", "learned_table", "learn_marginal", "save_net", "load_net", "changed_classes"]
