@@ -572,6 +572,31 @@ __device__ __forceinline__ int32_t upper_idx(const int32_t *a, int32_t len, int3
     return lo;
 }
 
+// Line samples of a list array: smp[j] = a[32 j + off], the first element of
+// every 128-byte line (off: the first index at a line start).  A search in a
+// list first narrows to one line through the samples (a small array that
+// stays in cache), then searches that line: about one line of the list is
+// read instead of one per halving step, and that line is the first one the
+// stream then reads anyway.
+constexpr int kSmpShift = 5;
+__host__ __device__ constexpr int64_t samples_of(int64_t entries) { return (entries >> kSmpShift) + 2; }
+
+// First index i in [b, b + len) with a[i] >= v, else b + len (a sorted there).
+__device__ __forceinline__ int32_t sampled_lower(const int32_t *a, const int32_t *smp, int32_t off, int32_t b,
+                                                 int32_t len, int32_t v) {
+    const int32_t e = b + len;
+    // samples whose positions 32 j + off lie in [b, e): j0 .. j1
+    const int32_t j0 = b > off ? (b - off + 31) >> kSmpShift : 0;
+    const int32_t j1 = e - 1 >= off ? (e - 1 - off) >> kSmpShift : -1;
+    if (j0 > j1) return b + lower_idx(a + b, len, v);
+    const int32_t j = j0 + lower_idx(smp + j0, j1 - j0 + 1, v);   // first sample >= v (j1 + 1: none)
+    // the answer lies after the sample before j (or from b) and at most at
+    // sample j's position (or the list's end)
+    const int32_t ps = j == j0 ? b : ((j - 1) << kSmpShift) + off + 1;
+    const int32_t pe = j <= j1 ? (j << kSmpShift) + off : e;
+    return ps + lower_idx(a + ps, pe - ps, v);
+}
+
 // search_count that also returns, for each key found, its index in a.
 template <int kPer>
 __device__ __forceinline__ uint32_t search_find(const int32_t *a, int32_t len, const int32_t (&v)[kPer],
@@ -617,6 +642,8 @@ struct Graph {
     const uint8_t *own;   // per c0 entry: bit k set when the row's vertex owns the edge for kind k
     const int32_t *pos0, *pos1;   // per-edge counts: input entry of every c0 / c1 entry
     int wide;           // the list arrays reach 2^30 entries: element byte offsets need 64 bits
+    const int32_t *s0, *s1;   // line samples of c0 / c1 (sliced searches; NULL when nothing is sliced)
+    int32_t so0, so1;         // index of the first line start in c0 / c1
 };
 
 // Elements per lane per window step, and the per-wavefront LDS scratch used
@@ -789,9 +816,11 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
     bool mine = partner_at(g, kind, p0 + l, je, sy, yb, yid);
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     if (sliced && mine) {
-        const int32_t b = lower_idx(lists + yb, sy, lo);
-        const int32_t e = lower_idx(lists + yb, sy, hi);
-        yb += b;
+        const int32_t *smp = kind == 0 ? g.s0 : g.s1;
+        const int32_t so = kind == 0 ? g.so0 : g.so1;
+        const int32_t b = sampled_lower(lists, smp, so, yb, sy, lo);
+        const int32_t e = sampled_lower(lists, smp, so, b, yb + sy - b, hi);
+        yb = b;
         sy = e - b;
         mine = sy > 0;   // two lists may not start at one window offset
     }
@@ -1466,6 +1495,7 @@ struct CountLayout {
     int32_t *bucket_items, *bucket_off, *bucket_cur, *q;
     Item *items;
     unsigned long long *stats;   // [0..6] unit stats, [8..9] T0/T1
+    int32_t *s0, *s1;            // line samples of the c0 / c1 lists (sliced searches)
 };
 
 static_assert(lane_partners(kLaneMergeOb) >= kMinPartnersPerItem, "lane items must respect the item capacity");
@@ -1489,6 +1519,23 @@ int64_t item_capacity(int32_t n, int64_t nnz) {
     return 2 * ((int64_t)n + nnz / kMinPartnersPerItem) + 64;
 }
 
+// Line samples of a list array (see sampled_lower).  Valid entries: the
+// c0 array holds *e0x2 of them, the c1 array nnz - *e0x2, the input rows
+// (cover-edge view) nnz.
+enum { kSmpC0 = 0, kSmpC1 = 1, kSmpAll = 2 };
+__global__ void k_samples(const int32_t *__restrict__ a, int32_t off, const int64_t *__restrict__ e0x2p, int mode,
+                          int64_t nnz, int32_t *__restrict__ smp) {
+    const int64_t lim = mode == kSmpC0 ? *e0x2p : mode == kSmpC1 ? nnz - *e0x2p : nnz;
+    const int64_t cnt = lim > off ? (lim - off + 31) >> kSmpShift : 0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += (int64_t)gridDim.x * blockDim.x)
+        smp[j] = a[(j << kSmpShift) + off];
+}
+
+// index of the first element of a that starts a 128-byte line
+int32_t line_start(const int32_t *a) {
+    return (int32_t)(((128 - (reinterpret_cast<uintptr_t>(a) & 127)) & 127) >> 2);
+}
+
 CountLayout carve_count(Carver &c, int32_t n, int64_t nnz) {
     CountLayout L;
     const int64_t nn = n > 0 ? n : 1;
@@ -1503,6 +1550,8 @@ CountLayout carve_count(Carver &c, int32_t n, int64_t nnz) {
     L.q = c.take<int32_t>(kQueueBlockInts);
     L.items = c.take<Item>(item_capacity(n, nnz));
     L.stats = c.take<unsigned long long>(16);
+    L.s0 = c.take<int32_t>(samples_of(nnz));
+    L.s1 = c.take<int32_t>(samples_of(nnz));
     return L;
 }
 
@@ -1683,6 +1732,9 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     if (cfg.tv && n > 0) TC_TRY(fill_u32(cfg.tv, 0, 2 * (int64_t)n, s));
     if (cfg.sup && nnz > 0) TC_TRY(fill_u32(cfg.sup, 0, nnz, s));
     const unsigned gp = (unsigned)di.cus * 8;
+    // owner lists are sliced only when longer than a workgroup slice, and no
+    // list is longer than nnz: below that, no search runs and no samples
+    const bool sliced_lists = sc.wg_slicing && nnz > ((int64_t)1 << sc.wg_cap_log2);
     if (n > 0) {
         TC_TRY(tile_table_run(n, pb.rp0, L.tlo, L.thi, s));
         hipLaunchKernelGGL(k_own, dim3(gp), dim3(kThreads), 0, s, n, pb.e0x2, pb.rp0, pb.c0, pb.up0, pb.rp1, pb.vrec, L.cnt,
@@ -1697,6 +1749,14 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         hipLaunchKernelGGL((k_items<1>), dim3(gu), dim3(kItemThreads), 0, s, n, pb.rp0, pb.up0, pb.rp1, L.cnt,
                            L.work, sc, L.bucket_items, L.bucket_off, L.bucket_cur, L.items, L.stats, nullptr);
         TC_HIP_TRY(hipGetLastError());
+        if (sliced_lists) {
+            const unsigned gs = grid_for(samples_of(nnz), 256, (int64_t)1 << 16);
+            hipLaunchKernelGGL(k_samples, dim3(gs), dim3(256), 0, s, pb.c0, line_start(pb.c0), pb.e0x2, (int)kSmpC0,
+                               nnz, L.s0);
+            hipLaunchKernelGGL(k_samples, dim3(gs), dim3(256), 0, s, pb.c1, line_start(pb.c1), pb.e0x2,
+                               cover ? (int)kSmpAll : (int)kSmpC1, nnz, L.s1);
+            TC_HIP_TRY(hipGetLastError());
+        }
     }
     if (cfg.timing) TC_HIP_TRY(hipEventRecord(ev.e[1], s));
     if (n > 0) {
@@ -1704,7 +1764,8 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         // byte offsets of list elements fit 32 bits below 2^30 entries (with
         // the padding)
         const int wide = nnz + 2 * kListPad + 1024 >= (int64_t(1) << 30) ? 1 : 0;
-        Graph g{pb.rp0, pb.c0, pb.up0, pb.rp1, pb.c1, pb.vrec, L.own, pb.pos0, pb.pos1, wide};
+        Graph g{pb.rp0,       pb.c0,  pb.up0, pb.rp1, pb.c1, pb.vrec, L.own, pb.pos0, pb.pos1, wide,
+                sliced_lists ? L.s0 : nullptr, sliced_lists ? L.s1 : nullptr, line_start(pb.c0), line_start(pb.c1)};
         const Sink sk{cfg.gid, cfg.batch_counts, cfg.tv, cfg.sup, cfg.cover_lev};
         if (cfg.prof && batch)
             hipLaunchKernelGGL((k_isect<true, kModeBatch>), dim3(gi), dim3(kIsectThreads), lds_bytes, s, g, L.items,
