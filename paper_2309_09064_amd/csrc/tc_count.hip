@@ -756,11 +756,12 @@ __device__ __forceinline__ uint32_t stream_rows(const int32_t *lists, uint64_t m
             s_rem -= kWave;
         }
     };
-    // the lanes of a partial or spent row become padding keys (uniform test)
+    // the lanes of a partial or spent row become padding keys: a compare
+    // and a select per key, unconditionally (testing first whether the row
+    // is partial makes the compiler select between selects, twice the VALU)
     auto masked = [&](int32_t (&v)[kPer], const int32_t (&lim)[kPer]) {
 #pragma unroll
-        for (int u = 0; u < kPer; ++u)
-            if (lim[u] < kWave) v[u] = l < lim[u] ? v[u] : kNoKey;
+        for (int u = 0; u < kPer; ++u) v[u] = lim[u] > l ? v[u] : kNoKey;
     };
     // software pipeline, two windows in ping-pong registers: the next
     // window's loads are issued (unconditionally, past the end at valid
