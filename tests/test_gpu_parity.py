@@ -233,6 +233,20 @@ def test_count_sliced_owner_lists(tc, cfg):
     assert tc.count(rp, col, dev(np.zeros(700, np.int32)), tc.Options(**cfg)).T == 700 * 699 * 698 // 6
 
 
+@pytest.mark.parametrize("slice_max", [64, 128, 512])
+def test_count_many_small_slices(tc, slice_max):
+    # workgroup slices of 64..512 owner elements: every long owner list is cut
+    # into many value ranges, and each partner list is narrowed to each range
+    # through the line samples (searches that start and end at every offset
+    # within a line); with every edge horizontal both kinds' lists are sliced
+    opts = tc.Options(force_strategy=1, wg_slice_max=slice_max)
+    for g in (complete(300), gnp(700, 0.3, 11), graph("kron14")):
+        check_count(tc, g, opts, levels=np.zeros(g.n, np.int32))
+        check_count(tc, g, opts)
+    rp, col = to_gpu(complete(300))
+    assert tc.count(rp, col, dev(np.zeros(300, np.int32)), opts).T == 300 * 299 * 298 // 6
+
+
 def test_count_closed_forms(tc):
     from _graphs import book, complete_tripartite, choose
     for n in (3, 5, 9, 20):
