@@ -127,11 +127,16 @@ typedef struct tc_options {
                                  most 31) take the lane merge (one lane per
                                  item of at most 32 partners); 0 = default
                                  15, -1 = never                              */
-    const int32_t *sched_table; /* device int32[TC_NUM_BUCKETS] strategies,
-                                 read when schedule == TC_SCHED_TABLE (NULL
-                                 otherwise).  A hash strategy in a bucket
-                                 whose owners exceed that table's capacity
-                                 is replaced as with force_strategy.         */
+    const int32_t *sched_table; /* device int32[TC_NUM_BUCKETS], read when
+                                 schedule == TC_SCHED_TABLE (NULL otherwise):
+                                 bits 0-1 the bucket's strategy, bit 2 (with
+                                 TC_STRAT_WG_HASH) owner slices of half the
+                                 usual size; other values mean binary
+                                 search.  A hash strategy in a bucket whose
+                                 owners exceed that table's capacity is
+                                 replaced as with force_strategy, and the
+                                 half-slice bit is dropped where it changes
+                                 nothing (owners shorter than half a slice). */
     int64_t batch_group_entries; /* batched counts: most vertices and most
                                  CSR entries one internal group of graphs
                                  may hold (a larger graph gets a group of
@@ -314,7 +319,9 @@ int tc_batch_plan_destroy(tc_batch_plan *plan);
 /*
  * The strategy every bucket gets from tc_count under opt for a graph of n
  * vertices and nnz CSR entries: force_strategy, the table or the heuristic,
- * after the feasibility rules.  d_table: device int32[TC_NUM_BUCKETS].
+ * after the feasibility rules, with bit 2 set where a table's half-size
+ * workgroup slices apply (see tc_options.sched_table).  d_table: device
+ * int32[TC_NUM_BUCKETS].
  */
 int tc_schedule_table(int32_t n, int64_t nnz, const tc_options *opt, int32_t *d_table, void *stream);
 

@@ -98,7 +98,7 @@ struct SchedCfg {
     int32_t wave_ob_max;   // largest owner-size class a wavefront table holds
     int32_t wg_ob_max;     // largest owner-size class the workgroup table holds whole
     int32_t wg_cap_log2;   // log2 of the owner elements one workgroup table holds
-    int32_t wg_slicing;    // longer owner lists are sliced (else they are searched)
+    int32_t wg_slicing;    // longer owner lists are sliced (else they are searched; also for half slices)
     int32_t heur_wave_ob;  // heuristic: wavefront table up to this class
     int32_t heur_merge_ob; // heuristic: lane merge up to this class (-1: never)
     int32_t chunk_work;    // probe elements per wavefront item
@@ -110,12 +110,17 @@ struct SchedCfg {
 // takes any owner while slicing is on: a list longer than half its table is
 // cut into value-range slices that each fill at most half of it, one work
 // item per slice.
+// A table entry holds the strategy in bits 0-1 and, in bit 2, the tile
+// choice of the workgroup hash: slices of half the usual size (more items,
+// a quarter-full table's pending probes halved).  Other values mean binary
+// search.
+constexpr int32_t kTileHalf = 4;
 __device__ __forceinline__ int strategy_for(const SchedCfg &c, int b) {
     const int ob = (b >> 5) & 31;
     const bool wg_ok = ob <= c.wg_ob_max || c.wg_slicing;
     int s;
     if (c.force >= 0) s = c.force;
-    else if (c.table) s = c.table[b];
+    else if (c.table) s = (uint32_t)c.table[b] < 8u ? (c.table[b] & 3) : TC_STRAT_BSEARCH;
     else if (ob <= c.heur_merge_ob) s = TC_STRAT_MERGE;
     else s = ob <= c.heur_wave_ob ? TC_STRAT_WAVE_HASH : (wg_ok ? TC_STRAT_WG_HASH : TC_STRAT_BSEARCH);
     if (s == TC_STRAT_WAVE_HASH && ob > c.wave_ob_max) s = wg_ok ? TC_STRAT_WG_HASH : TC_STRAT_BSEARCH;
@@ -124,8 +129,18 @@ __device__ __forceinline__ int strategy_for(const SchedCfg &c, int b) {
     return s;
 }
 
-constexpr int kSliceShift = 14;          // slice index in the item code's top 18 bits
+constexpr int kHalfShift = 14;           // item code bit: the item's owner is cut into half-size slices
+constexpr int kSliceShift = 15;          // slice index in the item code's top 17 bits
 constexpr int kMaxSlicesLog2 = 32 - kSliceShift;
+
+// Half-size workgroup slices for bucket b: asked for by its table entry,
+// the bucket takes the workgroup hash, and its owner lists are long enough
+// to be cut finer (at least half a slice).
+__device__ __forceinline__ int tile_half(const SchedCfg &c, int b, int s) {
+    if (c.force >= 0 || !c.table || s != TC_STRAT_WG_HASH || !c.wg_slicing) return 0;
+    const int32_t v = c.table[b];
+    return (uint32_t)v < 8u && (v & kTileHalf) && ((b >> 5) & 31) >= c.wg_cap_log2 - 1 ? 1 : 0;
+}
 
 // Slices of an owner list of sx elements under the workgroup hash.
 __device__ __forceinline__ int32_t owner_slices(int32_t sx, int cap_log2) {
@@ -286,7 +301,7 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
         const int32_t minp = s == TC_STRAT_WG_HASH ? kMinPartnersPerWgItem : kMinPartnersPerItem;
         // a sliced owner: each slice streams about w / nsl elements; the
         // items of a unit stay at most slices + partner chunks in number
-        const int32_t nsl = s == TC_STRAT_WG_HASH ? owner_slices(sx, sc.wg_cap_log2) : 1;
+        const int32_t nsl = s == TC_STRAT_WG_HASH ? owner_slices(sx, sc.wg_cap_log2 - tile_half(sc, b, s)) : 1;
         int64_t nch = ((int64_t)w / nsl + target - 1) / target;
         int64_t cap = (je - jb + minp - 1) / minp;
         if (nsl > 1) cap = (cap + nsl - 1) / nsl;
@@ -342,7 +357,8 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
         const int32_t jb = rp0[x], je = rp0[x + 1];
         const int64_t len = je - jb;
         const int32_t pos = bbase[bk[k]] + loc[k];
-        const int32_t code = (int32_t)(u & 1) | (st[k] << 1) | (bk[k] << 3);
+        const int32_t code =
+            (int32_t)(u & 1) | (st[k] << 1) | (bk[k] << 3) | (tile_half(sc, bk[k], st[k]) << kHalfShift);
         for (int32_t si = 0; si < nsls[k]; ++si)
             for (int32_t c = 0; c < nchs[k]; ++c) {
                 Item it;
@@ -1280,7 +1296,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
         const int32_t sx = list_size(kind, g.up0, g.rp1, x);
         // the owner slice of this item: positions [a_lo, a_hi), values [lo, hi)
-        const int32_t nsl = owner_slices(sx, wg_cap_log2);
+        const int32_t nsl = owner_slices(sx, wg_cap_log2 - (((uint32_t)item.code >> kHalfShift) & 1));
         const int32_t si = (int32_t)((uint32_t)item.code >> kSliceShift);
         const int32_t a_lo = (int32_t)((int64_t)sx * si / nsl), a_hi = (int32_t)((int64_t)sx * (si + 1) / nsl);
         const bool sliced = nsl > 1;
@@ -1590,9 +1606,10 @@ static SchedCfg sched_cfg(int32_t n, int64_t nnz, const CountCfg &cfg) {
     sc.wave_ob_max = wave_log2 - 2;
     sc.wg_cap_log2 = cfg.wg_slice_max > 0 ? ilog2_host(cfg.wg_slice_max) : wg_log2 - kWgCapShift;
     sc.wg_ob_max = sc.wg_cap_log2 - 1;
-    {   // slicing needs at most 2^18 slices per owner list (list length <= min(n - 1, nnz))
+    {   // slicing needs at most 2^17 slices per owner list (list length <= min(n - 1, nnz)),
+        // also with half-size slices
         const int64_t longest = (int64_t)n - 1 < nnz ? (int64_t)n - 1 : nnz;
-        sc.wg_slicing = longest <= ((int64_t)1 << (kMaxSlicesLog2 + sc.wg_cap_log2)) ? 1 : 0;
+        sc.wg_slicing = longest <= ((int64_t)1 << (kMaxSlicesLog2 + sc.wg_cap_log2 - 1)) ? 1 : 0;
     }
     // heuristic default: wavefront tables up to a quarter full (linear
     // probing lengthens quickly above that; the feasibility limit is half)
@@ -1605,7 +1622,10 @@ static SchedCfg sched_cfg(int32_t n, int64_t nnz, const CountCfg &cfg) {
 
 static __global__ void k_schedule_table(SchedCfg sc, int32_t *__restrict__ out) {
     const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (b < kBuckets) out[b] = strategy_for(sc, b);
+    if (b < kBuckets) {
+        const int st = strategy_for(sc, b);
+        out[b] = st | (tile_half(sc, b, st) ? kTileHalf : 0);
+    }
 }
 
 int schedule_table_run(int32_t n, int64_t nnz, const CountCfg &cfg, int32_t *table, hipStream_t s) {

@@ -217,8 +217,9 @@ def verify_schedule(graphs, table, options: Options | None = None, runs: int = 7
     so each class of change, (heuristic strategy a -> proposed strategy b),
     is tried on its own: a class is reverted to the heuristic's choice when
     the pass runs faster without it (by more than ``margin``).  If the
-    result is still not faster than the heuristic, the heuristic's table is
-    returned.  Returns (table as an int32 device tensor, {"heuristic_ms",
+    result is not faster than the heuristic by more than ``margin`` as
+    well, the heuristic's table is returned (the heuristic is the fallback
+    and the judge of the learned table's gain).  Returns (table as an int32 device tensor, {"heuristic_ms",
     "proposed_ms", "ms", "reverted": [(a, b), ...]})."""
     rp0, col0 = graphs[0][0], graphs[0][1]
     heur = schedule_table(rp0.numel() - 1, col0.numel(), Options(**{**(options or Options()).__dict__,
@@ -234,7 +235,7 @@ def verify_schedule(graphs, table, options: Options | None = None, runs: int = 7
         if t < t_cur * (1.0 - margin):
             cur, t_cur = trial, t
             reverted.append((a, b))
-    if t_cur >= t_heur:
+    if t_cur >= t_heur * (1.0 - margin):
         cur, t_cur = heur.astype(np.int32), t_heur
     info = {"heuristic_ms": t_heur, "proposed_ms": t_prop, "ms": t_cur, "reverted": reverted}
     return torch.from_numpy(np.ascontiguousarray(cur)).to(rp0.device), info
@@ -257,15 +258,25 @@ def learn_schedule(graphs, options: Options | None = None, seed: int = 0, steps:
     return table, net, ds, losses
 
 
+# Actions of the marginal-cost schedule, as strategy-table values: the four
+# strategies, and the workgroup hash with half-size slices (table bit 2).
+TILE_HALF = 4
+ACTIONS = np.array([0, 1, 2, 3, 1 | TILE_HALF], dtype=np.int32)
+ACTION_NAMES = ["wave_hash", "wg_hash", "bsearch", "merge", "wg_hash_half_slices"]
+
+
 def feasible(n: int, nnz: int, options: Options | None = None, device=None) -> np.ndarray:
-    """[TC_NUM_BUCKETS, TC_NUM_STRATEGIES] bool: strategy s can run bucket b
-    under ``options`` (the library maps an infeasible request to another
-    strategy, so s is feasible where forcing it leaves it in place)."""
-    base = {**(options or Options()).__dict__, "sched_table": None}
-    out = np.zeros((TC_NUM_BUCKETS, TC_NUM_STRATEGIES), dtype=bool)
-    for s in range(TC_NUM_STRATEGIES):
-        t = schedule_table(n, nnz, Options(**{**base, "force_strategy": s}), device).cpu().numpy()
-        out[:, s] = t == s
+    """[TC_NUM_BUCKETS, len(ACTIONS)] bool: action a can run bucket b under
+    ``options`` (the library maps an infeasible request to another strategy,
+    or drops the tile choice where it changes nothing, so an action is
+    feasible where asking for it leaves it in place)."""
+    base = {**(options or Options()).__dict__, "sched_table": None, "force_strategy": -1}
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = np.zeros((TC_NUM_BUCKETS, len(ACTIONS)), dtype=bool)
+    for a, v in enumerate(ACTIONS):
+        want = torch.full((TC_NUM_BUCKETS,), int(v), dtype=torch.int32, device=dev)
+        t = schedule_table(n, nnz, Options(**{**base, "sched_table": want}), dev).cpu().numpy()
+        out[:, a] = t == v
     return out
 
 
@@ -280,7 +291,7 @@ def bucket_elements(row_ptr, col, levels=None, options: Options | None = None) -
 @dataclass
 class MarginalSet:
     X: np.ndarray         # [R, 3] float32 features (ob, pb, kind)
-    c: np.ndarray         # [R] int32 strategy
+    c: np.ndarray         # [R] int32 action (index into ACTIONS)
     t: np.ndarray         # [R] float32 pass-time change per element (ps), 0 for the heuristic's choice
     w: np.ndarray         # [R] float32 weight: the bucket's share of its graph's elements
     bucket: np.ndarray    # [R] bucket id
@@ -295,8 +306,9 @@ def collect_marginal(graphs, options: Options | None = None, min_share: float = 
     """Whole-pass cost of each strategy change, one bucket at a time.
 
     Per graph and per bucket holding at least ``min_share`` of the probe
-    elements, every other feasible strategy replaces the heuristic's choice
-    for that bucket alone, and the bucketing plus intersection time (HIP
+    elements, every other feasible action (a strategy, or the workgroup hash
+    with half-size slices) replaces the heuristic's choice for that bucket
+    alone, and the bucketing plus intersection time (HIP
     events) is measured in ``pairs`` (heuristic, changed) pairs run back to
     back; the change's cost is the median paired difference.  A bucket's
     items share the pass with every other bucket, so only the pass time says
@@ -329,10 +341,10 @@ def collect_marginal(graphs, options: Options | None = None, min_share: float = 
         hs = []
         for b in np.nonzero(share >= min_share)[0]:
             for s in np.nonzero(feas[b])[0]:
-                if s == heur_np[b]:
+                if ACTIONS[s] == heur_np[b]:
                     continue
                 alt = heur_np.copy()
-                alt[b] = s
+                alt[b] = ACTIONS[s]
                 run(alt)                       # warm the changed shape
                 d = []
                 for _ in range(pairs):
@@ -413,13 +425,13 @@ def learned_table(net: "CostNet", n: int, nnz: int, hull: dict, margin: float, o
     that measured slower on the training graphs) keep the heuristic's choice."""
     base = {**(options or Options()).__dict__, "sched_table": None, "force_strategy": -1}
     dev = device if device is not None else net.device
-    heur = schedule_table(n, nnz, Options(**base), dev).cpu().numpy()
-    feas = feasible(n, nnz, Options(**base), dev)
-    _, cost = net.schedule(Options(**base), with_cost=True)
-    t = select_table(cost.cpu().numpy(), feas, heur, inside_hull(hull), margin)
+    heur = schedule_table(n, nnz, Options(**base), dev).cpu().numpy()   # heuristic values are actions 0..3
+    feas = feasible(n, nnz, Options(**base), dev)[:, :net.k]
+    cost = net.forward(torch.from_numpy(bucket_features(np.arange(TC_NUM_BUCKETS)))).cpu().numpy()
+    t = ACTIONS[select_table(cost, feas, heur, inside_hull(hull), margin)]
     for a, b in veto:
         t[(heur == a) & (t == b)] = a
-    return torch.from_numpy(t).to(dev)
+    return torch.from_numpy(np.ascontiguousarray(t, dtype=np.int32)).to(dev)
 
 
 def learn_marginal(graphs, options: Options | None = None, seed: int = 0, steps: int = 3000, lr: float = 1e-2,
@@ -430,7 +442,7 @@ def learn_marginal(graphs, options: Options | None = None, seed: int = 0, steps:
     ms = collect_marginal(graphs, options, min_share, pairs, log)
     if len(ms.c) == 0:
         raise ValueError("no bucket holds min_share of the elements")
-    net = CostNet(seed=seed)
+    net = CostNet(k=len(ACTIONS), seed=seed)
     losses = net.train(ms.X, ms.c, sgnlog(ms.t), steps, lr=lr, w=ms.w)
     return net, ms, losses, feature_hull(ms.X)
 
@@ -463,4 +475,5 @@ def load_net(path: str, device=None):
 
 __all__ = ["CostNet", "Dataset", "bucket_features", "collect_profile", "dataset", "isect_ms", "learn_schedule",
            "verify_schedule", "TCError", "MarginalSet", "collect_marginal", "feasible", "bucket_elements", "sgnlog", "feature_hull", "inside_hull",
-           "select_table", "learned_table", "learn_marginal", "save_net", "load_net", "changed_classes"]
+           "select_table", "learned_table", "learn_marginal", "save_net", "load_net", "changed_classes", "ACTIONS",
+           "ACTION_NAMES", "TILE_HALF"]

@@ -241,9 +241,10 @@ def test_learned_schedule_counts_exactly(tc, sched):
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_arbitrary_tables_count_exactly(tc, seed):
-    # any table, including hash choices the tables cannot hold, gives T
+    # any table, including hash choices the tables cannot hold, half-size
+    # workgroup slices and out-of-range values, gives T
     rng = np.random.default_rng(seed)
-    table = dev(rng.integers(0, 4, 2048))
+    table = dev(rng.integers(-1, 9, 2048))
     for g in (kron(12, seed=seed), gnp(500, 0.04, seed)):
         rp, col = to_gpu(g)
         for opts in (tc.Options(sched_table=table), tc.Options(sched_table=table, wave_slots=64, wg_slots=1024)):
@@ -268,6 +269,15 @@ def test_schedule_table_entry_point(tc):
     given = dev(np.full(2048, 0))
     t = tc.schedule_table(1000, 10000, tc.Options(sched_table=given, wave_slots=256)).cpu().numpy()
     assert np.all(t[ob <= 6] == 0) and np.all(t[ob > 6] == 1)
+    # half-size workgroup slices (bit 2): kept only for the workgroup hash and
+    # owners of at least half a slice (slices of 8192: classes 12 and up)
+    for v in (5, 4, 7):
+        t = tc.schedule_table(1 << 20, 1 << 24, tc.Options(sched_table=dev(np.full(2048, v)))).cpu().numpy()
+        want = np.where(ob >= 12, 5, 1) if v == 5 else np.full(2048, v & 3)
+        if v == 4:   # wavefront hash where it fits, else the workgroup hash
+            want = np.where(ob <= 9, 0, np.where(ob >= 12, 5, 1))
+        assert np.array_equal(t, want), v
+    assert np.all(tc.schedule_table(1000, 10000, tc.Options(sched_table=dev(np.full(2048, 9)))).cpu().numpy() == 2)
 
 
 def test_marginal_rows_and_counts(tc, sched):

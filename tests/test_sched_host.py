@@ -57,3 +57,10 @@ def test_changed_classes():
     table = np.array([0, 1, 1, 2, 0, 0])
     assert sched.changed_classes(heur, table) == [(0, 1), (1, 2), (3, 0)]
     assert sched.changed_classes(heur, heur) == []
+
+
+def test_actions_are_table_values():
+    # the four strategies as themselves, then the workgroup hash (1) with the
+    # half-slice bit
+    assert sched.ACTIONS.tolist() == [0, 1, 2, 3, 1 | sched.TILE_HALF]
+    assert sched.TILE_HALF == 4 and len(sched.ACTION_NAMES) == len(sched.ACTIONS)
