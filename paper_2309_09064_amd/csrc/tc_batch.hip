@@ -68,22 +68,35 @@ __global__ void k_batch_rp(int32_t g0, int32_t g1, int64_t v0, int64_t nv, int64
 
 // Group ids: the local id y of entry e of graph g becomes voff[g] - v0 + y.
 // bad (or NULL) gets bit 1 for a local id outside [0, n_g); such an id is
-// clamped into its graph.
+// clamped into its graph.  A block takes tiles of kThreads * kRun entries,
+// thread t entries t, t + kThreads, ... (each load and store of a wavefront
+// contiguous).  One thread finds the graphs of the tile's first and last
+// entries: a tile inside one graph (most entries) needs no search at all,
+// and otherwise an entry searches only that range of graphs.
 __global__ __launch_bounds__(kThreads) void k_batch_col(int32_t g0, int32_t g1, int64_t v0, int64_t e0, int64_t ne,
                                                          const int64_t *__restrict__ voff,
                                                          const int64_t *__restrict__ eoff,
                                                          const int32_t *__restrict__ col, int32_t *__restrict__ col_g,
                                                          int32_t *__restrict__ bad) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r * kRun < ne;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t a = r * kRun, b = a + kRun < ne ? a + kRun : ne;
-        int32_t g = last_le(eoff, g0, g1 - 1, e0 + a);
-        int64_t gend = eoff[g + 1] - e0;
-        int32_t base = (int32_t)(voff[g] - v0), ng = (int32_t)(voff[g + 1] - voff[g]);
-        for (int64_t e = a; e < b; ++e) {
-            while (e >= gend) {
-                ++g;
-                gend = eoff[g + 1] - e0;
+    constexpr int64_t kTile = (int64_t)kThreads * kRun;
+    __shared__ int32_t s_g[2];
+    for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < ne; t0 += (int64_t)gridDim.x * kTile) {
+        if (threadIdx.x == 0) {
+            const int64_t t1 = t0 + kTile < ne ? t0 + kTile : ne;
+            s_g[0] = last_le(eoff, g0, g1 - 1, e0 + t0);
+            s_g[1] = last_le(eoff, s_g[0], g1 - 1, e0 + t1 - 1);
+        }
+        __syncthreads();
+        const int32_t glo = s_g[0], ghi = s_g[1];
+        __syncthreads();   // s_g is rewritten for the next tile
+        const int32_t base0 = (int32_t)(voff[glo] - v0), ng0 = (int32_t)(voff[glo + 1] - voff[glo]);
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const int64_t e = t0 + (int64_t)k * kThreads + threadIdx.x;
+            if (e >= ne) break;
+            int32_t base = base0, ng = ng0;
+            if (ghi != glo) {
+                const int32_t g = last_le(eoff, glo, ghi, e0 + e);
                 base = (int32_t)(voff[g] - v0);
                 ng = (int32_t)(voff[g + 1] - voff[g]);
             }
