@@ -199,16 +199,33 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_batch(int32_t graphs, const
                     int32_t i = last_le(P, 0, f - 1, a);
                     int32_t iend = P[i + 1];
                     int32_t base = rp[F[i]] - P[i];
-                    for (int32_t e = a; e < b; ++e) {
-                        while (e >= iend) {
-                            ++i;
-                            iend = P[i + 1];
-                            base = rp[F[i]] - P[i];
+                    // the run's neighbour ids, then their levels, then the
+                    // compare-and-swaps: independent loads in flight rather
+                    // than one dependent chain per entry.  The levels are
+                    // read at workgroup scope (a line this CU holds may be
+                    // stale): a stale -1 only costs the compare-and-swap,
+                    // which decides.
+                    int32_t w[kBfsRun], lw[kBfsRun];
+#pragma unroll
+                    for (int k = 0; k < kBfsRun; ++k) {
+                        const int32_t e = a + k;
+                        w[k] = -1;
+                        if (e < b) {
+                            while (e >= iend) {
+                                ++i;
+                                iend = P[i + 1];
+                                base = rp[F[i]] - P[i];
+                            }
+                            w[k] = col[base + e];
                         }
-                        const int32_t w = col[base + e];
-                        if (level_of(lev, w) < 0 && atomicCAS(&lev[w], -1, level + 1) == -1)
-                            N[atomicAdd(&s_next, 1)] = w;
                     }
+#pragma unroll
+                    for (int k = 0; k < kBfsRun; ++k)
+                        lw[k] = w[k] >= 0 ? __hip_atomic_load(lev + w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                                          : 0;
+#pragma unroll
+                    for (int k = 0; k < kBfsRun; ++k)
+                        if (lw[k] < 0 && atomicCAS(&lev[w[k]], -1, level + 1) == -1) N[atomicAdd(&s_next, 1)] = w[k];
                 }
                 __syncthreads();   // the next frontier is complete
                 if (t == 0) s_front = s_next;
