@@ -1,30 +1,34 @@
-"""Learned schedule: profile, cost network, per-bucket strategy table.
+"""Learned schedule: measurements, cost network, per-bucket strategy table.
 
 Not part of the paper's method.  Every strategy counts exactly, so the
-schedule only decides speed.  The cycle:
+schedule only decides speed.  Two ways to train the network are here:
 
-1. ``collect_profile``: count graphs with the instrumented kernels
-   (``tc_count_profile``), which accumulate per (bucket, strategy) the
-   wavefront-ticks spent and the elements handled.  In the default
-   "context" mode the buckets are split into four random groups and each
-   group in turn runs each strategy while the other buckets keep the
-   heuristic's choice, so every (bucket, strategy) cost is measured once
-   inside a realistic mix (costs measured with one strategy forced
-   everywhere do not carry over: e.g. binary search then competes only with
-   itself for memory).
-2. ``dataset``: one training row per (bucket, strategy) with enough work:
-   features (ob, pb, kind) of the bucket, the strategy, and the target
-   log2(wavefront-ticks per element).
-3. ``CostNet.train``: full-batch Adam on the device (``tc_mlp_train``).
-4. ``CostNet.schedule``: per bucket the cheapest feasible strategy by the
-   network's prediction (``tc_mlp_schedule``), a table that
-   ``Options(sched_table=...)`` hands to ``tc_count``.
-5. ``verify_schedule``: the table's changes against the heuristic, one class
-   (heuristic strategy -> proposed strategy) at a time, are kept only where
-   the measured pass is faster with them.
+Whole-pass marginal costs (the one the stored network uses):
+
+1. ``collect_marginal``: per bucket with enough work and per alternative
+   action (a strategy, or the workgroup hash with half-size slices), the
+   change in the bucketing + intersection time when only that bucket
+   switches, measured in paired runs.
+2. ``learn_marginal``: training rows (features (ob, pb, kind), action,
+   sign(t) log2(1 + |t|) of the change per element), full-batch Adam on the
+   device (``tc_mlp_train``).
+3. ``learned_table``: per bucket the cheapest feasible action by the
+   network's prediction (``tc_mlp_forward``), kept only inside the training
+   ranges, beyond a margin and outside vetoed classes of change.
+4. ``verify_schedule``: the classes of change (heuristic strategy ->
+   proposed action) are tried one at a time on the training graphs and
+   vetoed where they do not pay; ``save_net`` / ``load_net`` store the
+   network with its ranges, margin and vetoes.
+
+Per-bucket wave-tick profiles (the earlier signal, kept and tested):
+``collect_profile`` runs the instrumented kernels (``tc_count_profile``),
+``dataset`` turns the ticks per element into rows, ``learn_schedule`` trains
+and schedules with ``tc_mlp_schedule``.  Ticks say which kernel spends less
+time on a bucket, not which one shortens the pass.
 
 Every numeric step of the network runs in the library's HIP kernels; this
-module marshals arguments and turns profile counters into training rows.
+module marshals arguments, turns measurements into training rows and
+applies the decision rule.
 """
 from __future__ import annotations
 
