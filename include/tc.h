@@ -509,9 +509,9 @@ int tc_partition(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t
 /*
  * tc_count for callers that cannot allocate: code under graph capture, tight
  * serving loops, harnesses that forbid allocation.  It allocates nothing and
- * takes no workspace: its scratch is a fixed device array of 128 MiB that
+ * takes no workspace: its scratch is a fixed device array of 256 MiB that
  * the library holds on every GPU it runs on until the process ends.  Graphs
- * whose tc_count workspace (tc_count_ws) exceeds 128 MiB -- a Kronecker
+ * whose tc_count workspace (tc_count_ws) exceeds 256 MiB -- a Kronecker
  * graph of scale 18 fits, one of scale 19 does not -- are rejected with
  * TC_ERR_TOO_LARGE
  * before any device work.  Levels, when not given, come from a BFS run by a

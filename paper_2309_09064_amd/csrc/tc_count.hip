@@ -150,18 +150,23 @@ __device__ __forceinline__ int32_t owner_slices(int32_t sx, int cap_log2) {
 // ---------------------------------------------------------------- ownership
 
 // Per owner and kind: number of owned partners and their total list length.
-// Per c0 entry (x, y) it also writes one ownership byte (bit k: x owns the
-// edge for kind k): the intersection pass reads it coalesced and gathers a
-// partner's record only where the edge is owned, half the positions.
+// Per c0 entry (x, y) and kind k it also writes the partner record the
+// intersection pass needs: y's kind-k list {offset, size} where x owns the
+// edge for kind k, {0, 0} where it does not (an owned partner's list is never
+// empty).  The pass then reads 8 coalesced bytes per position and kind
+// instead of gathering y's 16-byte vertex record, a 128-byte line per owned
+// partner: this pass gathers those records anyway.
 __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__restrict__ e0x2p,
                                                    const int32_t *__restrict__ rp0,
                                                    const int32_t *__restrict__ c0, const int32_t *__restrict__ up0,
                                                    const int32_t *__restrict__ rp1, const int4 *__restrict__ vrec,
                                                    int32_t *__restrict__ cnt, unsigned long long *__restrict__ work,
-                                                   uint8_t *__restrict__ own,
+                                                   int2 *__restrict__ prec0, int2 *__restrict__ prec1,
                                                    const int32_t *__restrict__ tlo, const int32_t *__restrict__ thi) {
     __shared__ int32_t acc_n[2][kOwnRowsMax];
     __shared__ unsigned long long acc_w[2][kOwnRowsMax];
+    constexpr int kHalf = kWave * kRun / 2;   // entries in half a wavefront's span
+    __shared__ int4 stg[kThreads / kWave][kHalf / 2];   // per wavefront: one kind's records of half its span
     const int64_t e0x2 = *e0x2p;
     constexpr int64_t kTile = (int64_t)kThreads * kRun;
     static_assert(kTile == kTileEntries, "a tile of this pass is a tile of the tile table");
@@ -176,6 +181,9 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
             }
         __syncthreads();
         const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
+        int2 r0[kRun], r1[kRun];   // the run's records, kind 0 and 1
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) r0[k] = r1[k] = make_int2(0, 0);
         if (e0 < e0x2) {
             const int64_t e1 = e0 + kRun < e0x2 ? e0 + kRun : e0x2;
             int64_t x = row_of(rp0, r_lo, r_hi, e0);
@@ -199,7 +207,6 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
             // row walk (two memory latencies per thread, not per entry)
             int32_t y[kRun];
             int4 ry[kRun];
-            uint8_t ob[kRun] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
             for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? c0[e0 + k] : 0;
 #pragma unroll
@@ -219,16 +226,46 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
                 const bool o1 = owns(s1x, ry[k].w, (int32_t)x, y[k]);
                 if (o0) { ++n0; w0 += (unsigned)ry[k].y; }
                 if (o1) { ++n1; w1 += (unsigned)ry[k].w; }
-                ob[k] = (uint8_t)((o0 ? 1 : 0) | (o1 ? 2 : 0));
+                r0[k] = o0 ? make_int2(ry[k].x, ry[k].y) : make_int2(0, 0);
+                r1[k] = o1 ? make_int2(ry[k].z, ry[k].w) : make_int2(0, 0);
             }
             flush();
-            if (e1 - e0 == kRun) {   // e0 is a multiple of 8: one 8-byte store
-                uint64_t word = 0;
+        }
+        // the records leave through LDS, half a wavefront's span at a time,
+        // so that every store instruction writes 1 KB of consecutive entries
+        // (a thread's own run is 64 bytes: its direct stores would touch a
+        // 16-byte piece of every 64 bytes per instruction)
+        {
+            const int w = (int)threadIdx.x / kWave, l = lane_id();
+            const int64_t wb = t0 + (int64_t)w * (2 * kHalf);   // first entry of the wavefront's span
+            if (wb < e0x2) {                                   // uniform in the wavefront
+                const bool full = wb + 2 * kHalf <= e0x2;
+                auto put = [&](const int2 (&r)[kRun], int2 *dst) {
 #pragma unroll
-                for (int k = 0; k < kRun; ++k) word |= (uint64_t)ob[k] << (8 * k);
-                *reinterpret_cast<uint64_t *>(own + e0) = word;
-            } else {
-                for (int64_t e = e0; e < e1; ++e) own[e] = ob[e - e0];
+                    for (int h = 0; h < 2; ++h) {
+                        if ((l >> 5) == h) {
+#pragma unroll
+                            for (int k = 0; k < kRun; k += 2)
+                                stg[w][(l & 31) * (kRun / 2) + k / 2] = make_int4(r[k].x, r[k].y, r[k + 1].x, r[k + 1].y);
+                        }
+                        wave_lds_sync();
+#pragma unroll
+                        for (int j = 0; j < kHalf / 2 / kWave; ++j) {
+                            const int q = l + kWave * j;                // 16-byte piece of the half span
+                            const int4 v = stg[w][q];
+                            const int64_t i = (int64_t)h * kHalf + 2 * q;   // entry in the wavefront's span
+                            if (full) {
+                                *reinterpret_cast<int4 *>(dst + i) = v;
+                            } else {
+                                if (wb + i < e0x2) dst[i] = make_int2(v.x, v.y);
+                                if (wb + i + 1 < e0x2) dst[i + 1] = make_int2(v.z, v.w);
+                            }
+                        }
+                        wave_lds_sync();   // the region is rewritten next
+                    }
+                };
+                put(r0, prec0 + wb);
+                put(r1, prec1 + wb);
             }
         }
         __syncthreads();
@@ -655,7 +692,7 @@ __device__ __forceinline__ uint32_t merge_count(const int32_t *a, int32_t la, co
 struct Graph {
     const int32_t *rp0, *c0, *up0, *rp1, *c1;
     const int4 *vrec;   // per vertex {rp0, |N0+|, rp1, |N1|}
-    const uint8_t *own;   // per c0 entry: bit k set when the row's vertex owns the edge for kind k
+    const int2 *prec0, *prec1;   // per c0 entry, kind 0 / 1: the partner's list {offset, size} if owned, else {0, 0}
     const int32_t *pos0, *pos1;   // per-edge counts: input entry of every c0 / c1 entry
     int wide;           // the list arrays reach 2^30 entries: element byte offsets need 64 bits
     const int32_t *s0, *s1;   // line samples of c0 / c1 (sliced searches; NULL when nothing is sliced)
@@ -699,8 +736,9 @@ __device__ __forceinline__ bool cover_counts(int32_t lw, int32_t lx, int32_t w, 
 }
 
 // Partner information for the c0 position p of owner x: is the edge owned
-// for this kind (the ownership pass's byte, read coalesced), which vertex is
-// the partner, and where is its list (one record, gathered only when owned).
+// for this kind, where is the partner's list (both from the ownership pass's
+// record, read coalesced), and which vertex is the partner (read only by the
+// modes that use it).
 __device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t p, int32_t je, int32_t &sy,
                                            int32_t &yb, int32_t &y) {
     sy = 0;
@@ -708,11 +746,10 @@ __device__ __forceinline__ bool partner_at(const Graph &g, int kind, int32_t p, 
     y = 0;
     if (p >= je) return false;
     y = g.c0[p];
-    if (!((g.own[p] >> kind) & 1)) return false;
-    const int4 r = g.vrec[y];
-    sy = kind == 0 ? r.y : r.w;
-    yb = kind == 0 ? r.x : r.z;
-    return true;
+    const int2 r = (kind == 0 ? g.prec0 : g.prec1)[p];
+    yb = r.x;
+    sy = r.y;
+    return sy > 0;
 }
 
 // Partner lists at least this long stream through stream_long.
@@ -1505,7 +1542,7 @@ unsigned grid_for(int64_t work, int threads, int64_t cap) {
 }
 
 struct CountLayout {
-    uint8_t *own;   // per c0 entry ownership bits (k_own)
+    int2 *prec0, *prec1;   // per c0 entry and kind: owned partner's list (k_own)
     int32_t *tlo, *thi;   // tile table of the N0 lists (k_own)
     int32_t *cnt;
     unsigned long long *work;
@@ -1556,7 +1593,8 @@ int32_t line_start(const int32_t *a) {
 CountLayout carve_count(Carver &c, int32_t n, int64_t nnz) {
     CountLayout L;
     const int64_t nn = n > 0 ? n : 1;
-    L.own = c.take<uint8_t>(nnz > 0 ? nnz : 1);
+    L.prec0 = c.take<int2>(nnz > 0 ? nnz : 1);
+    L.prec1 = c.take<int2>(nnz > 0 ? nnz : 1);
     L.tlo = c.take<int32_t>(tiles_of(nnz));
     L.thi = c.take<int32_t>(tiles_of(nnz));
     L.cnt = c.take<int32_t>(2 * nn);
@@ -1759,7 +1797,7 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
     if (n > 0) {
         TC_TRY(tile_table_run(n, pb.rp0, L.tlo, L.thi, s));
         hipLaunchKernelGGL(k_own, dim3(gp), dim3(kThreads), 0, s, n, pb.e0x2, pb.rp0, pb.c0, pb.up0, pb.rp1, pb.vrec, L.cnt,
-                           L.work, L.own, L.tlo, L.thi);
+                           L.work, L.prec0, L.prec1, L.tlo, L.thi);
         TC_HIP_TRY(hipGetLastError());
         const unsigned gu = grid_for(2 * (int64_t)n, kItemThreads * kUnitsPerThread, (int64_t)1 << 30);
         hipLaunchKernelGGL((k_items<0>), dim3(gu), dim3(kItemThreads), 0, s, n, pb.rp0, pb.up0, pb.rp1, L.cnt,
@@ -1785,7 +1823,7 @@ int count_run(int32_t n, int64_t nnz, const PartBufs &pb, const CountCfg &cfg, C
         // byte offsets of list elements fit 32 bits below 2^30 entries (with
         // the padding)
         const int wide = nnz + 2 * kListPad + 1024 >= (int64_t(1) << 30) ? 1 : 0;
-        Graph g{pb.rp0,       pb.c0,  pb.up0, pb.rp1, pb.c1, pb.vrec, L.own, pb.pos0, pb.pos1, wide,
+        Graph g{pb.rp0,       pb.c0,  pb.up0, pb.rp1, pb.c1, pb.vrec, L.prec0, L.prec1, pb.pos0, pb.pos1, wide,
                 sliced_lists ? L.s0 : nullptr, sliced_lists ? L.s1 : nullptr, line_start(pb.c0), line_start(pb.c1)};
         const Sink sk{cfg.gid, cfg.batch_counts, cfg.tv, cfg.sup, cfg.cover_lev};
         if (cfg.prof && batch)

@@ -11,7 +11,7 @@
 namespace tc {
 namespace {
 
-constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr size_t kScratchBytes = size_t(256) << 20;
 
 // The scratch of every call on this GPU.  Host code never passes this name
 // to a kernel (on the host it is only a stand-in for the symbol): it uses

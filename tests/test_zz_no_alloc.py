@@ -74,7 +74,7 @@ def test_given_levels_and_forced_strategy(tc):
     assert noalloc(tc, g2, rp2, col2) == reference(tc, rp2, col2)
 
 
-SCRATCH = 128 << 20
+SCRATCH = 256 << 20
 
 
 def count_ws(tc, g):
