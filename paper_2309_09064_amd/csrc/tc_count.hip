@@ -456,83 +456,145 @@ __global__ __launch_bounds__(1024) void k_bucket_order(const int32_t *__restrict
 
 // ---------------------------------------------------------------- probes
 
-// LDS hash table of 2-slot buckets with linear probing over buckets.  A
-// key's home bucket is a multiplicative hash of the id; a lookup reads the
-// bucket (one 8-byte read) and walks on only while the bucket is full
-// without the key.  The bucket width is a measured balance: 16-byte buckets
-// saturate the LDS address unit (a wavefront's 64 random reads fall into 8
-// bank groups), while single slots send about one key in eight past its home
-// slot at load 1/8 against about one in forty here.
-// Tables are sized so at most half the slots are used (1/32 where LDS
-// allows).
+// LDS hash table of 2-slot buckets.  A key's home bucket is a
+// multiplicative hash of the id; a lookup reads the bucket (one 8-byte read)
+// and walks on only while the bucket is full without the key.  The bucket
+// width is a measured balance: 16-byte buckets saturate the LDS address unit
+// (a wavefront's 64 random reads fall into 8 bank groups), while single
+// slots send about one key in eight past its home slot at load 1/8 against
+// about one in forty here.
+// Tables loaded above 1/16 take two candidate buckets per key (balanced
+// allocation): a key goes to the emptier of the two, and only when both are
+// full to linear probing from the first.  A lookup reads both and walks only
+// when both are full without the key: at load 1/4 one lookup in 800 instead
+// of one in ten.  Every window of lookups pays the slowest lane's walks, so
+// this trades a second read per key for the walks; below 1/16 the walks are
+// rare enough that one read is cheaper.
+// Tables are sized so at most half the slots are used (a quarter under the
+// heuristic schedule, 1/32 where LDS allows).
 struct HashTab {
     int32_t *tab;
     uint32_t mask;    // buckets - 1 (2 slots a bucket)
     int off, bits;    // home bucket: bits [off, off + bits) of the 24-bit product, bits = log2(buckets)
+    int two;          // two candidate buckets per key
     uint32_t *cnt;    // per-vertex / per-edge counts: a hit counter per slot, else unused
 };
 
-__device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots, uint32_t *cnt = nullptr) {
+constexpr int kTwoChoiceLoad = 16;   // two candidates above a load of 1 / kTwoChoiceLoad
+
+// keys: how many keys the table will hold
+__device__ __forceinline__ HashTab make_tab(int32_t *tab, int lg_slots, int32_t keys, uint32_t *cnt = nullptr) {
     HashTab t;
     t.tab = tab;
     t.cnt = cnt;
     t.mask = (1u << (lg_slots - 1)) - 1;
     t.bits = lg_slots - 1;
     t.off = 24 - t.bits;
+    t.two = __builtin_amdgcn_readfirstlane((int64_t)keys * kTwoChoiceLoad > ((int64_t)1 << lg_slots) ? 1 : 0);
     return t;
 }
 
-// Fibonacci hashing on a 2^24 ring: the top log2(buckets) bits of
-// (v * floor(2^24 / golden ratio)) mod 2^24.  The 24-bit multiply and the
-// field extract both issue at full rate, where a 32-bit multiply takes four
-// passes; ids of 2^24 and above share the hash of their low 24 bits, which
-// only lengthens probe sequences.
-__device__ __forceinline__ uint32_t home_slot(const HashTab &t, int32_t v) {
-    const uint32_t p = (uint32_t)__umul24((uint32_t)v, 0x9E3779u);
+// Fibonacci hashing on a 2^24 ring: the product
+// (v * floor(2^24 / golden ratio)) mod 2^24; the home bucket is its top
+// log2(buckets) bits, the second candidate its low ones.  The 24-bit
+// multiply, the field extract and the mask all issue at full rate, where a
+// 32-bit multiply takes four passes; ids of 2^24 and above share the hash of
+// their low 24 bits, which only lengthens probe sequences.
+__device__ __forceinline__ uint32_t hash_product(int32_t v) { return (uint32_t)__umul24((uint32_t)v, 0x9E3779u); }
+__device__ __forceinline__ uint32_t home_of(const HashTab &t, uint32_t p) {
     return __builtin_amdgcn_ubfe(p, (uint32_t)t.off, (uint32_t)t.bits);
+}
+__device__ __forceinline__ uint32_t home_slot(const HashTab &t, int32_t v) { return home_of(t, hash_product(v)); }
+
+__device__ __forceinline__ int bucket_used(const int32_t *tab, uint32_t b) {
+    const uint64_t w = __hip_atomic_load(reinterpret_cast<const uint64_t *>(tab + 2 * b), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return ((int32_t)(uint32_t)w != kEmpty ? 1 : 0) + ((int32_t)(uint32_t)(w >> 32) != kEmpty ? 1 : 0);
 }
 
 // Slots of a bucket fill in order: a bucket whose second slot is empty ends
-// every probe sequence through it.
+// every probe sequence through it.  With two candidates the emptier one is
+// tried first (the counts are a hint: the compare-and-swaps decide), then
+// the other; a key that finds both full probes on from the home bucket.
 __device__ __forceinline__ void hash_insert(const HashTab &t, int32_t v) {
-    uint32_t b = home_slot(t, v);
-    for (;;) {
+    const uint32_t p = hash_product(v);
+    uint32_t b = home_of(t, p);
+    if (t.two) {
+        const uint32_t c = p & t.mask;
+        const bool swap = bucket_used(t.tab, c) < bucket_used(t.tab, b);
+        const uint32_t f = swap ? c : b, g = swap ? b : c;
+        if (atomicCAS(&t.tab[2 * f], kEmpty, v) == kEmpty) return;
+        if (atomicCAS(&t.tab[2 * f + 1], kEmpty, v) == kEmpty) return;
+        if (atomicCAS(&t.tab[2 * g], kEmpty, v) == kEmpty) return;
+        if (atomicCAS(&t.tab[2 * g + 1], kEmpty, v) == kEmpty) return;
+    } else {
         if (atomicCAS(&t.tab[2 * b], kEmpty, v) == kEmpty) return;
         if (atomicCAS(&t.tab[2 * b + 1], kEmpty, v) == kEmpty) return;
+    }
+    for (;;) {
         b = (b + 1) & t.mask;
+        if (atomicCAS(&t.tab[2 * b], kEmpty, v) == kEmpty) return;
+        if (atomicCAS(&t.tab[2 * b + 1], kEmpty, v) == kEmpty) return;
     }
 }
 
 // Membership of up to kPer keys: ids >= 0, or kNoKey for window padding,
 // which matches no slot (never kEmpty, which would match empty ones).  Every
-// key's home
-// bucket is read once, unconditionally and interleaved; a key whose home
-// bucket is full without it (rare at the tables' load) then follows its
-// probe sequence, one pending key at a time per lane.  Keeping the common
-// case free of per-key predication is what bounds the instruction count:
-// the slowest of a wavefront's keys no longer sets the work of all of them.
+// key's candidate buckets are read once, unconditionally and interleaved; a
+// key whose candidates are all full without it (rare at the tables' load)
+// then follows its probe sequence from the home bucket, one pending key at a
+// time per lane.  Keeping the common case free of per-key predication is
+// what bounds the instruction count: the slowest of a wavefront's keys no
+// longer sets the work of all of them.
 // With kMask the result is the mask of keys found (bit u for key u) instead
 // of their number; with kSlots as well, slot[u] receives the slot of each key
 // found (per-vertex / per-edge counts credit the slot's counter).
 template <int kPer, bool kMask = false, bool kSlots = false>
 __device__ __forceinline__ uint32_t hash_probe(const HashTab &t, const int32_t (&v)[kPer], int32_t *slot) {
-    uint32_t b[kPer];
-    int2 q[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) b[u] = home_slot(t, v[u]);
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) q[u] = *reinterpret_cast<const int2 *>(&t.tab[2 * b[u]]);
     uint32_t hits = 0;
-    uint32_t pend = 0;   // keys whose home bucket is full (second slot used: keys are >= 0) without them
+    uint32_t pend = 0;   // keys whose candidates are full (second slot used: keys are >= 0) without them
+    if (t.two) {
+        uint32_t b[kPer], c[kPer];
+        int2 q[kPer], r[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int32_t x = v[u];
-        const bool m0 = q[u].x == x, m1 = q[u].y == x;
-        if constexpr (kMask) hits |= (m0 | m1) ? (1u << u) : 0u;
-        else hits += (m0 | m1) ? 1u : 0u;
-        if constexpr (kSlots) slot[u] = (int32_t)(2 * b[u] + (m0 ? 0 : 1));
-        // padding keys walk on too, rarely, and never match
-        pend |= (!(m0 | m1) & (q[u].y >= 0)) ? (1u << u) : 0u;
+        for (int u = 0; u < kPer; ++u) {
+            const uint32_t p = hash_product(v[u]);
+            b[u] = home_of(t, p);
+            c[u] = p & t.mask;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            q[u] = *reinterpret_cast<const int2 *>(&t.tab[2 * b[u]]);
+            r[u] = *reinterpret_cast<const int2 *>(&t.tab[2 * c[u]]);
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int32_t x = v[u];
+            const bool m0 = q[u].x == x, m1 = q[u].y == x, m2 = r[u].x == x, m3 = r[u].y == x;
+            const bool m = m0 | m1 | m2 | m3;
+            if constexpr (kMask) hits |= m ? (1u << u) : 0u;
+            else hits += m ? 1u : 0u;
+            if constexpr (kSlots)
+                slot[u] = (int32_t)(m0 | m1 ? 2 * b[u] + (m0 ? 0 : 1) : 2 * c[u] + (m2 ? 0 : 1));
+            pend |= (!m & (q[u].y >= 0) & (r[u].y >= 0)) ? (1u << u) : 0u;
+        }
+    } else {
+        uint32_t b[kPer];
+        int2 q[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) b[u] = home_slot(t, v[u]);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) q[u] = *reinterpret_cast<const int2 *>(&t.tab[2 * b[u]]);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int32_t x = v[u];
+            const bool m0 = q[u].x == x, m1 = q[u].y == x;
+            if constexpr (kMask) hits |= (m0 | m1) ? (1u << u) : 0u;
+            else hits += (m0 | m1) ? 1u : 0u;
+            if constexpr (kSlots) slot[u] = (int32_t)(2 * b[u] + (m0 ? 0 : 1));
+            // padding keys walk on too, rarely, and never match
+            pend |= (!(m0 | m1) & (q[u].y >= 0)) ? (1u << u) : 0u;
+        }
     }
     if (__ballot(pend != 0) == 0) return hits;
     while (pend) {
@@ -1340,7 +1402,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const int32_t lo = sliced ? a[a_lo] : 0;
         const int32_t hi = sliced && a_hi < sx ? a[a_hi] : INT32_MAX;
         const int lg = table_log2(a_hi - a_lo, wg_log2);
-        const HashTab ht = make_tab(lds, lg, kSlotCnt ? slot_cnt : nullptr);
+        const HashTab ht = make_tab(lds, lg, a_hi - a_lo, kSlotCnt ? slot_cnt : nullptr);
         if (threadIdx.x == 0) s_chunk = 0;
         for (int i = threadIdx.x; i < (1 << lg) / 4; i += kIsectThreads)
             reinterpret_cast<int4 *>(lds)[i] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
@@ -1407,7 +1469,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         uint32_t h = 0;
         if (strat == TC_STRAT_WAVE_HASH) {
             const int lg = table_log2(sx, wave_log2);
-            const HashTab ht = make_tab(tab, lg, kSlotCnt ? reinterpret_cast<uint32_t *>(tab + table_ints) : nullptr);
+            const HashTab ht = make_tab(tab, lg, sx, kSlotCnt ? reinterpret_cast<uint32_t *>(tab + table_ints) : nullptr);
             for (int i = l; i < (1 << lg) / 4; i += kWave)
                 reinterpret_cast<int4 *>(tab)[i] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
             wave_lds_sync();
