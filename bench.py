@@ -483,6 +483,12 @@ def secondary_legs(tc, torch, args):
                            levels=zero)
     assert all(x.T == T for x in fres), "forward-hashed count differs"
     k20["forward_hashed_same_kernels"] = {"value": m / fs, "ms_per_step": fs * 1e3, "phase_ms": phase_means(fres)}
+    # Algorithm 4 with the horizontal edges oriented by id (u < v as printed)
+    # instead of by (degree, id) rank
+    os_, ores = timed_steps(tc.Counter(n, col.numel(), tc.Options(timing=True, orientation=tc.TC_ORIENT_ID)), rp,
+                            col, args.steps, args.warmup)
+    assert all((x.T, x.T0, x.T1) == (T, r.T0, r.T1) for x in ores), "id-oriented count differs"
+    k20["id_orientation"] = {"value": m / os_, "ms_per_step": os_ * 1e3, "phase_ms": phase_means(ores)}
     for name, fn in (("vertex_triangles", tc.vertex_triangles), ("edge_support", tc.edge_support)):
         x_s, (_, rx) = time_calls(lambda: fn(rp, col), args.steps, args.warmup)
         assert rx.T == T, f"{name} count differs"
@@ -499,7 +505,8 @@ def secondary_legs(tc, torch, args):
                    "k_percent": round(100.0 * rbd.e0 / m, 2)},
         "ced": {"ms_per_step": (rl_s + ced_s) * 1e3, "value": m / (rl_s + ced_s), "count_ms": ced_s * 1e3}}
     out["kronecker20"] = k20
-    log(f"kronecker 20: {st * 1e3:.3f} ms/step; forward-hashed {fs * 1e3:.3f}; cover edge {ce_s * 1e3:.3f}")
+    log(f"kronecker 20: {st * 1e3:.3f} ms/step; id orientation {os_ * 1e3:.3f}; forward-hashed {fs * 1e3:.3f}; "
+        f"cover edge {ce_s * 1e3:.3f}")
     del rp, col, rp2, col2, zero
     torch.cuda.empty_cache()
     out["batch4096"] = batch_leg(tc, torch, args)

@@ -80,6 +80,18 @@ enum tc_strategy {
     TC_NUM_STRATEGIES = 4
 };
 
+/* Orientation of the horizontal edges for the forward count inside G0
+ * (Algorithm 2 as Algorithm 4 applies it): which endpoint's N0+ list holds
+ * an edge.  T, T0 and T1 do not depend on it; the lengths of the N0+ lists,
+ * and so the kind-0 work, do. */
+enum tc_orientation {
+    TC_ORIENT_RANK = 0,       /* y in N0+(x) when rank(y) > rank(x),
+                                 rank(v) = (deg(v), v) lexicographic: the
+                                 degree-ordered forward algorithm (default)  */
+    TC_ORIENT_ID = 1          /* y in N0+(x) when y > x, ids as stored: the
+                                 u < v form of Algorithms 2 and 4            */
+};
+
 enum tc_schedule {
     TC_SCHED_HEURISTIC = 0,   /* owner-list-size thresholds                  */
     TC_SCHED_TABLE = 1        /* one strategy per bucket from
@@ -145,6 +157,7 @@ typedef struct tc_options {
                                  in one table (power of 2, 64..wg_slots/2);
                                  longer lists are cut into value-range slices
                                  of at most this many; 0 = wg_slots / 4      */
+    int32_t orientation;      /* tc_orientation of the N0+ lists; 0 = rank   */
 } tc_options;
 
 /* Per-call statistics (host struct, all optional). */
@@ -488,11 +501,13 @@ int tc_mlp_schedule(const float *d_params, int32_t hidden, int32_t k, const tc_o
  * The two CSRs of the partition (Algorithm 4, partition loop), for tests and
  * for callers that reuse them.  d_levels: int32[n] device, levels that differ
  * by at most one on every edge (BFS levels do; TC_VALIDATE on tc_count checks
- * it).  Outputs (device, caller-owned):
+ * it).  orientation: a tc_orientation (else TC_ERR_ARG).  Outputs (device,
+ * caller-owned):
  *   d_rp0  int32[n+1], d_c0 int32[nnz]: N0(x) per row = the neighbours of
- *          equal level with rank above x, ascending, then those with rank
- *          below x, ascending; rank(y) = (deg(y), y) lexicographic.
- *   d_up0  int32[n]: size of the rank-above part of each N0 row.
+ *          equal level above x in the orientation (TC_ORIENT_RANK: rank
+ *          above, rank(y) = (deg(y), y) lexicographic; TC_ORIENT_ID: id
+ *          above), ascending, then the rest, ascending.
+ *   d_up0  int32[n]: size of the upper part (N0+) of each N0 row.
  *   d_rp1  int32[n+1], d_c1 int32[nnz]: N1(x) = neighbours of other level,
  *          ascending.
  *   h_e0   host: |E0| (undirected).
@@ -500,7 +515,7 @@ int tc_mlp_schedule(const float *d_params, int32_t hidden, int32_t k, const tc_o
  */
 int tc_partition_ws(int32_t n, int64_t nnz, size_t *h_ws_bytes);
 int tc_partition(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
-                 const int32_t *d_levels, int32_t *d_rp0, int32_t *d_c0, int32_t *d_up0,
+                 const int32_t *d_levels, int32_t orientation, int32_t *d_rp0, int32_t *d_c0, int32_t *d_up0,
                  int32_t *d_rp1, int32_t *d_c1, int64_t *h_e0, void *ws, size_t ws_bytes,
                  void *stream);
 

@@ -10,7 +10,7 @@ Counting" (arXiv 2309.09064):
 
 * :func:`build_csr`          simple undirected CSR from tuples (Introduction)
 * :func:`bfs_levels`         BFS from each unvisited vertex in id order (Alg. 4)
-* :func:`partition`          E0/E1 split, N0 rank-split rows (Alg. 4)
+* :func:`partition`          E0/E1 split, N0 rows split by rank or by id (Alg. 4)
 * :func:`alg4`               T0 = triangles inside G0, T1 = triangles with one
                              horizontal edge (the two sums of Alg. 4), by merges
 * :func:`count_emd`          direction-oriented sorted-merge edge iterator
@@ -63,7 +63,7 @@ def _load():
         lib.orc_build_csr.restype = ctypes.c_int64
         lib.orc_bfs_levels.argtypes = [ctypes.c_int64, _i64, _i32, _i32]
         lib.orc_bfs_levels.restype = ctypes.c_int64
-        lib.orc_partition.argtypes = [ctypes.c_int64, _i64, _i32, _i32, _i64, _i32, _i32, _i64, _i32]
+        lib.orc_partition.argtypes = [ctypes.c_int64, _i64, _i32, _i32, ctypes.c_int32, _i64, _i32, _i32, _i64, _i32]
         lib.orc_partition.restype = None
         lib.orc_alg4.argtypes = [ctypes.c_int64, _i64, _i32, _i32, ctypes.POINTER(ctypes.c_uint64),
                                  ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
@@ -149,7 +149,9 @@ def _col_or_dummy(g: CSR):
     return g.col if g.nnz else np.zeros(1, np.int32)
 
 
-def partition(g: CSR, level: np.ndarray) -> Partition:
+def partition(g: CSR, level: np.ndarray, by_id: bool = False) -> Partition:
+    """E0/E1 split of Alg. 4; each N0 row holds its upper part first: the
+    neighbours of higher (degree, id) rank, or of higher id with ``by_id``."""
     lev = np.ascontiguousarray(level, dtype=np.int32)
     rp0 = np.zeros(g.n + 1, np.int64)
     rp1 = np.zeros(g.n + 1, np.int64)
@@ -157,7 +159,7 @@ def partition(g: CSR, level: np.ndarray) -> Partition:
     c1 = np.empty(max(g.nnz, 1), np.int32)
     up0 = np.zeros(max(g.n, 1), np.int32)
     _load().orc_partition(g.n, g.row_ptr, _col_or_dummy(g), lev if g.n else np.zeros(1, np.int32),
-                          rp0, c0, up0, rp1, c1)
+                          1 if by_id else 0, rp0, c0, up0, rp1, c1)
     return Partition(rp0, c0[:rp0[-1]].copy(), up0[:g.n].copy(), rp1, c1[:rp1[-1]].copy())
 
 
@@ -264,7 +266,7 @@ def _floor_log2(v) -> np.ndarray:
     return np.array([max(int(x), 1).bit_length() - 1 for x in np.atleast_1d(v)], dtype=np.int64)
 
 
-def bucket_work(g: CSR, level: np.ndarray):
+def bucket_work(g: CSR, level: np.ndarray, by_id: bool = False):
     """Units and elements per schedule bucket (the library's work split, not
     the paper's): for kind 0 the lists are N0+ (sizes |N0+|), for kind 1 the
     N1 lists.  Each horizontal edge {x, y} belongs, per kind, to the endpoint
@@ -272,9 +274,9 @@ def bucket_work(g: CSR, level: np.ndarray):
     Owner x of kind k forms one unit with cnt owned partners and work = the
     sum of their list sizes; its bucket is (k * 32 + ob) * 32 + pb with
     ob = floor(log2 |list(x)|), pb = floor(log2 (work // cnt)), both capped at
-    31; the unit adds work + |list(x)| elements.  Returns int64 arrays
-    units[2048], elements[2048]."""
-    p = partition(g, level)
+    31; the unit adds work + |list(x)| elements.  ``by_id``: N0+ lists of the
+    id orientation.  Returns int64 arrays units[2048], elements[2048]."""
+    p = partition(g, level, by_id)
     n = g.n
     sizes = [p.up0.astype(np.int64), np.diff(p.rp1).astype(np.int64)]
     x = np.repeat(np.arange(n, dtype=np.int64), np.diff(p.rp0))   # every directed horizontal edge (x, y)

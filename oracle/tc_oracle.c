@@ -110,18 +110,20 @@ int64_t orc_bfs_levels(int64_t n, const int64_t *row_ptr, const int32_t *col, in
  *            rank(y) > rank(x) first, then the part with rank(y) < rank(x);
  *            each part ascending by id.                            (rp0, c0)
  *   up0[x] = |{y in N0(x) : rank(y) > rank(x)}|
- * rank(x) = (deg(x), x) compared lexicographically, deg = full degree in G.
- * The rank orientation is the forward algorithm's vertex order (paper,
- * Related work: forward with degree ordering); the paper leaves the tie-break
- * open, ids break ties here.
+ * With by_id == 0, rank(x) = (deg(x), x) compared lexicographically, deg =
+ * full degree in G: the forward algorithm's vertex order (paper, Related
+ * work: forward with degree ordering; the paper leaves the tie-break open,
+ * ids break ties here).  With by_id != 0, rank(x) = x: the u < v of
+ * Algorithms 2 and 4 as printed.
  */
-static int rank_above(const int64_t *rp, int64_t y, int64_t x)
+static int rank_above(const int64_t *rp, int64_t y, int64_t x, int by_id)
 {
+    if (by_id) return y > x;
     int64_t dy = rp[y + 1] - rp[y], dx = rp[x + 1] - rp[x];
     return dy > dx || (dy == dx && y > x);
 }
 
-void orc_partition(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *level,
+void orc_partition(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *level, int32_t by_id,
                    int64_t *rp0, int32_t *c0, int32_t *up0, int64_t *rp1, int32_t *c1)
 {
     rp0[0] = 0;
@@ -131,11 +133,11 @@ void orc_partition(int64_t n, const int64_t *row_ptr, const int32_t *col, const 
         int32_t up = 0;
         for (int64_t j = row_ptr[x]; j < row_ptr[x + 1]; ++j) {      /* upper part of N0 */
             int32_t y = col[j];
-            if (level[y] == level[x] && rank_above(row_ptr, y, x)) { c0[p0++] = y; ++up; }
+            if (level[y] == level[x] && rank_above(row_ptr, y, x, by_id)) { c0[p0++] = y; ++up; }
         }
         for (int64_t j = row_ptr[x]; j < row_ptr[x + 1]; ++j) {      /* lower part of N0 */
             int32_t y = col[j];
-            if (level[y] == level[x] && !rank_above(row_ptr, y, x)) c0[p0++] = y;
+            if (level[y] == level[x] && !rank_above(row_ptr, y, x, by_id)) c0[p0++] = y;
         }
         for (int64_t j = row_ptr[x]; j < row_ptr[x + 1]; ++j) {      /* N1 */
             int32_t y = col[j];

@@ -13,9 +13,9 @@ from dataclasses import dataclass, field
 import torch
 
 from . import _capi
-from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_BUCKETS, TC_NUM_STRATEGIES, TC_SCHED_HEURISTIC,
-                    TC_SCHED_TABLE, TC_STRAT_AUTO, TC_STRAT_BSEARCH, TC_STRAT_MERGE, TC_STRAT_WAVE_HASH,
-                    TC_STRAT_WG_HASH, TC_TIMING, TC_VALIDATE)
+from ._capi import (STRATEGY_NAMES, TC_COUNT_ERROR, TC_NUM_BUCKETS, TC_NUM_STRATEGIES, TC_ORIENT_ID,
+                    TC_ORIENT_RANK, TC_SCHED_HEURISTIC, TC_SCHED_TABLE, TC_STRAT_AUTO, TC_STRAT_BSEARCH,
+                    TC_STRAT_MERGE, TC_STRAT_WAVE_HASH, TC_STRAT_WG_HASH, TC_TIMING, TC_VALIDATE)
 
 __all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count", "count_profile", "workspace",
            "count_batched", "pack_csr", "Batch", "BatchPlan", "batch_workspace_bytes", "bfs_levels_batched", "schedule_table", "vertex_triangles", "edge_support",
@@ -23,7 +23,7 @@ __all__ = ["TCError", "Options", "build_csr", "bfs_levels", "partition", "count"
            "Counter", "CountResult", "new_profile",
            "STRATEGY_NAMES", "TC_STRAT_AUTO", "TC_STRAT_WAVE_HASH", "TC_STRAT_WG_HASH", "TC_STRAT_BSEARCH",
            "TC_STRAT_MERGE", "TC_SCHED_HEURISTIC", "TC_SCHED_TABLE", "TC_NUM_BUCKETS", "TC_NUM_STRATEGIES",
-           "TC_VALIDATE", "TC_TIMING"]
+           "TC_VALIDATE", "TC_TIMING", "TC_ORIENT_RANK", "TC_ORIENT_ID"]
 
 
 class TCError(RuntimeError):
@@ -75,6 +75,7 @@ class Options:
     sched_table: torch.Tensor | None = None   # int32[TC_NUM_BUCKETS] on the device: selects TC_SCHED_TABLE
     batch_group_entries: int = 0        # batched counts: vertices / entries per internal group; 0 = int32 limit
     wg_slice_max: int = 0               # longest owner slice of a workgroup table; 0 = wg_slots / 4
+    orientation: int = TC_ORIENT_RANK   # N0+ lists by (degree, id) rank, or by id (TC_ORIENT_ID)
 
     def to_c(self):
         o = _capi.tc_options()
@@ -96,6 +97,7 @@ class Options:
         o.merge_max_owner = self.merge_max_owner
         o.batch_group_entries = self.batch_group_entries
         o.wg_slice_max = self.wg_slice_max
+        o.orientation = self.orientation
         return o
 
 
@@ -151,8 +153,10 @@ def bfs_levels(row_ptr: torch.Tensor, col: torch.Tensor, stream=None):
     return lev[:n], nlev.value
 
 
-def partition(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor, stream=None):
-    """The E0/E1 partition CSRs as a dict of device tensors."""
+def partition(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor, stream=None,
+              orientation: int = TC_ORIENT_RANK):
+    """The E0/E1 partition CSRs as a dict of device tensors (N0+ lists in the
+    given orientation)."""
     for t, nm in ((row_ptr, "row_ptr"), (col, "col"), (levels, "levels")):
         _require_i32_cuda(t, nm)
     lib = _capi.load()
@@ -170,9 +174,9 @@ def partition(row_ptr: torch.Tensor, col: torch.Tensor, levels: torch.Tensor, st
         "c1": torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
     }
     e0 = ctypes.c_int64()
-    _check(lib.tc_partition(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(levels), _ptr(out["rp0"]), _ptr(out["c0"]),
-                            _ptr(out["up0"]), _ptr(out["rp1"]), _ptr(out["c1"]), ctypes.byref(e0), _ptr(ws),
-                            need.value, _stream(stream)), "tc_partition")
+    _check(lib.tc_partition(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(levels), orientation, _ptr(out["rp0"]),
+                            _ptr(out["c0"]), _ptr(out["up0"]), _ptr(out["rp1"]), _ptr(out["c1"]), ctypes.byref(e0),
+                            _ptr(ws), need.value, _stream(stream)), "tc_partition")
     out["e0"] = e0.value
     out["up0"] = out["up0"][:n]
     return out

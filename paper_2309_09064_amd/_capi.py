@@ -33,6 +33,8 @@ STRATEGY_NAMES = ["wave_hash", "wg_hash", "bsearch", "merge"]
 
 TC_SCHED_HEURISTIC = 0
 TC_SCHED_TABLE = 1
+TC_ORIENT_RANK = 0
+TC_ORIENT_ID = 1
 TC_NUM_BUCKETS = 2048
 TC_MLP_IN = 3
 
@@ -54,6 +56,7 @@ class tc_options(ctypes.Structure):
         ("sched_table", ctypes.c_void_p),
         ("batch_group_entries", ctypes.c_int64),
         ("wg_slice_max", ctypes.c_int32),
+        ("orientation", ctypes.c_int32),
     ]
 
 
@@ -129,8 +132,8 @@ _SIGNATURES = {
                                     _f32, _f32, _vp, _vp, _sz, _vp]),
     "tc_mlp_schedule": (ctypes.c_int, [_vp, _i32, _i32, _P(tc_options), _vp, _vp, _vp]),
     "tc_partition_ws": (ctypes.c_int, [_i32, _i64, _P(_sz)]),
-    "tc_partition": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _P(_i64), _vp, _sz,
-                                    _vp]),
+    "tc_partition": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _P(_i64), _vp,
+                                    _sz, _vp]),
 }
 
 

@@ -405,8 +405,9 @@ int enqueue_batch(int32_t graphs, const BatchShape &sh, const BatchLayout &L, co
         if (check && d_levels) {
             TC_TRY(validate_device((int32_t)nv, ne, L.rp_g, L.col_g, L.lev, L.flag + 2, s));
         }
-        TC_TRY(partition_run((int32_t)nv, ne, L.rp_g, L.col_g, L.lev, L.plan.pb, L.plan.scratch,
-                             L.plan.scratch_bytes, s));
+        PartBufs pb = L.plan.pb;
+        pb.by_id = base_cfg.orientation == TC_ORIENT_ID ? 1 : 0;
+        TC_TRY(partition_run((int32_t)nv, ne, L.rp_g, L.col_g, L.lev, pb, L.plan.scratch, L.plan.scratch_bytes, s));
         CountCfg cfg = base_cfg;
         cfg.gid = L.gid;
         cfg.batch_counts = reinterpret_cast<unsigned long long *>(d_counts + G.g0);

@@ -168,6 +168,8 @@ int make_cfg(const tc_options *opt, CountCfg *cfg, int *flags) {
                                   opt->wg_slice_max > c.wg_slots / 2))
             return TC_ERR_ARG;
         c.wg_slice_max = opt->wg_slice_max;
+        if (opt->orientation != TC_ORIENT_RANK && opt->orientation != TC_ORIENT_ID) return TC_ERR_ARG;
+        c.orientation = opt->orientation;
         if (opt->flags & ~(TC_VALIDATE | TC_TIMING)) return TC_ERR_ARG;
         *flags = opt->flags;
     }
@@ -331,10 +333,11 @@ int tc_partition_ws(int32_t n, int64_t nnz, size_t *h_ws_bytes) {
 }
 
 int tc_partition(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx, const int32_t *d_levels,
-                 int32_t *d_rp0, int32_t *d_c0, int32_t *d_up0, int32_t *d_rp1, int32_t *d_c1, int64_t *h_e0,
-                 void *ws, size_t ws_bytes, void *stream) {
+                 int32_t orientation, int32_t *d_rp0, int32_t *d_c0, int32_t *d_up0, int32_t *d_rp1, int32_t *d_c1,
+                 int64_t *h_e0, void *ws, size_t ws_bytes, void *stream) {
     int rc = check_graph_args(n, nnz, d_row_ptr, d_col_idx);
     if (rc != TC_OK) return fail(rc);
+    if (orientation != TC_ORIENT_RANK && orientation != TC_ORIENT_ID) return fail(TC_ERR_ARG);
     if (!d_rp0 || !d_rp1 || !h_e0 || (n > 0 && (!d_levels || !d_up0)) || (nnz > 0 && (!d_c0 || !d_c1)))
         return fail(TC_ERR_ARG);
     size_t need = 0;
@@ -363,6 +366,7 @@ int tc_partition(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t
     pb.d0 = c.take<int32_t>(nn);
     pb.rpu = c.take<int32_t>(nn + 1);
     pb.e0x2 = c.take<int64_t>(1);
+    pb.by_id = orientation == TC_ORIENT_ID ? 1 : 0;
     void *scratch = c.take<char>(partition_ws_bytes(n, nnz));
     rc = partition_run(n, nnz, d_row_ptr, d_col_idx, d_levels, pb, scratch, partition_ws_bytes(n, nnz), s);
     if (rc != TC_OK) return fail(rc);
@@ -451,6 +455,7 @@ static uint64_t count_impl(int32_t n, int64_t nnz, const int32_t *d_row_ptr, con
         lev = P.levels;
     }
     if (timing && hipEventRecord(ev.e[1], s) != hipSuccess) return fail_ev(TC_ERR_HIP);
+    P.pb.by_id = cfg.orientation == TC_ORIENT_ID ? 1 : 0;
     rc = partition_run(n, nnz, d_row_ptr, d_col_idx, lev, P.pb, P.scratch, P.scratch_bytes, s);
     if (rc != TC_OK) return fail_ev(rc);
     PartBufs pb = P.pb;

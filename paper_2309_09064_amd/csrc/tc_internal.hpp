@@ -213,6 +213,7 @@ struct PartBufs {
     int64_t *e0x2;                        // device scalar: 2|E0|
     int4 *vrec = nullptr;                 // n: {rp0, |N0+|, rp1, |N1|} per vertex, or NULL
     int32_t *pos0 = nullptr, *pos1 = nullptr;   // input entry of every c0 / c1 entry (nnz each), or NULL
+    int by_id = 0;                        // N0+ by id (TC_ORIENT_ID) instead of rank
 };
 size_t partition_ws_bytes(int32_t n, int64_t nnz);
 // Turns a partition into the full-row view the cover-edge count runs on
@@ -244,6 +245,7 @@ struct CountCfg {
     int wave_max_owner = 0;
     int wg_slice_max = 0;   // longest owner slice of a workgroup table; 0: wg_slots / 4
     int merge_max_owner = 0;
+    int orientation = TC_ORIENT_RANK;   // of the N0+ lists (the partition reads it)
     const int32_t *table = nullptr;   // device per-bucket strategies (schedule)
     unsigned long long *prof = nullptr;   // device per-(bucket, strategy) profile, or NULL
     const int32_t *gid = nullptr;         // batch: graph of every vertex, or NULL

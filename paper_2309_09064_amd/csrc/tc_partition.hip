@@ -5,7 +5,8 @@
 //             the equal-level neighbours ],   rank(y) = (deg(y), y);
 //   N1(x) = neighbours y with L(y) != L(x).
 // The rank-above part N0+(x) is the forward algorithm's oriented list
-// (Algorithm 2 with degree ordering).
+// (Algorithm 2 with degree ordering); with the id orientation rank(y) = y,
+// Algorithm 2's own u < v.
 //
 // Two coalesced passes over the CSR entries.  Pass 1 marks each entry
 // (horizontal, rank-above) into a byte, counts per row with atomics and per
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
                                                          const int32_t *__restrict__ thi,
                                                          uint8_t *__restrict__ flags, int32_t *__restrict__ d0,
                                                          int32_t *__restrict__ up0, int32_t *__restrict__ bh,
-                                                         int32_t *__restrict__ bu) {
+                                                         int32_t *__restrict__ bu, int by_id) {
     __shared__ int32_t sh[kWaves], su[kWaves];
     __shared__ int32_t acc_h[kTileRowsMax], acc_u[kTileRowsMax];
     __shared__ int32_t s_rp[kTileRowsMax + 1];
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
                     dx = (int32_t)(xe - xb);
                 }
                 const bool hor = (iy[k] & 3u) == lx;
-                const bool up = hor && rank_above_rec(iy[k] >> 2, y[k], (int32_t)x, dx, rp);
+                const bool up = hor && (by_id ? y[k] > (int32_t)x : rank_above_rec(iy[k] >> 2, y[k], (int32_t)x, dx, rp));
                 f[k] = (uint8_t)(hor | (up << 1));
                 ch += hor;
                 cu += up;
@@ -339,7 +340,7 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
         TC_TRY(tile_table_run(n, rp, L.tlo, L.thi, s));
         hipLaunchKernelGGL(k_part_vld, dim3(grid_for(n, 256)), dim3(256), 0, s, n, rp, lev, L.vld);
         hipLaunchKernelGGL(k_part_mark, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, L.vld, L.tlo,
-                           L.thi, L.flags, pb.d0, pb.up0, L.bh, L.bu);
+                           L.thi, L.flags, pb.d0, pb.up0, L.bh, L.bu, pb.by_id);
         TC_HIP_TRY(hipGetLastError());
     }
     TC_TRY(scan_exclusive_i32_to_i32(pb.d0, pb.rp0, n, L.scan, s));

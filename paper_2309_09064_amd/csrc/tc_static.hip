@@ -89,6 +89,7 @@ int tc_count_noalloc(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int
         if (rc != TC_OK) return fail(rc);
         lev = P.levels;
     }
+    P.pb.by_id = cfg.orientation == TC_ORIENT_ID ? 1 : 0;
     rc = partition_run(n, nnz, d_row_ptr, d_col_idx, lev, P.pb, P.scratch, P.scratch_bytes, s);
     if (rc != TC_OK) return fail(rc);
     cfg.sync = false;

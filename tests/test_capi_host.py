@@ -80,7 +80,8 @@ def test_bad_sizes_rejected(lib):
                                          ("wave_slots", 100), ("wave_slots", 8192), ("wg_slots", 512),
                                          ("wg_slots", 65536), ("chunk_work", -1), ("flags", 4),
                                          ("merge_max_owner", -2), ("merge_max_owner", 32), ("wg_slice_max", 100),
-                                         ("wg_slice_max", 32), ("wg_slice_max", 32768)])
+                                         ("wg_slice_max", 32), ("wg_slice_max", 32768), ("orientation", 2),
+                                         ("orientation", -1)])
 def test_bad_options_rejected(lib, field, value):
     opt = _capi.tc_options()
     setattr(opt, field, value)
@@ -256,3 +257,33 @@ def test_edge_support_needs_an_output_and_its_workspace(lib):
     assert rc == 0 and rc2 == 0 and edge >= plain + 2 * 4 * 20000
     T = lib.tc_edge_support(1000, 20000, fake, fake, None, None, fake, None, fake, plain, None)
     assert T == _capi.TC_COUNT_ERROR and lib.tc_last_error() == _capi.TC_ERR_WORKSPACE
+
+
+def test_partition_rejects_bad_orientation_before_device(lib):
+    fake = ctypes.c_void_p(0x1000)
+    e0 = ctypes.c_int64()
+    for orient in (2, -1):
+        assert lib.tc_partition(10, 20, fake, fake, fake, orient, fake, fake, fake, fake, fake, ctypes.byref(e0), fake,
+                                1 << 30, None) == _capi.TC_ERR_ARG
+
+
+@pytest.mark.parametrize("struct", ["tc_options", "tc_stats"])
+def test_struct_layout_matches_header(tmp_path, struct):
+    """The ctypes mirrors of the option and statistics structs have the C
+    layout: every field's offset and the struct's size, as gcc lays out
+    include/tc.h."""
+    cls = getattr(_capi, struct)
+    lines = [f'printf("size %zu\\n", sizeof({struct}));']
+    for name, _ in cls._fields_:
+        lines.append(f'printf("{name} %zu\\n", offsetof({struct}, {name}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tc.h"\nint main(void) {\n' +
+                   "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    assert int(out["size"]) == ctypes.sizeof(cls)
+    for name, _ in cls._fields_:
+        assert int(out[name]) == getattr(cls, name).offset, name

@@ -117,6 +117,16 @@ def test_batch_strategy_invariance(tc, force):
     assert np.array_equal(counts.cpu().numpy(), want_counts(gs))
 
 
+def test_batch_id_orientation(tc):
+    gs = small_batch(4)
+    b = tc.pack_csr([to_gpu(g) for g in gs])
+    counts, res = tc.count_batched(b, options=tc.Options(orientation=tc.TC_ORIENT_ID, validate=True))
+    want = want_counts(gs)
+    assert np.array_equal(counts.cpu().numpy(), want)
+    refs = [oracle.alg4(g) for g in gs if g.n]
+    assert (res.T0, res.T1) == (sum(r.T0 for r in refs), sum(r.T1 for r in refs))
+
+
 def test_batch_levels_match_single_graph_levels(tc):
     # given levels: each graph's own BFS levels, packed; same counts, and the
     # batch's own BFS gives the same levels count as the largest graph's

@@ -166,13 +166,14 @@ def test_bfs_levels_direction_mix(tc, first_small):
 
 # ------------------------------------------------------------------ partition
 
+@pytest.mark.parametrize("orientation", [0, 1])
 @pytest.mark.parametrize("name", ["k12", "wheel9", "union", "gnp", "kron11", "kron14", "er_dense", "chunglu14"])
-def test_partition_matches_oracle(tc, name):
+def test_partition_matches_oracle(tc, name, orientation):
     g = graph(name)
     lev, _ = oracle.bfs_levels(g)
-    ref = oracle.partition(g, lev)
+    ref = oracle.partition(g, lev, by_id=orientation == tc.TC_ORIENT_ID)
     rp, col = to_gpu(g)
-    out = tc.partition(rp, col, dev(lev))
+    out = tc.partition(rp, col, dev(lev), orientation=orientation)
     e0 = int(ref.rp0[-1]) // 2
     assert out["e0"] == e0
     assert np.array_equal(out["rp0"].cpu().numpy(), ref.rp0.astype(np.int32))
@@ -190,6 +191,15 @@ def check_count(tc, g, options=None, levels=None):
     res = tc.count(rp, col, None if levels is None else dev(levels), options)
     assert (res.T, res.T0, res.T1, res.e0) == (ref.T, ref.T0, ref.T1, ref.E0), (res, ref)
     return res
+
+
+@pytest.mark.parametrize("strategy", [-1, 0, 1, 3])
+@pytest.mark.parametrize("name", ["k12", "union", "kron11", "kron14", "er_dense", "chunglu14"])
+def test_count_id_orientation(tc, name, strategy):
+    # N0+ lists by id (the u < v of Algorithms 2 and 4): the same T, T0 and T1
+    res = check_count(tc, graph(name), tc.Options(orientation=tc.TC_ORIENT_ID, force_strategy=strategy,
+                                                   validate=True))
+    assert res.T == oracle.count_emd(graph(name))
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))

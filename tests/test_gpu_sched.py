@@ -192,15 +192,16 @@ def test_schedule_table(tc, sched, wave_slots, wg_slots, seed):
     assert clear.mean() > 0.9
 
 
-def test_profile_elements_and_items(tc):
+@pytest.mark.parametrize("orientation", [0, 1])
+def test_profile_elements_and_items(tc, orientation):
     g = kron(12, seed=4)
     lev, _ = oracle.bfs_levels(g)
-    units, elements = oracle.bucket_work(g, lev)
+    units, elements = oracle.bucket_work(g, lev, by_id=orientation == tc.TC_ORIENT_ID)
     rp, col = to_gpu(g)
     want_T = oracle.alg4(g, lev).T
     for s in range(4):
         prof = tc.new_profile()
-        r = tc.count_profile(rp, col, prof, options=tc.Options(force_strategy=s))
+        r = tc.count_profile(rp, col, prof, options=tc.Options(force_strategy=s, orientation=orientation))
         assert r.T == want_T
         p = prof.cpu().numpy()
         assert np.array_equal(p[:, :, 1].sum(axis=1), elements)

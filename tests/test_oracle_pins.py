@@ -291,20 +291,44 @@ def test_build_csr_rejects_bad_ids():
         oracle.build_csr(4, np.array([0, 4], np.int32), np.array([1, 2], np.int32))
 
 
-def test_partition_definition(kron12):
+@pytest.mark.parametrize("by_id", [False, True])
+def test_partition_definition(kron12, by_id):
     lev, _ = oracle.bfs_levels(kron12)
-    p = oracle.partition(kron12, lev)
+    p = oracle.partition(kron12, lev, by_id)
     g = kron12
     deg = g.degrees()
     for x in range(0, g.n, 7):
         nb = g.col[g.row_ptr[x]:g.row_ptr[x + 1]]
         hor = nb[lev[nb] == lev[x]]
-        above = (deg[hor] > deg[x]) | ((deg[hor] == deg[x]) & (hor > x))
+        above = (hor > x) if by_id else (deg[hor] > deg[x]) | ((deg[hor] == deg[x]) & (hor > x))
         row0 = p.c0[p.rp0[x]:p.rp0[x + 1]]
         assert np.array_equal(row0, np.concatenate([hor[above], hor[~above]]))
         assert p.up0[x] == above.sum()
         assert np.array_equal(p.c1[p.rp1[x]:p.rp1[x + 1]], nb[lev[nb] != lev[x]])
     assert p.rp0[-1] == 2 * oracle.alg4(g, lev).E0
+
+
+@pytest.mark.parametrize("by_id", [False, True])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_partition_orientations_give_forward_t0(by_id, seed):
+    """Either orientation makes every horizontal edge the upper-part member
+    of exactly one endpoint, and the forward algorithm over the upper parts
+    (a triangle x < y < w of the orientation found once, at its two lowest
+    vertices) counts the triangles whose three edges are horizontal: brute
+    force over all vertex triples, the same for both orientations."""
+    n, s, d = graphgen.kronecker(7, seed=seed)
+    g = oracle.build_csr(n, s, d)
+    lev, _ = oracle.bfs_levels(g)
+    p = oracle.partition(g, lev, by_id)
+    up = [set(p.c0[p.rp0[x]:p.rp0[x] + p.up0[x]].tolist()) for x in range(g.n)]
+    hor = {(x, y) for x in range(g.n) for y in g.col[g.row_ptr[x]:g.row_ptr[x + 1]].tolist() if lev[x] == lev[y]}
+    assert sum(len(u) for u in up) * 2 == len(hor)
+    assert all((y in up[x]) != (x in up[y]) for x, y in hor)
+    forward = sum(len(up[x] & up[y]) for x in range(g.n) for y in up[x])
+    adj = [set(g.col[g.row_ptr[x]:g.row_ptr[x + 1]].tolist()) for x in range(g.n)]
+    brute = sum(1 for x in range(g.n) for y in adj[x] if y > x for w in adj[x] & adj[y]
+                if w > y and lev[x] == lev[y] == lev[w])
+    assert forward == brute == oracle.alg4(g, lev).T0
 
 
 # ------------------------------------------------------------ per-vertex counts

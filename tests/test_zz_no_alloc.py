@@ -70,6 +70,8 @@ def test_given_levels_and_forced_strategy(tc):
     for s in (0, 1, 3):
         opts = tc.Options(force_strategy=s)
         assert noalloc(tc, g, rp, col, options=opts) == reference(tc, rp, col, options=opts)
+    opts = tc.Options(orientation=tc.TC_ORIENT_ID)
+    assert noalloc(tc, g, rp, col, options=opts) == reference(tc, rp, col)
     g2, rp2, col2 = graph(9, 6)
     assert noalloc(tc, g2, rp2, col2) == reference(tc, rp2, col2)
 
