@@ -1053,31 +1053,45 @@ __device__ __forceinline__ uint32_t stream_chunk(const Graph &g, int kind, int32
 // owner's) with the owner list.  Hits of this lane; in vertex mode every
 // common neighbour w and the partner get their triangles (the owner's are
 // added by the caller), in edge mode the three edges of every triangle.
-// Owners of at most kRegOwner elements (the heuristic's lane items) when
-// only counts are needed: the owner list sits in registers and each partner
-// list (never longer) is loaded with independent loads and compared with
-// all of it, so a partner costs a few load latencies instead of a chain of
-// dependent merge steps.
-constexpr int kRegOwner = 8;
-
-__device__ __forceinline__ uint32_t lane_reg_item(const Graph &g, int kind, int32_t x, int32_t sx, const int32_t *a,
-                                                  int32_t jb, int32_t je) {
+// When only counts are needed, owners of at most kOw elements take the
+// register form: the owner list sits in registers, and the partners are
+// taken kB at a time: their records, then all their list elements (never
+// more than the owner's), each with independent loads, then every element is
+// compared with the whole owner list.  A batch of partners thus costs two
+// load latencies, where a merge waits on every step.  The caller picks kOw
+// for the largest owner of the wavefront's items (a uniform choice).
+template <int kOw, int kB>
+__device__ __forceinline__ uint32_t lane_reg_item(const Graph &g, int kind, int32_t sx, const int32_t *a, int32_t jb,
+                                                  int32_t je) {
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
-    int32_t ao[kRegOwner];
+    int32_t ao[kOw];
 #pragma unroll
-    for (int k = 0; k < kRegOwner; ++k) ao[k] = k < sx ? a[k] : -1;
+    for (int k = 0; k < kOw; ++k) ao[k] = k < sx ? a[k] : -1;
     uint32_t hits = 0;
-    for (int32_t p = jb; p < je; ++p) {
-        int32_t sy, yb, y;
-        if (!partner_at(g, kind, p, je, sy, yb, y)) continue;   // owned: sx >= sy >= 1
-        const int32_t *b = lists + yb;
-        int32_t bv[kRegOwner];
+    for (int32_t p = jb; p < je; p += kB) {
+        int32_t sy[kB], yb[kB];
 #pragma unroll
-        for (int k = 0; k < kRegOwner; ++k) bv[k] = k < sy ? b[k] : -2;
+        for (int q = 0; q < kB; ++q) {
+            int32_t y;
+            partner_at(g, kind, p + q, je, sy[q], yb[q], y);   // sy = 0 past je or where not owned
+        }
+        // a partner's elements in rounds of at most 8 (16 loads in flight
+        // per lane keep the kernel within its registers)
+        constexpr int kC = kOw < 8 ? kOw : 8;
+#pragma unroll 1
+        for (int c = 0; c < kOw; c += kC) {
+            int32_t bv[kB][kC];
 #pragma unroll
-        for (int i = 0; i < kRegOwner; ++i)
+            for (int q = 0; q < kB; ++q)
 #pragma unroll
-            for (int j = 0; j < kRegOwner; ++j) hits += ao[i] == bv[j] ? 1u : 0u;
+                for (int k = 0; k < kC; ++k) bv[q][k] = c + k < sy[q] ? lists[yb[q] + c + k] : -2;
+#pragma unroll
+            for (int q = 0; q < kB; ++q)
+#pragma unroll
+                for (int i = 0; i < kOw; ++i)
+#pragma unroll
+                    for (int k = 0; k < kC; ++k) hits += ao[i] == bv[q][k] ? 1u : 0u;
+        }
     }
     return hits;
 }
@@ -1087,8 +1101,6 @@ __device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, in
                                                     const Sink &sk) {
     const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
     const int32_t sx = list_size(kind, g.up0, g.rp1, x);
-    if constexpr (kMode == kModePlain || kMode == kModeBatch)
-        if (sx <= kRegOwner) return lane_reg_item(g, kind, x, sx, a, jb, je);
     const int32_t *lists = kind == 0 ? g.c0 : g.c1;
     const int32_t *lpos = kind == 0 ? g.pos0 : g.pos1;   // edge mode only
     const int32_t xb = (int32_t)(a - lists);
@@ -1127,6 +1139,24 @@ __device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, in
             if (hits != h0) atomicAdd(&sk.sup[g.pos0[p]], hits - h0);
     }
     return hits;
+}
+
+// The counting modes' lane items of one wavefront (a lane without an item
+// has an empty partner range): the register form sized for the largest
+// owner among them, or the merge for owners above 16.
+template <int kMode>
+__device__ __forceinline__ uint32_t lane_count_item(const Graph &g, bool has, int kind, int32_t x, int32_t jb,
+                                                    int32_t je, const Sink &sk) {
+    const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
+    const int32_t sx = has ? list_size(kind, g.up0, g.rp1, x) : 0;
+    int32_t smax = sx;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) smax = max(smax, __shfl_xor(smax, d, kWave));
+    if (smax <= 2) return lane_reg_item<2, 4>(g, kind, sx, a, jb, je);
+    if (smax <= 4) return lane_reg_item<4, 4>(g, kind, sx, a, jb, je);
+    if (smax <= 8) return lane_reg_item<8, 2>(g, kind, sx, a, jb, je);
+    if (smax <= 16) return lane_reg_item<16, 1>(g, kind, sx, a, jb, je);
+    return has ? lane_merge_item<kMode>(g, kind, x, jb, je, sk) : 0u;
 }
 
 // Merge strategy: partners one at a time, each merged against the owner list.
@@ -1512,7 +1542,16 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
         const uint64_t t_beg = kProf ? wall_clock64() : 0;
         const int32_t it = g0 + l;
         int32_t code = 0;
-        if (it < n_all) {
+        if constexpr (kMode == kModePlain || kMode == kModeBatch) {
+            const bool has = it < n_all;
+            const Item item = has ? items[it] : Item{0, 0, 0, 0};
+            const int kind = item.code & 1;
+            code = item.code;
+            const uint32_t h = lane_count_item<kMode>(g, has, kind, item.owner, item.jb, item.je, sk);
+            if (kind == 0) acc0 += h; else acc1 += h;
+            if (kOwnerSink && h)
+                atomicAdd(kBatch ? &sk.counts[sk.gid[item.owner]] : &sk.tv[item.owner], (unsigned long long)h);
+        } else if (it < n_all) {
             const Item item = items[it];
             const int kind = item.code & 1;
             code = item.code;
