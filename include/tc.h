@@ -137,8 +137,10 @@ typedef struct tc_options {
                                  wavefront hash; 0 = wave_slots / 2          */
     int32_t merge_max_owner;  /* heuristic: owner lists up to this size (at
                                  most 31) take the lane merge (one lane per
-                                 item of at most 32 partners); 0 = default
-                                 15, -1 = never                              */
+                                 item of at most 32 partners); 0 = default:
+                                 31 for plain and batched counts with
+                                 2048-slot wavefront tables, else 15;
+                                 -1 = never                                  */
     const int32_t *sched_table; /* device int32[TC_NUM_BUCKETS], read when
                                  schedule == TC_SCHED_TABLE (NULL otherwise):
                                  bits 0-1 the bucket's strategy, bit 2 (with

@@ -71,7 +71,7 @@ class Options:
     chunk_work: int = 0
     grid_blocks: int = 0
     wave_max_owner: int = 0
-    merge_max_owner: int = 0            # 0 = default (15), -1 = never
+    merge_max_owner: int = 0            # 0 = default (31 for counts, 15 per vertex / edge), -1 = never
     sched_table: torch.Tensor | None = None   # int32[TC_NUM_BUCKETS] on the device: selects TC_SCHED_TABLE
     batch_group_entries: int = 0        # batched counts: vertices / entries per internal group; 0 = int32 limit
     wg_slice_max: int = 0               # longest owner slice of a workgroup table; 0 = wg_slots / 4

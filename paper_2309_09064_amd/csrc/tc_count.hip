@@ -53,14 +53,17 @@ constexpr int kQueueBlockInts = kQueueInts + kClaimStreams * kClaimStride;
 constexpr int kLaneMergeOb = 4;            // merge items with owner lists below 32: one lane each
 constexpr int kLanePartners = 32;          // row positions per lane item (owner classes 0-2)
 
-// Row positions per lane item of owner class ob.  A lane walks both lists
-// of each of its partners in turn, up to 2^(ob+2) steps per partner, and its
-// wavefront holds the group of 64 items until the slowest lane is done, so
-// the partner count halves per class above 2: every lane's walk stays within
-// about 512 steps.  Per-element cost profiles cannot see such a walk's
-// latency, only its share of the wavefront's time.
-__host__ __device__ constexpr int lane_partners(int ob) {
-    return ob <= 2 ? kLanePartners : kLanePartners >> (ob - 2);
+// Row positions per lane item of owner class ob.  A merging lane walks both
+// lists of each of its partners in turn, up to 2^(ob+2) steps per partner,
+// and its wavefront holds the group of 64 items until the slowest lane is
+// done, so the partner count halves per class above 2: every lane's walk
+// stays within about 512 steps.  Per-element cost profiles cannot see such
+// a walk's latency, only its share of the wavefront's time.  The register
+// and LDS forms of the counting modes (`batched`) cost a few load latencies
+// per batch of partners whatever the class, so their items all take
+// kLanePartners positions.
+__host__ __device__ constexpr int lane_partners(int ob, bool batched = false) {
+    return ob <= 2 || batched ? kLanePartners : kLanePartners >> (ob - 2);
 }
 
 struct Item {
@@ -102,6 +105,7 @@ struct SchedCfg {
     int32_t heur_wave_ob;  // heuristic: wavefront table up to this class
     int32_t heur_merge_ob; // heuristic: lane merge up to this class (-1: never)
     int32_t chunk_work;    // probe elements per wavefront item
+    int32_t lane_batched;  // lane items take the register / LDS forms (counting modes, 2048-slot wavefront tables)
 };
 
 // Strategy of a bucket.  Feasibility depends only on the owner-size class
@@ -344,7 +348,7 @@ __global__ __launch_bounds__(kItemThreads) void k_items(int32_t n, const int32_t
         if (nsl > 1) cap = (cap + nsl - 1) / nsl;
         if (nch > cap) nch = cap;
         if (s == TC_STRAT_MERGE && ((b >> 5) & 31) <= kLaneMergeOb) {   // one lane walks an item's partners
-            const int lp = lane_partners((b >> 5) & 31);
+            const int lp = lane_partners((b >> 5) & 31, sc.lane_batched != 0);
             nch = (je - jb + lp - 1) / lp;
         }
         if (nch < 1) nch = 1;
@@ -1141,12 +1145,68 @@ __device__ __forceinline__ uint32_t lane_merge_item(const Graph &g, int kind, in
     return hits;
 }
 
+// Owners of up to kLdsOwner elements when only counts are needed and the
+// wavefront's table region holds kLdsOwner ints per lane: each lane keeps
+// its owner list in LDS, element k of lane l at tab[k * 64 + l] (a
+// wavefront's reads of one step hit 64 distinct banks), padded with
+// INT32_MAX, and looks every partner element up by a branch-free binary
+// search there (five dependent LDS reads, no global ones).  Partners come
+// kB at a time and their elements eight at a time, loaded independently,
+// so a batch costs two load latencies as in the register form.
+constexpr int kLdsOwner = 32;
+template <int kB>
+__device__ __forceinline__ uint32_t lane_lds_item(const Graph &g, int kind, int32_t sx, const int32_t *a, int32_t jb,
+                                                  int32_t je, int32_t *tab) {
+    static_assert(kLdsOwner == 32, "the search below takes five halving steps");
+    const int l = lane_id();
+    const int32_t *lists = kind == 0 ? g.c0 : g.c1;
+#pragma unroll 1
+    for (int c = 0; c < kLdsOwner; c += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = c + k < sx ? a[c + k] : INT32_MAX;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tab[(c + k) * kWave + l] = v[k];
+    }
+    uint32_t hits = 0;
+    for (int32_t p = jb; p < je; p += kB) {
+        int32_t sy[kB], yb[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            int32_t y;
+            partner_at(g, kind, p + q, je, sy[q], yb[q], y);   // sy = 0 past je or where not owned
+        }
+#pragma unroll 1
+        for (int c = 0; c < kLdsOwner; c += 8) {
+            int32_t bv[kB][8];
+#pragma unroll
+            for (int q = 0; q < kB; ++q)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) bv[q][k] = c + k < sy[q] ? lists[yb[q] + c + k] : -2;
+#pragma unroll
+            for (int q = 0; q < kB; ++q) {
+                int32_t pos[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) pos[k] = 0;
+#pragma unroll
+                for (int step = 16; step > 0; step >>= 1)
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) pos[k] += tab[(pos[k] + step - 1) * kWave + l] < bv[q][k] ? step : 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) hits += tab[pos[k] * kWave + l] == bv[q][k] ? 1u : 0u;
+            }
+        }
+    }
+    return hits;
+}
+
 // The counting modes' lane items of one wavefront (a lane without an item
 // has an empty partner range): the register form sized for the largest
-// owner among them, or the merge for owners above 16.
+// owner among them, the LDS form up to kLdsOwner elements where the
+// wavefront's table region holds them, or the merge.
 template <int kMode>
 __device__ __forceinline__ uint32_t lane_count_item(const Graph &g, bool has, int kind, int32_t x, int32_t jb,
-                                                    int32_t je, const Sink &sk) {
+                                                    int32_t je, const Sink &sk, int32_t *tab, int wave_log2) {
     const int32_t *a = list_ptr(kind, g.rp0, g.c0, g.rp1, g.c1, x);
     const int32_t sx = has ? list_size(kind, g.up0, g.rp1, x) : 0;
     int32_t smax = sx;
@@ -1156,6 +1216,7 @@ __device__ __forceinline__ uint32_t lane_count_item(const Graph &g, bool has, in
     if (smax <= 4) return lane_reg_item<4, 4>(g, kind, sx, a, jb, je);
     if (smax <= 8) return lane_reg_item<8, 2>(g, kind, sx, a, jb, je);
     if (smax <= 16) return lane_reg_item<16, 1>(g, kind, sx, a, jb, je);
+    if (smax <= kLdsOwner && (kLdsOwner << 6) <= (1 << wave_log2)) return lane_lds_item<2>(g, kind, sx, a, jb, je, tab);
     return has ? lane_merge_item<kMode>(g, kind, x, jb, je, sk) : 0u;
 }
 
@@ -1547,7 +1608,7 @@ __global__ __launch_bounds__(kIsectThreads) void k_isect(Graph g, const Item *__
             const Item item = has ? items[it] : Item{0, 0, 0, 0};
             const int kind = item.code & 1;
             code = item.code;
-            const uint32_t h = lane_count_item<kMode>(g, has, kind, item.owner, item.jb, item.je, sk);
+            const uint32_t h = lane_count_item<kMode>(g, has, kind, item.owner, item.jb, item.je, sk, tab, wave_log2);
             if (kind == 0) acc0 += h; else acc1 += h;
             if (kOwnerSink && h)
                 atomicAdd(kBatch ? &sk.counts[sk.gid[item.owner]] : &sk.tv[item.owner], (unsigned long long)h);
@@ -1753,7 +1814,13 @@ static SchedCfg sched_cfg(int32_t n, int64_t nnz, const CountCfg &cfg) {
     // heuristic default: wavefront tables up to a quarter full (linear
     // probing lengthens quickly above that; the feasibility limit is half)
     sc.heur_wave_ob = cfg.wave_max_owner > 0 ? ilog2_host(cfg.wave_max_owner) : wave_log2 - 3;
-    sc.heur_merge_ob = cfg.merge_max_owner < 0 ? -1 : ilog2_host(cfg.merge_max_owner > 0 ? cfg.merge_max_owner : 15);
+    // lane items by default for owners up to 31 when only counts are needed
+    // and the wavefront tables hold the LDS form (32 ints per lane), else up
+    // to 15 (the per-vertex, per-edge and cover counts merge)
+    const bool lds_form = !cfg.tv && !cfg.sup && !cfg.cover_lev && wave_log2 >= 11;
+    sc.lane_batched = lds_form ? 1 : 0;
+    sc.heur_merge_ob =
+        cfg.merge_max_owner < 0 ? -1 : ilog2_host(cfg.merge_max_owner > 0 ? cfg.merge_max_owner : lds_form ? 31 : 15);
     if (sc.heur_merge_ob > kLaneMergeOb) sc.heur_merge_ob = kLaneMergeOb;
     sc.chunk_work = cfg.chunk_work > 0 ? cfg.chunk_work : default_chunk_work(nnz);
     return sc;

@@ -261,8 +261,13 @@ def test_schedule_table_entry_point(tc):
     # heuristic's three owner-size ranges, and a given table after feasibility
     t = tc.schedule_table(1000, 10000).cpu().numpy()
     ob = (np.arange(2048) >> 5) & 31
-    # wavefront tables (2048 slots) take owners up to a quarter of their slots
-    assert np.all(t[ob <= 3] == 3) and np.all(t[(ob > 3) & (ob <= 8)] == 0) and np.all(t[ob > 8] == 1)
+    # lane merges up to 31, wavefront tables (2048 slots) up to a quarter of
+    # their slots
+    assert np.all(t[ob <= 4] == 3) and np.all(t[(ob > 4) & (ob <= 8)] == 0) and np.all(t[ob > 8] == 1)
+    t = tc.schedule_table(1000, 10000, tc.Options(merge_max_owner=15)).cpu().numpy()
+    assert np.all(t[ob <= 3] == 3) and np.all(t[(ob > 3) & (ob <= 8)] == 0)
+    t = tc.schedule_table(1000, 10000, tc.Options(wave_slots=1024)).cpu().numpy()
+    assert np.all(t[ob <= 3] == 3) and np.all(t[ob == 4] == 0)
     t = tc.schedule_table(1000, 10000, tc.Options(force_strategy=0, wave_slots=64)).cpu().numpy()
     assert np.all(t[ob <= 4] == 0) and np.all(t[ob > 4] == 1)
     t = tc.schedule_table(1000, 10000, tc.Options(merge_max_owner=-1)).cpu().numpy()
