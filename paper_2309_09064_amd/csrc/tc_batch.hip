@@ -30,6 +30,7 @@ constexpr int kRun = 8;
 constexpr int kBfsThreads = 1024;
 constexpr int kBfsWaves = kBfsThreads / kWave;
 constexpr int kBfsRun = 8;
+constexpr int kBfsLdsVerts = 65536;   // graphs up to this size keep their visited bits in LDS (8 KB)
 constexpr int64_t kGroupMax = (int64_t(1) << 31) - 1024;   // vertices or entries of one group
 
 // Largest g in [lo, hi] with off[g] <= x.
@@ -123,10 +124,13 @@ __device__ __forceinline__ int32_t level_of(const int32_t *lev, int32_t v) {
 // its component (Algorithm 4's loop over v in id order) and a
 // level-synchronous BFS from it labels the component.  A level expands the
 // concatenated rows of its frontier, kBfsRun entries a thread, and a vertex
-// joins the next frontier through the one compare-and-swap that sets its
-// level, so every vertex is expanded once.  fa, fb and pre are scratch of
-// (vertices), (vertices) and (vertices + graphs) ints; *levels_max receives
-// the largest level count.
+// joins the next frontier through the one atomic that claims it, so every
+// vertex is expanded once.  Graphs of at most kBfsLdsVerts vertices keep a
+// visited bit per vertex in LDS: the per-entry test and the claim are LDS
+// operations, and only the claiming thread writes the level to memory;
+// larger graphs test and claim with the levels themselves.  fa, fb and pre
+// are scratch of (vertices), (vertices) and (vertices + graphs) ints;
+// *levels_max receives the largest level count.
 __global__ __launch_bounds__(kBfsThreads) void k_bfs_batch(int32_t graphs, const int32_t *__restrict__ order,
                                                             int32_t g0, int64_t v0, const int64_t *__restrict__ voff,
                                                             const int32_t *__restrict__ rp,
@@ -135,12 +139,24 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_batch(int32_t graphs, const
                                                             int32_t *levels_max) {
     __shared__ int32_t s_front, s_next, s_root;
     __shared__ int32_t s_wsum[kBfsWaves];
+    __shared__ uint32_t s_vis[kBfsLdsVerts / 32];   // visited bits of a small graph's vertices
     const int t = threadIdx.x;
     for (int32_t k = blockIdx.x; k < graphs; k += gridDim.x) {
         const int32_t gi = order[k];
         const int32_t vb = (int32_t)(voff[g0 + gi] - v0), ve = (int32_t)(voff[g0 + gi + 1] - v0);
         int32_t *P = pre + vb + gi;   // room for (ve - vb) + 1 prefix values
+        const bool in_lds = ve - vb <= kBfsLdsVerts;
         for (int32_t v = vb + t; v < ve; v += kBfsThreads) lev[v] = rp[v + 1] == rp[v] ? 0 : -1;
+        if (in_lds) {   // isolated vertices start visited, like their level 0
+            for (int32_t wd = t; wd < (ve - vb + 31) / 32; wd += kBfsThreads) {
+                uint32_t bits = 0;
+                for (int j = 0; j < 32; ++j) {
+                    const int32_t v = vb + wd * 32 + j;
+                    if (v < ve && rp[v + 1] == rp[v]) bits |= 1u << j;
+                }
+                s_vis[wd] = bits;
+            }
+        }
         __syncthreads();
         int32_t next = vb;
         int32_t deepest = 0;
@@ -167,6 +183,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_batch(int32_t graphs, const
             int32_t *F = fa + vb, *N = fb + vb;
             if (t == 0) {
                 lev[root] = 0;
+                if (in_lds) s_vis[(root - vb) >> 5] |= 1u << ((root - vb) & 31);
                 F[0] = root;
                 s_front = 1;
             }
@@ -219,13 +236,40 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_batch(int32_t graphs, const
                             w[k] = col[base + e];
                         }
                     }
+                    if (in_lds) {
+                        // the visited bit: tested, then claimed by one atomic
+                        // or (a stale clear bit only costs the atomic); ids
+                        // outside the graph, which validation rejects, are
+                        // skipped rather than indexed
+                        const uint32_t nv_g = (uint32_t)(ve - vb);
 #pragma unroll
-                    for (int k = 0; k < kBfsRun; ++k)
-                        lw[k] = w[k] >= 0 ? __hip_atomic_load(lev + w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                                          : 0;
+                        for (int k = 0; k < kBfsRun; ++k) {
+                            const uint32_t o = (uint32_t)(w[k] - vb);
+                            lw[k] = w[k] >= 0 && o < nv_g
+                                        ? (int32_t)((__hip_atomic_load(&s_vis[o >> 5], __ATOMIC_RELAXED,
+                                                                       __HIP_MEMORY_SCOPE_WORKGROUP) >> (o & 31)) & 1u)
+                                        : 1;
+                        }
 #pragma unroll
-                    for (int k = 0; k < kBfsRun; ++k)
-                        if (lw[k] < 0 && atomicCAS(&lev[w[k]], -1, level + 1) == -1) N[atomicAdd(&s_next, 1)] = w[k];
+                        for (int k = 0; k < kBfsRun; ++k)
+                            if (!lw[k]) {
+                                const uint32_t o = (uint32_t)(w[k] - vb), bit = 1u << (o & 31);
+                                if (!(atomicOr(&s_vis[o >> 5], bit) & bit)) {
+                                    lev[w[k]] = level + 1;
+                                    N[atomicAdd(&s_next, 1)] = w[k];
+                                }
+                            }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < kBfsRun; ++k)
+                            lw[k] = w[k] >= 0 ? __hip_atomic_load(lev + w[k], __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_WORKGROUP)
+                                              : 0;
+#pragma unroll
+                        for (int k = 0; k < kBfsRun; ++k)
+                            if (lw[k] < 0 && atomicCAS(&lev[w[k]], -1, level + 1) == -1)
+                                N[atomicAdd(&s_next, 1)] = w[k];
+                    }
                 }
                 __syncthreads();   // the next frontier is complete
                 if (t == 0) s_front = s_next;

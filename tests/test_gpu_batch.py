@@ -109,6 +109,25 @@ def test_batched_levels_many_components(tc):
     assert np.array_equal(counts.cpu().numpy(), want_counts(gs))
 
 
+def test_batch_levels_both_bfs_paths(tc):
+    # graphs of at most 65536 vertices keep their visited bits in LDS, larger
+    # ones claim vertices through the levels: both in one batch, at and
+    # around the size limit, with a path (one level per vertex), a star and
+    # many components
+    big = kron(17, seed=5)   # 131072 vertices
+    edge = kron(16, seed=6)  # 65536 vertices
+    path = csr_from_edges(70000, [(i, i + 1) for i in range(69999)])
+    star = csr_from_edges(65537, [(0, i) for i in range(1, 65537)])
+    gs = [big, edge, path, star, gnp(3000, 0.002, 7), complete(9)]
+    b = tc.pack_csr([to_gpu(g) for g in gs])
+    lev, nl = tc.bfs_levels_batched(b)
+    want = np.concatenate([oracle.bfs_levels(g)[0] for g in gs])
+    assert np.array_equal(lev.cpu().numpy(), want)
+    assert nl == 70000
+    counts, _ = tc.count_batched(b, options=tc.Options(validate=True))
+    assert np.array_equal(counts.cpu().numpy(), want_counts(gs))
+
+
 @pytest.mark.parametrize("force", [0, 1, 2, 3])
 def test_batch_strategy_invariance(tc, force):
     gs = small_batch(3)
