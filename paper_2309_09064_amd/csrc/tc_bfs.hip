@@ -146,17 +146,31 @@ __global__ void k_bfs_init_rest(int32_t n, const int32_t *__restrict__ comp, int
 // part[2 * blockIdx.x] and part[2 * blockIdx.x + 1] (launched on at most
 // kFlagBlocks blocks; k_front_mail adds them up).
 constexpr int kFlagBlocks = 1024;
+// The frontier also as bits, one per vertex (bits[v / 64] bit v % 64): the
+// bottom-up pass tests its neighbours there, an array of n / 8 bytes that
+// stays in L2, instead of gathering their levels.
 __global__ __launch_bounds__(kThreads) void k_level_flags(int32_t n, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ lev, int32_t level,
                                                            const int32_t *__restrict__ only,
                                                            int32_t *__restrict__ flag,
+                                                           unsigned long long *__restrict__ bits,
                                                            unsigned long long *__restrict__ part) {
     __shared__ unsigned long long s_sum[kThreads / kWave][2];
     unsigned long long c = 0, d = 0;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t deg = rp[v + 1] - rp[v];
-        const bool in = lev[v] == level && deg > 0 && (only == nullptr || only[v] >= 0);
-        flag[v] = in;
+    // a wavefront takes 64 consecutive vertices (the grid stride is a
+    // multiple of 64): one bit word per wavefront and step
+    for (int64_t vb = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); vb < n;
+         vb += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = vb + lane_id();
+        bool in = false;
+        int32_t deg = 0;
+        if (v < n) {
+            deg = rp[v + 1] - rp[v];
+            in = lev[v] == level && deg > 0 && (only == nullptr || only[v] >= 0);
+            flag[v] = in;
+        }
+        const uint64_t word = __ballot(in);
+        if (lane_id() == 0) bits[vb >> 6] = word;
         c += in ? 1ull : 0ull;
         d += in ? (unsigned long long)deg : 0ull;
     }
@@ -254,8 +268,13 @@ __global__ __launch_bounds__(kThreads) void k_bfs_expand(int32_t f, const int32_
 // next_level != level, so concurrent readers looking for `level` are unaffected.
 constexpr int32_t kBigRow = 64;
 
+__device__ __forceinline__ bool in_frontier(const unsigned long long *__restrict__ bits, int32_t y) {
+    return (bits[y >> 6] >> (y & 63)) & 1ull;
+}
+
 __global__ __launch_bounds__(kThreads) void k_bfs_bottom_up(int32_t n, const int32_t *__restrict__ rp,
                                                              const int32_t *__restrict__ col, int32_t level,
+                                                             const unsigned long long *__restrict__ bits,
                                                              int32_t *lev) {
     const int l = lane_id();
     for (int64_t vb = (int64_t)blockIdx.x * blockDim.x; vb < n; vb += (int64_t)gridDim.x * blockDim.x) {
@@ -271,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_bottom_up(int32_t n, const int
         bool found = false;
         if (todo && !big) {
             for (int32_t j = b; j < e; ++j)
-                if (lev[col[j]] == level) { found = true; break; }
+                if (in_frontier(bits, col[j])) { found = true; break; }
         }
         uint64_t bm = __ballot(big);
         while (bm) {
@@ -280,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_bottom_up(int32_t n, const int
             const int32_t sb = __shfl(b, src, kWave), se = __shfl(e, src, kWave);
             bool hit = false;
             for (int32_t j = sb; j < se && !hit; j += kWave) {
-                const bool h = j + l < se && lev[col[j + l]] == level;
+                const bool h = j + l < se && in_frontier(bits, col[j + l]);
                 hit = __ballot(h) != 0;
             }
             if (l == src) found = hit;
@@ -298,6 +317,7 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65536) {
 
 struct BfsLayout {
     int32_t *comp, *front, *flag, *pos, *fdeg, *giant;
+    unsigned long long *bits;   // the frontier, one bit per vertex
     int64_t *fpre;
     unsigned long long *part;   // per-block frontier sizes and degree sums
     void *scan;
@@ -309,6 +329,7 @@ BfsLayout carve_bfs(Carver &c, int32_t n) {
     L.comp = c.take<int32_t>(nn);
     L.front = c.take<int32_t>(nn);
     L.flag = c.take<int32_t>(nn);
+    L.bits = c.take<unsigned long long>((nn + 63) / 64);
     L.pos = c.take<int32_t>(nn + 1);
     L.fdeg = c.take<int32_t>(nn);
     L.fpre = c.take<int64_t>(nn + 1);
@@ -355,7 +376,7 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
         for (;;) {
             // frontier of `level` (vertices with an edge), compacted in id order
             hipLaunchKernelGGL(k_level_flags, dim3(gf), dim3(kThreads), 0, s, n, rp, lev, level, only, L.flag,
-                               L.part);
+                               L.bits, L.part);
             hipLaunchKernelGGL(k_front_mail, dim3(1), dim3(kThreads), 0, s, L.part, (int)gf, mb.dev);
             TC_HIP_TRY(hipGetLastError());
             TC_HIP_TRY(hipStreamSynchronize(s));
@@ -367,7 +388,7 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
             m_unexplored -= m_front;
             if (bottom_up) {
                 // large frontier: bottom-up, every unvisited vertex checks its row
-                hipLaunchKernelGGL(k_bfs_bottom_up, dim3(gb), dim3(kThreads), 0, s, n, rp, col, level, lev);
+                hipLaunchKernelGGL(k_bfs_bottom_up, dim3(gb), dim3(kThreads), 0, s, n, rp, col, level, L.bits, lev);
                 TC_HIP_TRY(hipGetLastError());
             } else {
                 // positions in the frontier list: only top-down levels need them
