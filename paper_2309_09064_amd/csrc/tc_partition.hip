@@ -35,33 +35,38 @@ __device__ __forceinline__ bool rank_above(int32_t dy, int32_t y, int32_t x, int
     return dy > dx || (dy == dx && y > x);
 }
 
-// {level, degree} of every vertex in one 4-byte record, so the marking pass
-// gathers one word per neighbour: degree << 2 | (level mod 4).  Levels of
-// adjacent vertices differ by at most one (BFS levels do; caller-given
-// levels must), so two neighbours share a level exactly when their levels
-// agree mod 4.  Degrees saturate at kDegSat; the rank test reads the exact
-// degree when both sides are that large.
-constexpr uint32_t kDegSat = (1u << 30) - 1;
+// {level, degree} of every vertex in one byte, so the marking pass gathers
+// one byte per neighbour from an array of n bytes (a quarter of the levels'
+// size, so more of it stays in L2): degree code << 2 | (level mod 4).
+// Levels of adjacent vertices differ by at most one (BFS levels do;
+// caller-given levels must), so two neighbours share a level exactly when
+// their levels agree mod 4.  The degree code is monotone: the degree itself
+// below 32, then 32 + floor(log2 d) - 5 (at most 57); when two codes differ
+// they order the degrees, when they are equal below 32 the degrees are
+// equal, and equal codes above that take the exact degree from the row
+// pointers.
+constexpr uint32_t kExactCodes = 32;
+__device__ __forceinline__ uint32_t deg_code(int32_t d) {
+    return d < (int32_t)kExactCodes ? (uint32_t)d : kExactCodes + (31u - __clz(d)) - 5u;
+}
 __global__ void k_part_vld(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ lev,
-                           uint32_t *__restrict__ vld) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t d = (uint32_t)(rp[v + 1] - rp[v]);
-        vld[v] = (d < kDegSat ? d : kDegSat) << 2 | ((uint32_t)lev[v] & 3u);
-    }
+                           uint8_t *__restrict__ vld) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        vld[v] = (uint8_t)(deg_code(rp[v + 1] - rp[v]) << 2 | ((uint32_t)lev[v] & 3u));
 }
 
-// rank_above with y's degree from its record (dyp, saturated at kDegSat)
-// and x's exact degree dx.
-__device__ __forceinline__ bool rank_above_rec(uint32_t dyp, int32_t y, int32_t x, int32_t dx,
+// rank_above with y's degree code cy from its record and x's exact degree dx.
+__device__ __forceinline__ bool rank_above_rec(uint32_t cy, int32_t y, int32_t x, int32_t dx,
                                                const int32_t *__restrict__ rp) {
-    int32_t dy = (int32_t)dyp;
-    if (dyp == kDegSat && dx >= (int32_t)kDegSat) dy = rp[y + 1] - rp[y];
-    return rank_above(dy, y, x, dx);
+    const uint32_t cx = deg_code(dx);
+    if (cy != cx) return cy > cx;
+    if (cx < kExactCodes) return y > x;   // equal degrees
+    return rank_above(rp[y + 1] - rp[y], y, x, dx);
 }
 
 __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
-                                                         const uint32_t *__restrict__ vld,
+                                                         const uint8_t *__restrict__ vld,
                                                          const int32_t *__restrict__ tlo,
                                                          const int32_t *__restrict__ thi,
                                                          uint8_t *__restrict__ flags, int32_t *__restrict__ d0,
@@ -118,7 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
 #pragma unroll
         for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? col[e0 + k] : 0;
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) iy[k] = e0 + k < e1 ? vld[y[k]] : 0u;
+        for (int k = 0; k < kRun; ++k) iy[k] = e0 + k < e1 ? (uint32_t)vld[y[k]] : 0u;
         uint8_t f[kRun];
 #pragma unroll
         for (int k = 0; k < kRun; ++k) f[k] = 0;
@@ -293,7 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
 
 struct PartLayout {
     int32_t *tlo, *thi;   // tile table of the input CSR
-    uint32_t *vld;
+    uint8_t *vld;
     uint8_t *flags;
     int32_t *bh, *bu;
     void *scan;
@@ -304,7 +309,7 @@ PartLayout carve_part(Carver &c, int32_t n, int64_t nnz) {
     const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
     L.tlo = c.take<int32_t>(tiles_of(nnz));
     L.thi = c.take<int32_t>(tiles_of(nnz));
-    L.vld = c.take<uint32_t>(n > 0 ? n : 1);
+    L.vld = c.take<uint8_t>(n > 0 ? n : 1);
     L.flags = c.take<uint8_t>(nnz > 0 ? nnz : 1);
     L.bh = c.take<int32_t>(nblk + 1);
     L.bu = c.take<int32_t>(nblk + 1);
