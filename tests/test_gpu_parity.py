@@ -193,6 +193,36 @@ def check_count(tc, g, options=None, levels=None):
     return res
 
 
+@pytest.fixture(scope="module", params=[700, 3000])
+def colliding(request):
+    """Two owners X, Y (level 1, joined by a horizontal edge, both on the
+    root) whose lists hold five ids equal modulo 2^24: the tables hash the
+    low 24 bits, so all five share both candidate buckets (four slots) of
+    any table and at least one goes on to linear probing; the other
+    neighbours also sit above 2^24.  With 700 other neighbours a forced
+    wavefront table is loaded above 1/16 (two candidates) and the workgroup
+    table below (one); with 3000 the workgroup table takes two candidates.
+    The triangles are X-Y-root and X-Y-c for the five c: 6.  The graph, its
+    device copy and the oracle's counts are made once per size."""
+    c = [7 + (k << 24) for k in range(5)]
+    n = (4 << 24) + 16
+    fill = request.param
+    filler_x = [(1 << 24) + 100 + i for i in range(fill)]
+    filler_y = [(1 << 24) + 100 + fill + i for i in range(fill)]
+    X, Y = 1, 2
+    edges = [(0, X), (0, Y), (X, Y)] + [(X, v) for v in c + filler_x] + [(Y, v) for v in c + filler_y]
+    g = csr_from_edges(n, edges)
+    return to_gpu(g), oracle.alg4(g)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(force_strategy=0), dict(force_strategy=1),
+                                  dict(force_strategy=1, wg_slice_max=256)])
+def test_count_colliding_ids(tc, colliding, opts):
+    (rp, col), ref = colliding
+    res = tc.count(rp, col, options=tc.Options(**opts))
+    assert (res.T, res.T0, res.T1, res.e0) == (ref.T, ref.T0, ref.T1, ref.E0) == (6, 0, 6, 1)
+
+
 @pytest.mark.parametrize("strategy", [-1, 0, 1, 3])
 @pytest.mark.parametrize("name", ["k12", "union", "kron11", "kron14", "er_dense", "chunglu14"])
 def test_count_id_orientation(tc, name, strategy):
