@@ -579,7 +579,7 @@ __device__ __forceinline__ uint32_t hash_probe(const HashTab &t, const int32_t (
             if constexpr (kMask) hits |= m ? (1u << u) : 0u;
             else hits += m ? 1u : 0u;
             if constexpr (kSlots)
-                slot[u] = (int32_t)(m0 | m1 ? 2 * b[u] + (m0 ? 0 : 1) : 2 * c[u] + (m2 ? 0 : 1));
+                slot[u] = (int32_t)((m0 | m1) ? 2 * b[u] + (m0 ? 0 : 1) : 2 * c[u] + (m2 ? 0 : 1));
             pend |= (!m & (q[u].y >= 0) & (r[u].y >= 0)) ? (1u << u) : 0u;
         }
     } else {

@@ -49,10 +49,23 @@ constexpr uint32_t kExactCodes = 32;
 __device__ __forceinline__ uint32_t deg_code(int32_t d) {
     return d < (int32_t)kExactCodes ? (uint32_t)d : kExactCodes + (31u - __clz(d)) - 5u;
 }
+// The level parities also go into a bitmap of n bits (bit v of word v / 64),
+// small enough to stay in every L2: the marking pass tests a neighbour's
+// parity there first and gathers its byte record only for an equal-level
+// neighbour under the degree rank, which needs its degree code.
 __global__ void k_part_vld(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ lev,
-                           uint8_t *__restrict__ vld) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        vld[v] = (uint8_t)(deg_code(rp[v + 1] - rp[v]) << 2 | ((uint32_t)lev[v] & 3u));
+                           uint8_t *__restrict__ vld, uint64_t *__restrict__ par) {
+    for (int64_t vb = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); vb < n;
+         vb += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = vb + lane_id();
+        uint32_t l = 0;
+        if (v < n) {
+            l = (uint32_t)lev[v];
+            vld[v] = (uint8_t)(deg_code(rp[v + 1] - rp[v]) << 2 | (l & 3u));
+        }
+        const uint64_t word = __ballot((l & 1u) != 0);
+        if (lane_id() == 0) par[vb >> 6] = word;
+    }
 }
 
 // rank_above with y's degree code cy from its record and x's exact degree dx.
@@ -67,6 +80,7 @@ __device__ __forceinline__ bool rank_above_rec(uint32_t cy, int32_t y, int32_t x
 __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
                                                          const uint8_t *__restrict__ vld,
+                                                         const uint64_t *__restrict__ par,
                                                          const int32_t *__restrict__ tlo,
                                                          const int32_t *__restrict__ thi,
                                                          uint8_t *__restrict__ flags, int32_t *__restrict__ d0,
@@ -115,15 +129,26 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
             }
             ch = cu = 0;
         };
-        // the run's neighbour ids, then their records, all issued before
-        // the row walk: two memory latencies per thread instead of two per
-        // entry
+        // the run's neighbour ids, their level parities, then the records
+        // of the equal-parity ones, all issued before the row walk: three
+        // memory latencies per thread instead of three per entry.  The
+        // parity of row x decides which records are needed: the run's rows
+        // all lie in [x, row of e1 - 1], and a row change only matters for
+        // entries past it, whose records are then gathered in the walk.
         int32_t y[kRun];
-        uint32_t iy[kRun];
+        uint32_t py[kRun], iy[kRun];
 #pragma unroll
         for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? col[e0 + k] : 0;
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) iy[k] = e0 + k < e1 ? (uint32_t)vld[y[k]] : 0u;
+        for (int k = 0; k < kRun; ++k)
+            py[k] = e0 + k < e1 ? (uint32_t)(par[(uint32_t)y[k] >> 6] >> (y[k] & 63)) & 1u : 2u;
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) iy[k] = 0u;
+        if (!by_id) {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k)
+                if (py[k] == (lx & 1u)) iy[k] = (uint32_t)vld[y[k]];
+        }
         uint8_t f[kRun];
 #pragma unroll
         for (int k = 0; k < kRun; ++k) f[k] = 0;
@@ -139,8 +164,19 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
                     lx = lvx(x);
                     dx = (int32_t)(xe - xb);
                 }
-                const bool hor = (iy[k] & 3u) == lx;
-                const bool up = hor && (by_id ? y[k] > (int32_t)x : rank_above_rec(iy[k] >> 2, y[k], (int32_t)x, dx, rp));
+                const bool hor = py[k] == (lx & 1u);
+                bool up = false;
+                if (hor) {
+                    if (by_id) {
+                        up = y[k] > (int32_t)x;
+                    } else {
+                        // not prefetched (the row changed parity since):
+                        // gather now; a neighbour's record is never 0, its
+                        // degree being at least one
+                        if (iy[k] == 0u) iy[k] = (uint32_t)vld[y[k]];
+                        up = rank_above_rec(iy[k] >> 2, y[k], (int32_t)x, dx, rp);
+                    }
+                }
                 f[k] = (uint8_t)(hor | (up << 1));
                 ch += hor;
                 cu += up;
@@ -299,6 +335,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
 struct PartLayout {
     int32_t *tlo, *thi;   // tile table of the input CSR
     uint8_t *vld;
+    uint64_t *par;        // level parity, one bit per vertex
     uint8_t *flags;
     int32_t *bh, *bu;
     void *scan;
@@ -310,6 +347,7 @@ PartLayout carve_part(Carver &c, int32_t n, int64_t nnz) {
     L.tlo = c.take<int32_t>(tiles_of(nnz));
     L.thi = c.take<int32_t>(tiles_of(nnz));
     L.vld = c.take<uint8_t>(n > 0 ? n : 1);
+    L.par = c.take<uint64_t>(n > 0 ? ((int64_t)n + 63) / 64 : 1);
     L.flags = c.take<uint8_t>(nnz > 0 ? nnz : 1);
     L.bh = c.take<int32_t>(nblk + 1);
     L.bu = c.take<int32_t>(nblk + 1);
@@ -343,8 +381,8 @@ int partition_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
     const int64_t nblk = (nnz + kBlockEntries - 1) / kBlockEntries;
     if (nnz > 0) {
         TC_TRY(tile_table_run(n, rp, L.tlo, L.thi, s));
-        hipLaunchKernelGGL(k_part_vld, dim3(grid_for(n, 256)), dim3(256), 0, s, n, rp, lev, L.vld);
-        hipLaunchKernelGGL(k_part_mark, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, L.vld, L.tlo,
+        hipLaunchKernelGGL(k_part_vld, dim3(grid_for(n, 256)), dim3(256), 0, s, n, rp, lev, L.vld, L.par);
+        hipLaunchKernelGGL(k_part_mark, dim3((unsigned)nblk), dim3(kThreads), 0, s, n, nnz, rp, col, L.vld, L.par, L.tlo,
                            L.thi, L.flags, pb.d0, pb.up0, L.bh, L.bu, pb.by_id);
         TC_HIP_TRY(hipGetLastError());
     }
