@@ -27,7 +27,7 @@
 namespace tc {
 namespace {
 
-constexpr int kRun = 8;                 // CSR entries per thread in row passes
+constexpr int kRun = 8;                 // CSR entries per thread in row passes (load_run8)
 constexpr int kThreads = 256;
 constexpr int kIsectThreads = 1024;     // 16 wavefronts per persistent block
 constexpr int kIsectWaves = kIsectThreads / kWave;
@@ -211,8 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
             // row walk (two memory latencies per thread, not per entry)
             int32_t y[kRun];
             int4 ry[kRun];
-#pragma unroll
-            for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? c0[e0 + k] : 0;
+            load_run8(c0, e0, e1, y);
 #pragma unroll
             for (int k = 0; k < kRun; ++k) ry[k] = e0 + k < e1 ? vrec[y[k]] : make_int4(0, 0, 0, 0);
 #pragma unroll

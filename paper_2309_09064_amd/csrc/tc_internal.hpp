@@ -133,6 +133,20 @@ __device__ __forceinline__ int64_t row_of(const P *rp, int64_t lo, int64_t hi, i
     return lo;
 }
 
+// The 8 entries [e0, e1) of a thread's run (e1 - e0 <= 8), 0 past e1: two
+// 16-byte loads when the run is whole and 16-byte aligned (a wavefront's
+// instruction then covers 1 KB instead of 256 bytes), else one load each.
+__device__ __forceinline__ void load_run8(const int32_t *__restrict__ a, int64_t e0, int64_t e1, int32_t (&y)[8]) {
+    if (e1 - e0 == 8 && ((uintptr_t)(a + e0) & 15) == 0) {
+        const int4 lo = *reinterpret_cast<const int4 *>(a + e0), hi = *reinterpret_cast<const int4 *>(a + e0 + 4);
+        y[0] = lo.x; y[1] = lo.y; y[2] = lo.z; y[3] = lo.w;
+        y[4] = hi.x; y[5] = hi.y; y[6] = hi.z; y[7] = hi.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) y[k] = e0 + k < e1 ? a[e0 + k] : 0;
+    }
+}
+
 // Rows spanned by the tile of CSR entries [t0, t1) (t0 < t1 <= rp[nrows]):
 // one thread searches, the block shares the range through `sh` (2 entries).
 // Ends with a barrier.  Threads then search only inside [lo, hi].

@@ -27,6 +27,7 @@ constexpr int kThreads = 256;
 constexpr int kRun = 8;
 constexpr int kBlockEntries = kThreads * kRun;
 static_assert(kBlockEntries == kTileEntries, "a block is one tile of the tile table");
+static_assert(kRun == 8, "runs are loaded by load_run8");
 constexpr int kWaves = kThreads / kWave;
 constexpr int kTileRowsMax = 1024;   // rows a tile may span and still count in LDS
 
@@ -137,8 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_part_mark(int32_t n, int64_t nnz, 
         // entries past it, whose records are then gathered in the walk.
         int32_t y[kRun];
         uint32_t py[kRun], iy[kRun];
-#pragma unroll
-        for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? col[e0 + k] : 0;
+        load_run8(col, e0, e1, y);
 #pragma unroll
         for (int k = 0; k < kRun; ++k)
             py[k] = e0 + k < e1 ? (uint32_t)(par[(uint32_t)y[k] >> 6] >> (y[k] & 63)) & 1u : 2u;
@@ -298,8 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
     int64_t H = (int64_t)bh_off[blockIdx.x] + (before >> 32);
     int64_t U = (int64_t)bu_off[blockIdx.x] + (before & 0xffffffffll);
     int32_t y[kRun];   // issued before the row walk
-#pragma unroll
-    for (int k = 0; k < kRun; ++k) y[k] = e0 + k < e1 ? col[e0 + k] : 0;
+    load_run8(col, e0, e1, y);
     auto rpx = [&](int64_t r) -> int64_t { return local ? (int64_t)s_rp[r - r_lo] : (int64_t)rp[r]; };
     // N0+ entries of row x go to rp0[x] + (U - rpu[x]), the rest of its
     // horizontal entries to H - U + rpu[x + 1]: two per-row terms
