@@ -239,7 +239,10 @@ __global__ void k_part_rp1(int32_t n, const int32_t *__restrict__ rp, const int3
 }
 
 // kPos also records, for every c0 / c1 entry, the input entry it came from
-// (per-edge counts add to input entries).
+// (per-edge counts add to input entries).  The block's N1 entries fill one
+// run of c1 (entry e goes to e - H(e)): they are gathered in LDS and leave
+// in consecutive stores instead of one 4-byte store per entry spread over
+// the wavefront's 2 KB of input.
 template <bool kPos>
 __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ col,
@@ -254,6 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
                                                             int32_t *__restrict__ pos0, int32_t *__restrict__ pos1) {
     __shared__ int64_t wsum[kWaves];
     __shared__ int32_t s_rp[kTileRowsMax + 1], s_ub[kTileRowsMax], s_lb[kTileRowsMax];
+    __shared__ int32_t s_c1[kBlockEntries], s_p1[kPos ? kBlockEntries : 1];
     const int64_t t0 = (int64_t)blockIdx.x * kBlockEntries;
     // the tile's row pointers and per-row targets staged in LDS (made
     // visible by the scan's barrier below): the walk across row boundaries
@@ -293,41 +297,55 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(int32_t n, int64_t nn
     if (lane_id() == kWave - 1) wsum[w] = inc;
     __syncthreads();
     int64_t before = inc - packed;
-    for (int i = 0; i < w; ++i) before += wsum[i];
-    if (e0 >= e1) return;
-    int64_t H = (int64_t)bh_off[blockIdx.x] + (before >> 32);
-    int64_t U = (int64_t)bu_off[blockIdx.x] + (before & 0xffffffffll);
-    int32_t y[kRun];   // issued before the row walk
-    load_run8(col, e0, e1, y);
-    auto rpx = [&](int64_t r) -> int64_t { return local ? (int64_t)s_rp[r - r_lo] : (int64_t)rp[r]; };
-    // N0+ entries of row x go to rp0[x] + (U - rpu[x]), the rest of its
-    // horizontal entries to H - U + rpu[x + 1]: two per-row terms
-    auto upb = [&](int64_t r) -> int64_t { return local ? (int64_t)s_ub[r - r_lo] : (int64_t)rp0[r] - rpu[r]; };
-    auto lob = [&](int64_t r) -> int64_t { return local ? (int64_t)s_lb[r - r_lo] : (int64_t)rpu[r + 1]; };
-    int64_t x = local ? r_lo + row_of(s_rp, 0, nr - 1, e0) : row_of(rp, r_lo, r_hi, e0);
-    int64_t xe = rpx(x + 1);
-    int64_t up_base = upb(x), lo_base = lob(x);
+    int64_t blk = 0;   // the block's horizontal entries
+    for (int i = 0; i < kWaves; ++i) {
+        if (i < w) before += wsum[i];
+        blk += wsum[i] >> 32;
+    }
+    const int64_t hb = bh_off[blockIdx.x];   // horizontal entries before the block
+    const int64_t nblk = (t0 + kBlockEntries < nnz ? t0 + kBlockEntries : nnz) - t0;
+    if (e0 < e1) {
+        int64_t H = hb + (before >> 32);
+        int64_t U = (int64_t)bu_off[blockIdx.x] + (before & 0xffffffffll);
+        int32_t y[kRun];   // issued before the row walk
+        load_run8(col, e0, e1, y);
+        auto rpx = [&](int64_t r) -> int64_t { return local ? (int64_t)s_rp[r - r_lo] : (int64_t)rp[r]; };
+        // N0+ entries of row x go to rp0[x] + (U - rpu[x]), the rest of its
+        // horizontal entries to H - U + rpu[x + 1]: two per-row terms
+        auto upb = [&](int64_t r) -> int64_t { return local ? (int64_t)s_ub[r - r_lo] : (int64_t)rp0[r] - rpu[r]; };
+        auto lob = [&](int64_t r) -> int64_t { return local ? (int64_t)s_lb[r - r_lo] : (int64_t)rpu[r + 1]; };
+        int64_t x = local ? r_lo + row_of(s_rp, 0, nr - 1, e0) : row_of(rp, r_lo, r_hi, e0);
+        int64_t xe = rpx(x + 1);
+        int64_t up_base = upb(x), lo_base = lob(x);
 #pragma unroll
-    for (int k = 0; k < kRun; ++k) {
-        const int64_t e = e0 + k;
-        if (e < e1) {
-            if (e >= xe) {
-                do { ++x; xe = rpx(x + 1); } while (e >= xe);
-                up_base = upb(x);
-                lo_base = lob(x);
+        for (int k = 0; k < kRun; ++k) {
+            const int64_t e = e0 + k;
+            if (e < e1) {
+                if (e >= xe) {
+                    do { ++x; xe = rpx(x + 1); } while (e >= xe);
+                    up_base = upb(x);
+                    lo_base = lob(x);
+                }
+                const uint8_t fe = f[k];
+                if (fe & 1) {
+                    const int64_t d = (fe & 2) ? up_base + U : H - U + lo_base;
+                    c0[d] = y[k];
+                    if (kPos) pos0[d] = (int32_t)e;
+                } else {
+                    const int64_t i = (e - t0) - (H - hb);   // place in the block's run of c1
+                    s_c1[i] = y[k];
+                    if (kPos) s_p1[i] = (int32_t)e;
+                }
+                H += fe & 1;
+                U += fe >> 1;
             }
-            const uint8_t fe = f[k];
-            if (fe & 1) {
-                const int64_t d = (fe & 2) ? up_base + U : H - U + lo_base;
-                c0[d] = y[k];
-                if (kPos) pos0[d] = (int32_t)e;
-            } else {
-                c1[e - H] = y[k];
-                if (kPos) pos1[e - H] = (int32_t)e;
-            }
-            H += fe & 1;
-            U += fe >> 1;
         }
+    }
+    __syncthreads();
+    const int64_t n1 = nblk - blk, d1 = t0 - hb;   // the run: c1[d1, d1 + n1)
+    for (int64_t i = threadIdx.x; i < n1; i += kThreads) {
+        c1[d1 + i] = s_c1[i];
+        if (kPos) pos1[d1 + i] = s_p1[i];
     }
 }
 
