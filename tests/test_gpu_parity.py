@@ -183,6 +183,30 @@ def test_partition_matches_oracle(tc, name, orientation):
     assert np.array_equal(out["c1"].cpu().numpy()[:len(ref.c1)], ref.c1)
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_partition_and_count_unaligned_col(tc, shift):
+    """A column array 4, 8 or 12 bytes past a 16-byte boundary: the row
+    passes read each thread's run entry by entry instead of by 16-byte
+    loads, with the same partition and counts."""
+    g = graph("kron14")
+    lev, _ = oracle.bfs_levels(g)
+    ref = oracle.partition(g, lev)
+    rp, col = to_gpu(g)
+    buf = torch.zeros(col.numel() + 4, dtype=torch.int32, device=col.device)
+    view = buf[shift:shift + col.numel()]
+    view.copy_(col)
+    assert view.data_ptr() % 16 == 4 * shift
+    out = tc.partition(rp, view, dev(lev))
+    e0 = int(ref.rp0[-1]) // 2
+    assert out["e0"] == e0
+    assert np.array_equal(out["rp0"].cpu().numpy(), ref.rp0.astype(np.int32))
+    assert np.array_equal(out["c0"].cpu().numpy()[:2 * e0], ref.c0)
+    assert np.array_equal(out["c1"].cpu().numpy()[:len(ref.c1)], ref.c1)
+    res = tc.count(rp, view)
+    r4 = oracle.alg4(g)
+    assert (res.T, res.T0, res.T1, res.e0) == (r4.T, r4.T0, r4.T1, r4.E0)
+
+
 # ------------------------------------------------------------------ count
 
 def check_count(tc, g, options=None, levels=None):
