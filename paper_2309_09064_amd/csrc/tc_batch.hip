@@ -131,7 +131,9 @@ __device__ __forceinline__ int32_t level_of(const int32_t *lev, int32_t v) {
 // larger graphs test and claim with the levels themselves.  fa, fb and pre
 // are scratch of (vertices), (vertices) and (vertices + graphs) ints;
 // *levels_max receives the largest level count.
-__global__ __launch_bounds__(kBfsThreads) void k_bfs_batch(int32_t graphs, const int32_t *__restrict__ order,
+// Held to 64 vector registers (eight wavefronts per SIMD), so that two
+// graphs' workgroups share a CU.
+__global__ __launch_bounds__(kBfsThreads, 8) void k_bfs_batch(int32_t graphs, const int32_t *__restrict__ order,
                                                             int32_t g0, int64_t v0, const int64_t *__restrict__ voff,
                                                             const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ col, int32_t *lev,
