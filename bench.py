@@ -352,6 +352,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the Chung-Lu, scale-20 and batch legs")
     ap.add_argument("--main-only", action="store_true",
                     help="time only the headline leg, so that a profile of the run holds its kernels alone")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the 4096-graph batch leg and print its record (for a profile of the batch)")
     ap.add_argument("--train-schedule", metavar="PATH",
                     help="measure the training graphs, train the schedule network, write it to PATH and exit")
     ap.add_argument("--train-steps", type=int, default=3000)
@@ -372,6 +374,9 @@ def main():
     stream_gbs = copy_probe(torch)
     if args.train_schedule:
         train_schedule(tc, torch, args.train_schedule, args.train_steps)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch4096": batch_leg(tc, torch, args)}))
         return
     n, rp, col = make_graph(tc, torch, "kronecker", args.scale, args.seed)
     nnz = col.numel()

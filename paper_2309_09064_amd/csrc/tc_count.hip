@@ -185,9 +185,11 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
             }
         __syncthreads();
         const int64_t e0 = t0 + (int64_t)threadIdx.x * kRun;
-        int2 r0[kRun], r1[kRun];   // the run's records, kind 0 and 1
-#pragma unroll
-        for (int k = 0; k < kRun; ++k) r0[k] = r1[k] = make_int2(0, 0);
+        // the run's partner records and which of them the row's vertex owns
+        // (bit k per kind): the stores below select from them, so that no
+        // second copy of the records stays live through the row walk
+        int4 ry[kRun];
+        uint32_t own0 = 0, own1 = 0;
         if (e0 < e0x2) {
             const int64_t e1 = e0 + kRun < e0x2 ? e0 + kRun : e0x2;
             int64_t x = row_of(rp0, r_lo, r_hi, e0);
@@ -210,7 +212,6 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
             // the run's partners and their list sizes, issued before the
             // row walk (two memory latencies per thread, not per entry)
             int32_t y[kRun];
-            int4 ry[kRun];
             load_run8(c0, e0, e1, y);
 #pragma unroll
             for (int k = 0; k < kRun; ++k) ry[k] = e0 + k < e1 ? vrec[y[k]] : make_int4(0, 0, 0, 0);
@@ -229,10 +230,13 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
                 const bool o1 = owns(s1x, ry[k].w, (int32_t)x, y[k]);
                 if (o0) { ++n0; w0 += (unsigned)ry[k].y; }
                 if (o1) { ++n1; w1 += (unsigned)ry[k].w; }
-                r0[k] = o0 ? make_int2(ry[k].x, ry[k].y) : make_int2(0, 0);
-                r1[k] = o1 ? make_int2(ry[k].z, ry[k].w) : make_int2(0, 0);
+                own0 |= (uint32_t)o0 << k;
+                own1 |= (uint32_t)o1 << k;
             }
             flush();
+        } else {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) ry[k] = make_int4(0, 0, 0, 0);
         }
         // the records leave through LDS, half a wavefront's span at a time,
         // so that every store instruction writes 1 KB of consecutive entries
@@ -243,13 +247,21 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
             const int64_t wb = t0 + (int64_t)w * (2 * kHalf);   // first entry of the wavefront's span
             if (wb < e0x2) {                                   // uniform in the wavefront
                 const bool full = wb + 2 * kHalf <= e0x2;
-                auto put = [&](const int2 (&r)[kRun], int2 *dst) {
+                // kind 0 stores {rp0, |N0+|} of the owned partners, kind 1
+                // {rp1, |N1|}; {0, 0} elsewhere
+                auto rec = [&](int kind, int k) -> int2 {
+                    const bool o = (((kind ? own1 : own0) >> k) & 1u) != 0;
+                    return o ? (kind ? make_int2(ry[k].z, ry[k].w) : make_int2(ry[k].x, ry[k].y)) : make_int2(0, 0);
+                };
+                auto put = [&](int kind, int2 *dst) {
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         if ((l >> 5) == h) {
 #pragma unroll
-                            for (int k = 0; k < kRun; k += 2)
-                                stg[w][(l & 31) * (kRun / 2) + k / 2] = make_int4(r[k].x, r[k].y, r[k + 1].x, r[k + 1].y);
+                            for (int k = 0; k < kRun; k += 2) {
+                                const int2 a = rec(kind, k), b = rec(kind, k + 1);
+                                stg[w][(l & 31) * (kRun / 2) + k / 2] = make_int4(a.x, a.y, b.x, b.y);
+                            }
                         }
                         wave_lds_sync();
 #pragma unroll
@@ -267,8 +279,8 @@ __global__ __launch_bounds__(kThreads) void k_own(int32_t n, const int64_t *__re
                         wave_lds_sync();   // the region is rewritten next
                     }
                 };
-                put(r0, prec0 + wb);
-                put(r1, prec1 + wb);
+                put(0, prec0 + wb);
+                put(1, prec1 + wb);
             }
         }
         __syncthreads();
