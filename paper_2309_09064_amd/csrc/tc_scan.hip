@@ -29,16 +29,70 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *total) {
     return before + inc - v;
 }
 
+// A thread's kPer consecutive elements [base, base + kPer), 0 past n: by
+// 16-byte loads when the run is whole and 16-byte aligned (a wavefront's
+// instruction then covers 1 KB instead of 256 or 512 bytes), else one load
+// each.  In-place scans read a thread's elements before it stores them, and
+// no other thread touches them.
+template <class T>
+__device__ __forceinline__ void load_per(const T *p, int64_t base, int64_t n, int64_t (&v)[kPer]) {
+    static_assert(kPer == 8 && (sizeof(T) == 4 || sizeof(T) == 8), "runs of 8 four- or eight-byte elements");
+    if (base + kPer <= n && ((uintptr_t)(p + base) & 15) == 0) {
+        const int4 *q = reinterpret_cast<const int4 *>(p + base);
+        if (sizeof(T) == 4) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int4 a = q[j];
+                v[4 * j] = (int64_t)(T)a.x; v[4 * j + 1] = (int64_t)(T)a.y;
+                v[4 * j + 2] = (int64_t)(T)a.z; v[4 * j + 3] = (int64_t)(T)a.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int4 a = q[j];
+                v[2 * j] = (int64_t)(T)(((uint64_t)(uint32_t)a.y << 32) | (uint32_t)a.x);
+                v[2 * j + 1] = (int64_t)(T)(((uint64_t)(uint32_t)a.w << 32) | (uint32_t)a.z);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) v[i] = base + i < n ? (int64_t)p[base + i] : 0;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void store_per(T *p, int64_t base, int64_t n, const int64_t (&r)[kPer]) {
+    if (base + kPer <= n && ((uintptr_t)(p + base) & 15) == 0) {
+        int4 *q = reinterpret_cast<int4 *>(p + base);
+        if (sizeof(T) == 4) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                q[j] = make_int4((int32_t)(T)r[4 * j], (int32_t)(T)r[4 * j + 1], (int32_t)(T)r[4 * j + 2],
+                                 (int32_t)(T)r[4 * j + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint64_t a = (uint64_t)(T)r[2 * j], b = (uint64_t)(T)r[2 * j + 1];
+                q[j] = make_int4((int32_t)(uint32_t)a, (int32_t)(uint32_t)(a >> 32), (int32_t)(uint32_t)b,
+                                 (int32_t)(uint32_t)(b >> 32));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i)
+            if (base + i < n) p[base + i] = (T)r[i];
+    }
+}
+
 template <class Tin>
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const Tin *__restrict__ in, int64_t n,
                                                            int64_t *__restrict__ sums) {
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kPer;
+    int64_t v[kPer];
+    load_per(in, base, n, v);
     int64_t acc = 0;
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        int64_t idx = base + i;
-        if (idx < n) acc += (int64_t)in[idx];
-    }
+    for (int i = 0; i < kPer; ++i) acc += v[i];
     int64_t tot;
     (void)block_excl_scan(acc, &tot);
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
@@ -49,23 +103,21 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const Tin *in, int64_t 
                                                           Tout *out) {
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kPer;
     int64_t v[kPer];
+    load_per(in, base, n, v);
     int64_t acc = 0;
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        int64_t idx = base + i;
-        v[i] = (idx < n) ? (int64_t)in[idx] : 0;
-        acc += v[i];
-    }
+    for (int i = 0; i < kPer; ++i) acc += v[i];
     int64_t tot;
     int64_t run = block_excl_scan(acc, &tot);
     const int64_t off = offs ? offs[blockIdx.x] : 0;
     run += off;
+    int64_t r[kPer];
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-        int64_t idx = base + i;
-        if (idx < n) out[idx] = (Tout)run;
+        r[i] = run;
         run += v[i];
     }
+    store_per(out, base, n, r);
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = (Tout)(off + tot);
 }
 
