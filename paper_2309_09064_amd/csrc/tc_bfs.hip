@@ -140,8 +140,10 @@ __global__ void k_bfs_init_rest(int32_t n, const int32_t *__restrict__ comp, int
         if (comp[v] == (int32_t)v) lev[v] = 0;
 }
 
-// Frontier of `level`: flag[v] = 1 for vertices on that level with an edge
-// (in the second pass, only those of the pass: comp[v] >= 0).  Each block
+// Frontier of `level`: the vertices on that level with an edge (in the
+// second pass, only those of the pass: comp[v] >= 0), as bits (below) and,
+// per 64-bit word of them, their number wcnt[v / 64] (a top-down level
+// compacts the frontier from a prefix sum of n / 64 word counts).  Each block
 // also writes the number and the degree sum of its frontier vertices to
 // part[2 * blockIdx.x] and part[2 * blockIdx.x + 1] (launched on at most
 // kFlagBlocks blocks; k_front_mail adds them up).
@@ -152,7 +154,7 @@ constexpr int kFlagBlocks = 1024;
 __global__ __launch_bounds__(kThreads) void k_level_flags(int32_t n, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ lev, int32_t level,
                                                            const int32_t *__restrict__ only,
-                                                           int32_t *__restrict__ flag,
+                                                           int32_t *__restrict__ wcnt,
                                                            unsigned long long *__restrict__ bits,
                                                            unsigned long long *__restrict__ part) {
     __shared__ unsigned long long s_sum[kThreads / kWave][2];
@@ -167,10 +169,12 @@ __global__ __launch_bounds__(kThreads) void k_level_flags(int32_t n, const int32
         if (v < n) {
             deg = rp[v + 1] - rp[v];
             in = lev[v] == level && deg > 0 && (only == nullptr || only[v] >= 0);
-            flag[v] = in;
         }
         const uint64_t word = __ballot(in);
-        if (lane_id() == 0) bits[vb >> 6] = word;
+        if (lane_id() == 0) {
+            bits[vb >> 6] = word;
+            wcnt[vb >> 6] = __popcll(word);
+        }
         c += in ? 1ull : 0ull;
         d += in ? (unsigned long long)deg : 0ull;
     }
@@ -218,10 +222,15 @@ __global__ __launch_bounds__(kThreads) void k_front_mail(const unsigned long lon
     }
 }
 
-__global__ void k_compact(int32_t n, const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
+// The frontier list in id order: vertex v of the bits goes to the prefix of
+// the word counts before its word plus the set bits below it in the word.
+__global__ void k_compact(int32_t n, const unsigned long long *__restrict__ bits, const int32_t *__restrict__ wpos,
                           int32_t *__restrict__ front) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        if (flag[v]) front[pos[v]] = (int32_t)v;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long word = bits[v >> 6];
+        const int b = (int)(v & 63);
+        if ((word >> b) & 1ull) front[wpos[v >> 6] + __popcll(word & ((1ull << b) - 1ull))] = (int32_t)v;
+    }
 }
 
 __global__ void k_front_deg(int32_t f, const int32_t *__restrict__ front, const int32_t *__restrict__ rp,
@@ -316,7 +325,7 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65536) {
 }
 
 struct BfsLayout {
-    int32_t *comp, *front, *flag, *pos, *fdeg, *giant;
+    int32_t *comp, *front, *wcnt, *wpos, *fdeg, *giant;   // wcnt, wpos: per 64-bit word of bits
     unsigned long long *bits;   // the frontier, one bit per vertex
     int64_t *fpre;
     unsigned long long *part;   // per-block frontier sizes and degree sums
@@ -328,9 +337,9 @@ BfsLayout carve_bfs(Carver &c, int32_t n) {
     const int64_t nn = n > 0 ? n : 1;
     L.comp = c.take<int32_t>(nn);
     L.front = c.take<int32_t>(nn);
-    L.flag = c.take<int32_t>(nn);
+    L.wcnt = c.take<int32_t>((nn + 63) / 64);
     L.bits = c.take<unsigned long long>((nn + 63) / 64);
-    L.pos = c.take<int32_t>(nn + 1);
+    L.wpos = c.take<int32_t>((nn + 63) / 64 + 1);
     L.fdeg = c.take<int32_t>(nn);
     L.fpre = c.take<int64_t>(nn + 1);
     L.giant = c.take<int32_t>(64);
@@ -375,7 +384,7 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
         int32_t level = 0;
         for (;;) {
             // frontier of `level` (vertices with an edge), compacted in id order
-            hipLaunchKernelGGL(k_level_flags, dim3(gf), dim3(kThreads), 0, s, n, rp, lev, level, only, L.flag,
+            hipLaunchKernelGGL(k_level_flags, dim3(gf), dim3(kThreads), 0, s, n, rp, lev, level, only, L.wcnt,
                                L.bits, L.part);
             hipLaunchKernelGGL(k_front_mail, dim3(1), dim3(kThreads), 0, s, L.part, (int)gf, mb.dev);
             TC_HIP_TRY(hipGetLastError());
@@ -392,8 +401,8 @@ int bfs_run(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, int32
                 TC_HIP_TRY(hipGetLastError());
             } else {
                 // positions in the frontier list: only top-down levels need them
-                TC_TRY(scan_exclusive_i32_to_i32(L.flag, L.pos, n, L.scan, s));
-                hipLaunchKernelGGL(k_compact, dim3(gv), dim3(kThreads), 0, s, n, L.flag, L.pos, L.front);
+                TC_TRY(scan_exclusive_i32_to_i32(L.wcnt, L.wpos, ((int64_t)n + 63) / 64, L.scan, s));
+                hipLaunchKernelGGL(k_compact, dim3(gv), dim3(kThreads), 0, s, n, L.bits, L.wpos, L.front);
                 hipLaunchKernelGGL(k_front_deg, dim3(grid_for(f, kThreads)), dim3(kThreads), 0, s, f, L.front, rp,
                                    L.fdeg);
                 TC_HIP_TRY(hipGetLastError());
